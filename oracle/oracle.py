@@ -1,0 +1,288 @@
+"""FP64 CPU oracle for the P-SPIR PSF system matrix -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The library never does: it shares no
+code with the oracle, and the oracle shares none with it.
+
+The heavy lifting is plain C in ``psf_oracle.c`` / ``psf_oracle3d.c`` (FP64,
+no FMA contraction), loaded through ctypes.  What is done here in numpy is the
+plain linear algebra on top of the dense matrix columns the C code returns:
+projections ``y = A x`` and ``x = A^T y``, the sensitivity ``A^T 1``, the
+thresholded CSR, and the list-mode OSEM update.
+
+Paper: Sun et al., Chinese Physics C (2016), arXiv 1607.06170.  Sections,
+equations and tables are cited next to each function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "_psf_oracle.so")
+SOURCES = [os.path.join(HERE, "psf_oracle.c"), os.path.join(HERE, "psf_oracle3d.c")]
+
+# flag bits (see psf_oracle.c)
+F_MIRROR_TIE = 1
+F_ROW_TIE = 2
+F_OVERLAP_TIE = 4
+F_REMAP_TIE = 8
+F_RANGE = 16
+F_GEOM = 32
+F_TIES = F_MIRROR_TIE | F_ROW_TIE | F_OVERLAP_TIE | F_REMAP_TIE
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle's C sources into a shared object next to them."""
+    srcs = [s for s in SOURCES if os.path.exists(s)]
+    if not force and os.path.exists(SO_PATH):
+        so_m = os.path.getmtime(SO_PATH)
+        if all(os.path.getmtime(s) <= so_m for s in srcs):
+            return SO_PATH
+    tmp = SO_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SO_PATH)
+    return SO_PATH
+
+
+class Geom(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("n_ct", C.c_int32), ("n_cz", C.c_int32), ("n_brings", C.c_int32),
+                ("pitch_t", C.c_double), ("pitch_z", C.c_double), ("depth", C.c_double),
+                ("r_face", C.c_double), ("gap_z", C.c_double), ("mu", C.c_double), ("phi0", C.c_double)]
+
+
+class Image(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double)]
+
+
+class Table(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_sub", C.c_int32), ("step_deg", C.c_double),
+                ("data", C.POINTER(C.c_double))]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(SO_PATH)
+            G, I, T = C.POINTER(Geom), C.POINTER(Image), C.POINTER(Table)
+            L.og_rho_point.restype = C.c_double
+            L.og_rho_point.argtypes = [C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double]
+            L.og_rho_sub.restype = C.c_double
+            L.og_rho_sub.argtypes = [C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double]
+            L.og_table_2d.restype = None
+            L.og_table_2d.argtypes = [G, C.c_int, C.c_int, C.c_double, _dp]
+            L.og_sigma.restype = C.c_double
+            L.og_sigma.argtypes = [G]
+            L.og_ap1.restype = C.c_double
+            L.og_ap1.argtypes = [G, C.c_double, C.c_double]
+            L.og_uv_row_2d.restype = C.c_int
+            L.og_uv_row_2d.argtypes = [G, T, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _i32p]
+            L.og_samples_2d.restype = C.c_int
+            L.og_samples_2d.argtypes = [G, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64, _i32p, _i32p, _dp,
+                                        C.POINTER(C.c_int64)]
+            L.og_column_2d.restype = C.c_int
+            L.og_column_2d.argtypes = [G, T, C.c_double, C.c_double, C.c_int, _dp]
+            L.og_columns_2d.restype = None
+            L.og_columns_2d.argtypes = [G, T, I, _i64p, C.c_int64, C.c_int, _dp, _i32p, C.c_int]
+            L.og_table_grad_2d.restype = None
+            L.og_table_grad_2d.argtypes = [G, T, I, _dp, _dp, C.c_int, _dp, C.c_int]
+            L.og_gauss_legendre.restype = None
+            L.og_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
+            if hasattr(L, "og_table_3d"):
+                _bind3d(L, G, I, T)
+            _lib = L
+    return _lib
+
+
+def _bind3d(L, G, I, T):
+    pass
+
+
+# ---------------------------------------------------------------------------
+# Python-side views of the C structures
+# ---------------------------------------------------------------------------
+
+def geom(cfg: dict) -> Geom:
+    return Geom(int(cfg["n_blocks"]), int(cfg["n_ct"]), int(cfg.get("n_cz", 1)), int(cfg.get("n_brings", 1)),
+                float(cfg["pitch_t"]), float(cfg.get("pitch_z", cfg["pitch_t"])), float(cfg["depth"]),
+                float(cfg["r_face"]), float(cfg.get("gap_z", 0.0)), float(cfg["mu"]), float(cfg.get("phi0", 0.0)))
+
+
+def image(cfg: dict) -> Image:
+    return Image(int(cfg["nx"]), int(cfg["ny"]), int(cfg.get("nz", 1)), 0, float(cfg["dx"]), float(cfg["dy"]),
+                 float(cfg.get("dz", 1.0)), float(cfg.get("cx", 0.0)), float(cfg.get("cy", 0.0)),
+                 float(cfg.get("cz", 0.0)))
+
+
+class TableRef:
+    """Keeps the numpy array alive next to the C view of it."""
+
+    def __init__(self, data: np.ndarray, n_rows: int, n_sub: int, step_deg: float):
+        self.data = np.ascontiguousarray(data, dtype=np.float64)
+        self.n_rows, self.n_sub, self.step_deg = n_rows, n_sub, step_deg
+        self.c = Table(n_rows, n_sub, step_deg, self.data.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def n_crystals_ring(cfg: dict) -> int:
+    return int(cfg["n_blocks"]) * int(cfg["n_ct"])
+
+
+def n_bins_2d(cfg: dict) -> int:
+    n = n_crystals_ring(cfg)
+    return n * (n - 1) // 2
+
+
+def voxel_centre(cfg: dict, j: int) -> np.ndarray:
+    nx, ny = int(cfg["nx"]), int(cfg["ny"])
+    ix, iy, iz = j % nx, (j // nx) % ny, j // (nx * ny)
+    nz = int(cfg.get("nz", 1))
+    return np.array([(ix - 0.5 * (nx - 1)) * cfg["dx"] + cfg.get("cx", 0.0),
+                     (iy - 0.5 * (ny - 1)) * cfg["dy"] + cfg.get("cy", 0.0),
+                     (iz - 0.5 * (nz - 1)) * cfg.get("dz", 1.0) + cfg.get("cz", 0.0)])
+
+
+# ---------------------------------------------------------------------------
+# Response table (Sec 2.1.1, Eq.1, 6, 7)
+# ---------------------------------------------------------------------------
+
+def table_2d(cfg: dict, n_rows: int = 61, n_sub: int = 4, step_deg: float = 1.0) -> TableRef:
+    """Analytic absolute response table rho[row][p][a+2] (FP64)."""
+    out = np.zeros(n_rows * n_sub * 5)
+    lib().og_table_2d(C.byref(geom(cfg)), n_rows, n_sub, step_deg, out)
+    return TableRef(out.reshape(n_rows, n_sub, 5), n_rows, n_sub, step_deg)
+
+
+def rho_point(alpha: float, u: float, a: int, lam: float, depth: float, mu: float) -> float:
+    return lib().og_rho_point(alpha, u, a, lam, depth, mu)
+
+
+def rho_sub(alpha: float, p: int, n_sub: int, a: int, lam: float, depth: float, mu: float) -> float:
+    return lib().og_rho_sub(alpha, p, n_sub, a, lam, depth, mu)
+
+
+def sigma(cfg: dict) -> float:
+    return lib().og_sigma(C.byref(geom(cfg)))
+
+
+def ap1(cfg: dict, alpha: float, nu: float) -> float:
+    """Eq.4, the equivalent incidence position in the next block."""
+    return lib().og_ap1(C.byref(geom(cfg)), alpha, nu)
+
+
+def uv_row_2d(cfg: dict, tab: TableRef, v: np.ndarray, g: int, p: int):
+    val = np.zeros(5)
+    src = np.zeros(5, dtype=np.int32)
+    fl = lib().og_uv_row_2d(C.byref(geom(cfg)), C.byref(tab.c), float(v[0]), float(v[1]), int(g), int(p), val, src)
+    return val, src, fl
+
+
+# ---------------------------------------------------------------------------
+# Homogenization samples and matrix columns (Sec 2.3, Eq.10-12)
+# ---------------------------------------------------------------------------
+
+def samples_2d(cfg: dict, n_sub: int, v: np.ndarray, homog_k: int = 0):
+    """(s1, s2, w) for every homogenized line through v, s1 < s2; plus flags."""
+    maxs = 1 << 16 if homog_k == 0 else homog_k + 16
+    s1 = np.zeros(maxs, np.int32)
+    s2 = np.zeros(maxs, np.int32)
+    w = np.zeros(maxs)
+    n = C.c_int64(0)
+    fl = lib().og_samples_2d(C.byref(geom(cfg)), n_sub, float(v[0]), float(v[1]), homog_k, maxs, s1, s2, w,
+                             C.byref(n))
+    n = n.value
+    assert n <= maxs
+    return s1[:n].copy(), s2[:n].copy(), w[:n].copy(), fl
+
+
+def columns_2d(cfg: dict, tab: TableRef, vox, homog_k: int = 0, nthreads: int = 0):
+    """Dense FP64 columns A[:, v] for the voxels in ``vox``: array [len(vox), n_bins], flags."""
+    vox = np.ascontiguousarray(np.asarray(vox, dtype=np.int64))
+    nb = n_bins_2d(cfg)
+    out = np.zeros((len(vox), nb))
+    flags = np.zeros(len(vox), np.int32)
+    lib().og_columns_2d(C.byref(geom(cfg)), C.byref(tab.c), C.byref(image(cfg)), vox, len(vox), homog_k,
+                        out.reshape(-1), flags, nthreads)
+    return out, flags
+
+
+def table_grad_2d(cfg: dict, tab: TableRef, x: np.ndarray, gy: np.ndarray, homog_k: int = 0, nthreads: int = 0):
+    """d <gy, A x> / d table, for one image x (all voxels) and bin weights gy."""
+    grad = np.zeros(tab.data.size)
+    lib().og_table_grad_2d(C.byref(geom(cfg)), C.byref(tab.c), C.byref(image(cfg)),
+                           np.ascontiguousarray(x, dtype=np.float64).reshape(-1),
+                           np.ascontiguousarray(gy, dtype=np.float64).reshape(-1), homog_k, grad, nthreads)
+    return grad.reshape(tab.data.shape)
+
+
+# ---------------------------------------------------------------------------
+# Plain linear algebra on the dense matrix (rows = bins, columns = voxels)
+# ---------------------------------------------------------------------------
+
+def csr_from_columns(cols: np.ndarray, threshold: float):
+    """CSR of A^T (rows = voxels, columns = bins ascending) keeping A >= threshold
+    (and A > 0).  Returns row_ptr (int64), col (int32), val (float64)."""
+    keep = (cols > 0) & (cols >= threshold)
+    counts = keep.sum(axis=1)
+    row_ptr = np.zeros(cols.shape[0] + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    r, c = np.nonzero(keep)
+    return row_ptr, c.astype(np.int32), cols[r, c]
+
+
+def project_fwd(cols: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y[B, bins] = A x for x[B, voxels]; cols[voxels, bins] holds A^T."""
+    return np.atleast_2d(x) @ cols
+
+
+def project_adj(cols: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """x[B, voxels] = A^T y for y[B, bins]."""
+    return np.atleast_2d(y) @ cols.T
+
+
+def sensitivity(cols: np.ndarray) -> np.ndarray:
+    """s = A^T 1."""
+    return cols.sum(axis=1)
+
+
+def listmode_fwd(cols: np.ndarray, ev_bins: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """q_e = a_e^T x for every event, a_e the matrix row of the event's bin."""
+    return cols[:, ev_bins].T @ x
+
+
+def listmode_adj(cols: np.ndarray, ev_bins: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """sum_e h_e a_e."""
+    return cols[:, ev_bins] @ h
+
+
+def lm_osem_update(cols: np.ndarray, ev_bins: np.ndarray, x: np.ndarray, sens: np.ndarray, n_subsets: int,
+                   randoms: float) -> np.ndarray:
+    """One list-mode OSEM subset update: x <- x / (s/M) * sum_e a_e / (a_e^T x + r)."""
+    q = listmode_fwd(cols, ev_bins, x) + randoms
+    back = listmode_adj(cols, ev_bins, 1.0 / q)
+    out = np.zeros_like(x)
+    nz = sens > 0
+    out[nz] = x[nz] / (sens[nz] / n_subsets) * back[nz]
+    return out
+
+
+def pair_bin(i, j, n):
+    i, j = np.minimum(i, j), np.maximum(i, j)
+    return i * n - i * (i + 1) // 2 + (j - i - 1)
