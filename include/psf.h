@@ -1,0 +1,189 @@
+/*
+ * psf.h -- C ABI of the P-SPIR PSF system-matrix library for AMD MI355X (gfx950).
+ *
+ * Method: Sun et al., "Fast and accurate generation method of PSF-based system
+ * matrix for PET reconstruction", Chinese Physics C (2016), arXiv 1607.06170.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: PSF_OK (0) on success, a negative PSF_E* code otherwise.
+ *     No exception ever crosses this interface.
+ *   - Pointers named *_dev, and the data fields of psf_table / psf_csr, are
+ *     device (HBM) pointers; everything else is host memory.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream)
+ *     and runs asynchronously unless the description says the call blocks.
+ *   - The caller owns every buffer passed in.  The library never frees caller
+ *     memory; its own device state lives in the handle (geometry constants)
+ *     and in the caller-provided workspace (sized by psf_workspace_size).
+ *   - Outputs are overwritten unless psf_opts.accumulate is 1.
+ *
+ * Geometry (paper Sec 2.1.2 symbols in brackets): n_blocks flat blocks [R]
+ * per ring; block b has outward normal at angle phi0 + 2 pi b / R and its front
+ * face at distance radius_face from the axis; along the face, n_cryst_t
+ * crystals of width pitch_t [lambda]; crystal depth `depth`; attenuation `mu`.
+ * Global transaxial crystal index g = b * n_cryst_t + c increases
+ * counter-clockwise.  3D scanners stack n_block_rings rings of blocks of
+ * n_cryst_z crystals axially (pitch_z), with crystal id = ring * N_c + g.
+ *
+ * Image: voxel (ix, iy, iz) has centre ((ix - (nx-1)/2) dx + cx, ...), linear
+ * index (iz * ny + iy) * nx + ix.
+ *
+ * Bins: a bin is an unordered crystal pair (i < j), numbered
+ *   bin(i, j) = i * N - i (i + 1) / 2 + (j - i - 1),   N crystals in total.
+ */
+#ifndef PSF_H
+#define PSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PSF_OK = 0,
+    PSF_EINVAL = -1,       /* a NULL pointer, a negative size or a bad option */
+    PSF_EGEOM = -2,        /* inconsistent geometry (e.g. a voxel outside the ring) */
+    PSF_ERANGE = -3,       /* an incidence angle beyond the table's last row, or table shape mismatch */
+    PSF_ESIZE = -4,        /* a buffer is too small; the required size is written back */
+    PSF_EHIP = -5,         /* a HIP runtime error (see psf_last_hip_error) */
+    PSF_EOVERFLOW = -6,    /* fill phase produced more entries than the count phase allotted */
+    PSF_EUNSUPPORTED = -7  /* geometry or option combination this build does not handle */
+};
+
+/* precision of the tile contraction T = U^T W V (paper Sec 2.2-2.3, Eq.10, 12) */
+enum {
+    PSF_FP32 = 0,   /* FP32 products, FP64 bin accumulation */
+    PSF_BF16 = 1,   /* X = W V in FP32; U and X rounded to BF16 for T = U^T X, FP32 accumulation */
+    PSF_BF16X2 = 2  /* as PSF_BF16 with a hi/lo BF16 split of U and X (three products) */
+};
+
+typedef struct {
+    int32_t n_blocks;       /* R: blocks per ring (Eq.2) */
+    int32_t n_cryst_t;      /* crystals per block along the face (transaxial) */
+    int32_t n_cryst_z;      /* crystals per block axially (1 for a 2D ring) */
+    int32_t n_block_rings;  /* block rings along z (1 for a 2D ring) */
+    double pitch_t;         /* lambda: crystal width transaxially, mm (Eq.5) */
+    double pitch_z;         /* crystal width axially, mm */
+    double depth;           /* crystal length, mm */
+    double radius_face;     /* axis-to-front-face distance, mm */
+    double gap_z;           /* axial gap between block rings, mm (must be 0) */
+    double mu;              /* linear attenuation, 1/mm (table builder only) */
+    double phi0;            /* angle of block 0's outward normal, rad */
+} psf_geometry;
+
+typedef struct {
+    int32_t nx, ny, nz, pad;
+    double dx, dy, dz;      /* voxel size, mm */
+    double cx, cy, cz;      /* image centre, mm */
+} psf_image;
+
+/* Response table (paper Sec 2.1.1, Eq.1, 6-7): absolute first-interaction
+ * probability for a photon entering sub-position p of a crystal at incidence
+ * angle row * step_deg, tilted towards larger crystal offsets; entry a+2 is
+ * the crystal at offset a in -2..2.
+ *   2D: data[n_rows][n_sub][5]
+ *   3D: data[n_rows][n_rows][n_sub][n_sub][5][5]  (transaxial angle row,
+ *       axial angle row, transaxial sub-position, axial sub-position,
+ *       transaxial offset, axial offset) */
+typedef struct {
+    int32_t n_rows;
+    int32_t n_sub;
+    double step_deg;
+    const float* data;      /* device */
+} psf_table;
+
+typedef struct {
+    int32_t precision;      /* PSF_FP32 / PSF_BF16 / PSF_BF16X2 */
+    int32_t homog_k;        /* 0: homogenization in the k -> infinity limit; k > 0: Eq.11 with k lines */
+    double threshold;       /* build_psf_sysmat keeps entries with A >= threshold (and A > 0) */
+    int64_t vox_begin;      /* voxel range of build_psf_sysmat: [vox_begin, vox_end) */
+    int64_t vox_end;        /* vox_end <= 0 means all voxels */
+    int32_t accumulate;     /* 1: add into the output instead of overwriting */
+    int32_t pad;
+} psf_opts;
+
+/* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
+typedef struct {
+    int64_t n_rows;         /* out: vox_end - vox_begin */
+    int64_t nnz;            /* out (phase 1), in (phase 2): capacity of col/val */
+    int64_t* row_ptr;       /* device [n_rows + 1] */
+    int32_t* col;           /* device [nnz]; NULL selects phase 1 */
+    float* val;             /* device [nnz] */
+} psf_csr;
+
+typedef struct psf_handle psf_handle;
+
+/* Validate the geometry and image and upload geometry constants to the
+ * current device.  mode3d = 0: a single 2D ring (n_cryst_z = n_block_rings = 1,
+ * nz = 1, lines in the transaxial plane); mode3d = 1: the 3D scanner.
+ * PSF_EGEOM if any voxel centre lies outside the ring of face lines. */
+int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, psf_handle** out);
+void psf_destroy(psf_handle* h);
+
+/* Number of crystals N and of bins N (N - 1) / 2; number of voxels. */
+int psf_sizes(const psf_handle* h, int64_t* n_crystals, int64_t* n_bins, int64_t* n_voxels);
+
+/* Analytic response table (stands in for the paper's GATE simulation, Sec
+ * 2.1.1 Eq.1, normalised as Eq.6-7): first-interaction probability with
+ * attenuation `mu` in a laterally unbounded crystal array, averaged over each
+ * sub-position; computed in FP64 on the device, stored as FP32 into
+ * table_dev (layout of psf_table, 2D or 3D by the handle's mode). */
+int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, float* table_dev,
+                    void* stream);
+
+/* Device workspace in bytes needed by the calls below for these options,
+ * batch size and number of events. */
+int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
+                       int64_t n_events, size_t* bytes);
+
+/* System matrix, voxel by voxel (paper Sec 2.3): for each voxel of
+ * [vox_begin, vox_end), every homogenized line through its centre (Eq.11)
+ * spreads, through the response rows of its two end crystals (Eq.2-7), into
+ * the crystal-pair bins with probability w U[a] V[b] (Eq.10, summed as Eq.12).
+ * Two phases on the same options:
+ *   phase 1 (csr->col == NULL): writes row_ptr and sets csr->nnz; BLOCKS.
+ *   phase 2: fills col/val (capacity csr->nnz); BLOCKS; PSF_EOVERFLOW if a
+ *   row would exceed what phase 1 allotted. */
+int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
+                     size_t workspace_bytes, psf_csr* csr, void* stream);
+
+/* Forward projection y = A x on the fly, without storing A (paper Table 2's
+ * projector).  x_dev: [batch][n_voxels]; y_dev: [batch][n_bins] when
+ * events_dev is NULL, else [batch][n_events] with events_dev an int32
+ * [n_events][2] list of crystal pairs (list-mode rows). */
+int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x_dev, int32_t batch,
+                const int32_t* events_dev, int64_t n_events, float* y_dev, void* workspace_dev,
+                size_t workspace_bytes, void* stream);
+
+/* Back projection x = A^T y (layouts as project_fwd).  If grad_table_dev is
+ * not NULL, also accumulates d <y, A xt> / d table into it (FP32, table
+ * layout, summed over the batch) with xt = xt_dev [batch][n_voxels]. */
+int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y_dev, int32_t batch,
+                const int32_t* events_dev, int64_t n_events, float* x_dev, const float* xt_dev,
+                float* grad_table_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Sensitivity s = A^T 1 over all bins, FP32 [n_voxels] (summed in FP64). */
+int psf_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts, float* s_dev,
+                    void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* One list-mode OSEM subset update (the list-mode use the paper names as
+ * its next step, Sec 4):
+ *   x_out = x_in / (s / n_subsets) * sum_e a_e / (a_e^T x_in + randoms)
+ * over the n_events crystal pairs of events_dev; voxels with s = 0 get 0. */
+int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* opts, const int32_t* events_dev,
+                       int64_t n_events, float randoms, const float* sens_dev, int32_t n_subsets,
+                       const float* x_in_dev, float* x_out_dev, void* workspace_dev, size_t workspace_bytes,
+                       void* stream);
+
+/* Wait for `stream` and report the status word the kernels keep in the
+ * workspace (PSF_ERANGE if an incidence angle fell beyond the table). */
+int psf_check(psf_handle* h, void* workspace_dev, void* stream);
+
+const char* psf_status_string(int status);
+int psf_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSF_H */

@@ -1,0 +1,379 @@
+// C ABI of the library (declared in include/psf.h): argument checks, handle,
+// workspace carving and kernel launches.  No exception crosses this boundary.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.hpp"
+
+using namespace psf;
+
+struct psf_handle {
+    psf_geometry g;
+    psf_image im;
+    int mode3d;
+    int device;
+    int64_t n_crystals, n_bins, n_vox;
+    double sigma;
+    double* frames_dev;  // [R][2] cos, sin of each block's outward normal
+};
+
+static thread_local int g_last_hip = 0;
+
+#define HIP_TRY(expr)                         \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) {               \
+            g_last_hip = (int)e_;             \
+            return PSF_EHIP;                  \
+        }                                     \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int check_geometry(const psf_geometry* g, const psf_image* im, int mode3d) {
+    if (g->n_blocks < 3 || g->n_cryst_t < 1 || g->n_cryst_z < 1 || g->n_block_rings < 1) return PSF_EINVAL;
+    if (!(g->pitch_t > 0) || !(g->pitch_z > 0) || !(g->depth > 0) || !(g->radius_face > 0) || !(g->mu > 0))
+        return PSF_EINVAL;
+    if (g->gap_z != 0.0) return PSF_EUNSUPPORTED;
+    if (im->nx < 1 || im->ny < 1 || im->nz < 1 || !(im->dx > 0) || !(im->dy > 0) || !(im->dz > 0)) return PSF_EINVAL;
+    if (mode3d == 0 && (g->n_cryst_z != 1 || g->n_block_rings != 1 || im->nz != 1)) return PSF_EINVAL;
+    // blocks must not overlap on the polygon of face lines
+    const double half_w = 0.5 * g->n_cryst_t * g->pitch_t;
+    if (g->radius_face * tan(M_PI / g->n_blocks) - half_w < 0.0) return PSF_EGEOM;
+    // every voxel centre strictly inside every face line (corners suffice: convex)
+    for (int b = 0; b < g->n_blocks; ++b) {
+        const double phi = g->phi0 + 2.0 * M_PI * b / g->n_blocks;
+        const double c = cos(phi), s = sin(phi);
+        for (int cxs = 0; cxs < 2; ++cxs)
+            for (int cys = 0; cys < 2; ++cys) {
+                const double x = (cxs ? 0.5 : -0.5) * (im->nx - 1) * im->dx + im->cx;
+                const double y = (cys ? 0.5 : -0.5) * (im->ny - 1) * im->dy + im->cy;
+                if (!(c * x + s * y < g->radius_face)) return PSF_EGEOM;
+            }
+    }
+    return PSF_OK;
+}
+
+extern "C" {
+
+int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, psf_handle** out) {
+    if (!geom || !img || !out) return PSF_EINVAL;
+    *out = nullptr;
+    if (mode3d != 0 && mode3d != 1) return PSF_EINVAL;
+    const int st = check_geometry(geom, img, mode3d);
+    if (st != PSF_OK) return st;
+    psf_handle* h = new (std::nothrow) psf_handle();
+    if (!h) return PSF_EINVAL;
+    h->g = *geom;
+    h->im = *img;
+    h->mode3d = mode3d;
+    const int64_t Nc = (int64_t)geom->n_blocks * geom->n_cryst_t;
+    const int64_t rings = (int64_t)geom->n_cryst_z * geom->n_block_rings;
+    h->n_crystals = mode3d ? Nc * rings : Nc;
+    h->n_bins = h->n_crystals * (h->n_crystals - 1) / 2;
+    h->n_vox = (int64_t)img->nx * img->ny * img->nz;
+    h->sigma = geom->radius_face * tan(M_PI / geom->n_blocks) - 0.5 * geom->n_cryst_t * geom->pitch_t;
+    double* fr = (double*)malloc(sizeof(double) * 2 * geom->n_blocks);
+    for (int b = 0; b < geom->n_blocks; ++b) {
+        const double phi = geom->phi0 + 2.0 * M_PI * b / geom->n_blocks;
+        fr[2 * b] = cos(phi);
+        fr[2 * b + 1] = sin(phi);
+    }
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->frames_dev, sizeof(double) * 2 * geom->n_blocks);
+    if (e == hipSuccess) e = hipMemcpy(h->frames_dev, fr, sizeof(double) * 2 * geom->n_blocks, hipMemcpyHostToDevice);
+    free(fr);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        if (h->frames_dev) (void)hipFree(h->frames_dev);
+        delete h;
+        return PSF_EHIP;
+    }
+    *out = h;
+    return PSF_OK;
+}
+
+void psf_destroy(psf_handle* h) {
+    if (!h) return;
+    if (h->frames_dev) (void)hipFree(h->frames_dev);
+    delete h;
+}
+
+int psf_sizes(const psf_handle* h, int64_t* n_crystals, int64_t* n_bins, int64_t* n_voxels) {
+    if (!h) return PSF_EINVAL;
+    if (n_crystals) *n_crystals = h->n_crystals;
+    if (n_bins) *n_bins = h->n_bins;
+    if (n_voxels) *n_voxels = h->n_vox;
+    return PSF_OK;
+}
+
+const char* psf_status_string(int s) {
+    switch (s) {
+        case PSF_OK: return "ok";
+        case PSF_EINVAL: return "invalid argument";
+        case PSF_EGEOM: return "inconsistent geometry";
+        case PSF_ERANGE: return "incidence angle beyond the response table";
+        case PSF_ESIZE: return "buffer too small";
+        case PSF_EHIP: return "HIP runtime error";
+        case PSF_EOVERFLOW: return "fill phase exceeded the counted row sizes";
+        case PSF_EUNSUPPORTED: return "unsupported geometry or options";
+        default: return "unknown status";
+    }
+}
+
+int psf_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static int64_t table_elems(const psf_handle* h, const psf_table* t) {
+    if (h->mode3d) return (int64_t)t->n_rows * t->n_rows * t->n_sub * t->n_sub * kNb * kNb;
+    return (int64_t)t->n_rows * t->n_sub * kNb;
+}
+
+static int check_table(const psf_handle* h, const psf_table* t) {
+    if (!t || !t->data) return PSF_EINVAL;
+    if (t->n_rows < 1 || t->n_sub < 1 || !(t->step_deg > 0)) return PSF_EINVAL;
+    return PSF_OK;
+}
+
+static Ring2D make_ring2d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
+    Ring2D G;
+    G.R = h->g.n_blocks;
+    G.nc = h->g.n_cryst_t;
+    G.P = t->n_sub;
+    G.Nc = G.R * G.nc;
+    G.nseg = G.Nc * G.P;
+    G.n_rows = t->n_rows;
+    G.nx = h->im.nx;
+    G.ny = h->im.ny;
+    G.nbins = h->n_bins;
+    G.nvox = h->n_vox;
+    G.lam = h->g.pitch_t;
+    G.half_w = 0.5 * h->g.n_cryst_t * h->g.pitch_t;
+    G.rf = h->g.radius_face;
+    G.sigma = h->sigma;
+    G.step_deg = t->step_deg;
+    G.two_pi_R = 2.0 * M_PI / h->g.n_blocks;
+    G.dx = h->im.dx;
+    G.dy = h->im.dy;
+    G.cx = h->im.cx;
+    G.cy = h->im.cy;
+    G.frames = h->frames_dev;
+    G.table = t->data;
+    G.precision = o ? o->precision : PSF_FP32;
+    return G;
+}
+
+static int check_2d_support(const psf_handle* h, const Ring2D& G, int mode) {
+    int dev = 0, maxsm = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSF_EHIP;
+    if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PSF_EHIP;
+    if (voxel2d_smem_bytes(G, mode) > (size_t)maxsm) return PSF_EUNSUPPORTED;
+    return PSF_OK;
+}
+
+static int check_opts(const psf_opts* o) {
+    if (!o) return PSF_EINVAL;
+    if (o->precision < PSF_FP32 || o->precision > PSF_BF16X2) return PSF_EINVAL;
+    if (o->homog_k < 0) return PSF_EINVAL;
+    if (o->homog_k > 0) return PSF_EUNSUPPORTED;  // finite-k sampling is an oracle test mode
+    return PSF_OK;
+}
+
+// status word: zero at the start of a call, read back by psf_check
+__global__ void k_zero_header(int* p) {
+    if (threadIdx.x < kWsHeader / sizeof(int)) p[threadIdx.x] = 0;
+}
+
+static int zero_header(void* ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, (int*)ws);
+    HIP_TRY(hipGetLastError());
+    return PSF_OK;
+}
+
+static int read_status(void* ws, hipStream_t st) {
+    int s = 0;
+    HIP_TRY(hipMemcpyAsync(&s, ws, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (s & kStatOverflow) return PSF_EOVERFLOW;
+    if (s & kStatRange) return PSF_ERANGE;
+    if (s & kStatGeom) return PSF_EGEOM;
+    return PSF_OK;
+}
+
+// workspace: header | FP64 bin accumulator [batch][n_bins] | FP64 table gradient
+static size_t ws_need(const psf_handle* h, const psf_table* t, int batch) {
+    size_t b = kWsHeader;
+    b += align256(sizeof(double) * (size_t)(batch > 0 ? batch : 1) * (size_t)h->n_bins);
+    b += align256(sizeof(double) * (size_t)table_elems(h, t));
+    return b;
+}
+
+extern "C" {
+
+int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
+                       int64_t n_events, size_t* bytes) {
+    (void)opts;
+    (void)n_events;
+    if (!h || !table || !bytes || batch < 0) return PSF_EINVAL;
+    *bytes = ws_need(h, table, batch);
+    return PSF_OK;
+}
+
+int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, float* table_dev, void* stream) {
+    if (!h || !table_dev || n_rows < 1 || n_sub < 1 || !(step_deg > 0)) return PSF_EINVAL;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    HIP_TRY(launch_table_2d(h->g, n_rows, n_sub, step_deg, table_dev, (hipStream_t)stream));
+    return PSF_OK;
+}
+
+int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* ws, size_t ws_bytes,
+                     psf_csr* csr, void* stream) {
+    if (!h || !csr || !ws) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (ws_bytes < kWsHeader) return PSF_ESIZE;
+    const int64_t vb = opts->vox_begin, ve = opts->vox_end > 0 ? opts->vox_end : h->n_vox;
+    if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
+    if (!csr->row_ptr) return PSF_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    Ring2D G = make_ring2d(h, table, opts);
+    VoxArgs2D a;
+    memset(&a, 0, sizeof(a));
+    a.vox_begin = vb;
+    a.n_vox_range = ve - vb;
+    a.batch = 1;
+    a.threshold = opts->threshold;
+    a.row_ptr = csr->row_ptr;
+    a.col = csr->col;
+    a.val = csr->val;
+    a.status = (int*)ws;
+    csr->n_rows = ve - vb;
+    const int mode = csr->col ? kModeFill : kModeCount;
+    if ((st = check_2d_support(h, G, mode))) return st;
+    if ((st = zero_header(ws, s))) return st;
+    if (!csr->col) {
+        HIP_TRY(launch_voxel2d(kModeCount, G, a, s));
+        HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));
+        int64_t nnz = 0;
+        HIP_TRY(hipMemcpyAsync(&nnz, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        st = read_status(ws, s);  // synchronises
+        csr->nnz = nnz;
+        return st;
+    }
+    if (!csr->val) return PSF_EINVAL;
+    int64_t need = 0;
+    HIP_TRY(hipMemcpyAsync(&need, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (csr->nnz < need) {
+        csr->nnz = need;
+        return PSF_ESIZE;
+    }
+    HIP_TRY(launch_voxel2d(kModeFill, G, a, s));
+    return read_status(ws, s);
+}
+
+int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int32_t batch,
+                const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !x || !y || !ws || batch < 1) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d || events) return PSF_EUNSUPPORTED;
+    (void)n_events;
+    if (ws_bytes < ws_need(h, table, batch)) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    Ring2D G = make_ring2d(h, table, opts);
+    if ((st = check_2d_support(h, G, kModeFwd))) return st;
+    double* y64 = (double*)((char*)ws + kWsHeader);
+    VoxArgs2D a;
+    memset(&a, 0, sizeof(a));
+    a.vox_begin = 0;
+    a.n_vox_range = h->n_vox;
+    a.batch = batch;
+    a.x = x;
+    a.y64 = y64;
+    a.status = (int*)ws;
+    if ((st = zero_header(ws, s))) return st;
+    HIP_TRY(launch_zero_f64(y64, (int64_t)batch * h->n_bins, s));
+    HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
+    HIP_TRY(launch_finalize(y64, y, (int64_t)batch * h->n_bins, opts->accumulate, s));
+    return PSF_OK;
+}
+
+static int adj_common(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int ones,
+                      int32_t batch, float* x, const float* xt, float* grad, void* ws, size_t ws_bytes,
+                      hipStream_t s) {
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (ws_bytes < ws_need(h, table, batch)) return PSF_ESIZE;
+    Ring2D G = make_ring2d(h, table, opts);
+    const int mode = grad ? kModeAdjGrad : kModeAdj;
+    if ((st = check_2d_support(h, G, mode))) return st;
+    double* g64 = (double*)((char*)ws + kWsHeader + align256(sizeof(double) * (size_t)batch * h->n_bins));
+    if ((st = zero_header(ws, s))) return st;
+    const int64_t tsize = table_elems(h, table);
+    if (grad) HIP_TRY(launch_zero_f64(g64, tsize, s));
+    // the table-gradient kernel keeps up to 8 images' voxel values in registers
+    const int chunk = grad ? 8 : batch;
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+        VoxArgs2D a;
+        memset(&a, 0, sizeof(a));
+        a.vox_begin = 0;
+        a.n_vox_range = h->n_vox;
+        a.batch = nb;
+        a.y = ones ? nullptr : y + (int64_t)b0 * h->n_bins;
+        a.ones = ones;
+        a.xout = x + (int64_t)b0 * h->n_vox;
+        a.x = xt ? xt + (int64_t)b0 * h->n_vox : nullptr;
+        a.grad64 = g64;
+        a.status = (int*)ws;
+        a.accumulate = opts->accumulate;
+        HIP_TRY(launch_voxel2d(mode, G, a, s));
+    }
+    if (grad) HIP_TRY(launch_finalize(g64, grad, tsize, 1, s));
+    return PSF_OK;
+}
+
+int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int32_t batch,
+                const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
+                size_t ws_bytes, void* stream) {
+    if (!h || !y || !x || !ws || batch < 1) return PSF_EINVAL;
+    if (grad && !xt) return PSF_EINVAL;
+    if (events) return PSF_EUNSUPPORTED;
+    (void)n_events;
+    return adj_common(h, table, opts, y, 0, batch, x, xt, grad, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int psf_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts, float* s_dev, void* ws,
+                    size_t ws_bytes, void* stream) {
+    if (!h || !s_dev || !ws) return PSF_EINVAL;
+    return adj_common(h, table, opts, nullptr, 1, 1, s_dev, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* opts, const int32_t* events,
+                       int64_t n_events, float randoms, const float* sens, int32_t n_subsets, const float* x_in,
+                       float* x_out, void* ws, size_t ws_bytes, void* stream) {
+    (void)h; (void)table; (void)opts; (void)events; (void)n_events; (void)randoms; (void)sens;
+    (void)n_subsets; (void)x_in; (void)x_out; (void)ws; (void)ws_bytes; (void)stream;
+    return PSF_EUNSUPPORTED;
+}
+
+int psf_check(psf_handle* h, void* ws, void* stream) {
+    if (!h || !ws) return PSF_EINVAL;
+    return read_status(ws, (hipStream_t)stream);
+}
+
+}  // extern "C"

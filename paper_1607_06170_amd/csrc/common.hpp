@@ -1,0 +1,75 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psf.h"
+
+namespace psf {
+
+constexpr double kPi = 3.14159265358979323846;
+// Direction overlaps at or below this many radians are empty: a set of lines
+// of zero measure (it guards exact antipodal coincidences against rounding).
+constexpr double kEpsOverlap = 1e-12;
+constexpr int kNb = 5;  // neighbour crystals per axis: offsets -2..2
+
+// status bits kept in the first word of the workspace
+constexpr int kStatRange = 1;     // an incidence angle beyond the last table row was used
+constexpr int kStatOverflow = 2;  // fill phase wanted more entries than allotted
+constexpr int kStatGeom = 4;
+
+// Workspace header: status word, nnz total, padding to 256 bytes.
+constexpr size_t kWsHeader = 256;
+
+// Everything a 2D-ring kernel needs, passed by value.
+struct Ring2D {
+    int R, nc, P, Nc, nseg, n_rows, nx, ny;
+    int64_t nbins, nvox;
+    double lam, half_w, rf, sigma, step_deg, two_pi_R;
+    double dx, dy, cx, cy;
+    const double* frames;  // [R][2]: cos, sin of the block's outward normal
+    const float* table;    // [n_rows][P][5]
+    int precision;
+};
+
+// Device view of the handle (host struct defined in api.cpp).
+struct HandleView {
+    psf_geometry g;
+    psf_image im;
+    int mode3d;
+    int64_t n_crystals, n_bins, n_vox;
+    double sigma;
+    const double* frames;
+};
+
+// Per-call arguments of the voxel-stationary 2D kernels.
+struct VoxArgs2D {
+    int64_t vox_begin, n_vox_range;
+    int batch;
+    double threshold;
+    const float* x;       // [batch][nvox]       fwd input / table-gradient image
+    const float* y;       // [batch][nbins]      adj input
+    double* y64;          // [batch][nbins]      fwd FP64 accumulator
+    float* xout;          // [batch][nvox]       adj output
+    int64_t* row_ptr;     // CSR row pointers (count: slot v+1 gets the count)
+    int32_t* col;
+    float* val;
+    double* grad64;       // table-gradient FP64 accumulator (table size)
+    int* status;
+    int accumulate;
+    int ones;             // adj with y == 1 (sensitivity)
+};
+
+// host launchers (ring2d.hip / table.hip)
+hipError_t launch_table_2d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out,
+                           hipStream_t st);
+hipError_t launch_voxel2d(int mode, const Ring2D& G, const VoxArgs2D& a, hipStream_t st);
+hipError_t launch_scan_rowptr(int64_t* row_ptr, int64_t n, hipStream_t st);
+hipError_t launch_finalize(const double* src, float* dst, int64_t n, int accumulate, hipStream_t st);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+size_t voxel2d_smem_bytes(const Ring2D& G, int mode);
+
+enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad = 4 };
+
+}  // namespace psf

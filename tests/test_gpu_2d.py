@@ -1,0 +1,259 @@
+"""GPU parity of the 2D-ring path against the FP64 oracle, through the C ABI.
+
+Bar: crystal-pair indices and the CSR sparsity pattern bit-exact; values
+within 1e-5 relative (FP32 plain form); projections within 1e-5 relative to
+the largest entry.  Decisions the oracle flags as taken within a hair of a
+boundary, and bins within 1e-4 relative of the threshold, are excused from
+the bit-exact pattern check only.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06170_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+CFG = S.CFG_2D
+NARROW = S.CFG_2D_NARROW
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _scanner(cfg):
+    from paper_1607_06170_amd import Scanner
+    return Scanner(cfg)
+
+
+@pytest.fixture(scope="module")
+def ref1(oracle):
+    """Oracle columns for every voxel of the 64 x 64 configuration."""
+    tab = oracle.table_2d(CFG)
+    cols, flags = oracle.columns_2d(CFG, tab, np.arange(64 * 64))
+    return tab, cols, flags
+
+
+@pytest.fixture(scope="module")
+def refn(oracle):
+    tab = oracle.table_2d(NARROW)
+    n = NARROW["nx"] * NARROW["ny"]
+    cols, flags = oracle.columns_2d(NARROW, tab, np.arange(n))
+    return tab, cols, flags
+
+
+@pytest.mark.parametrize("cfg", [CFG, NARROW, dict(CFG, n_sub=1), dict(CFG, n_sub=8)])
+def test_table_parity(torch, oracle, cfg):
+    sc = _scanner(cfg)
+    P = cfg["n_sub"]
+    t = sc.build_table(61, P, 1.0)
+    ref = oracle.table_2d(cfg, n_sub=P).data.reshape(-1)
+    got = t.data.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9)
+
+
+def _compare_csr(oracle, rp, col, val, cols, flags, thr, vox):
+    """CSR from the GPU vs the oracle's thresholded columns for voxels vox."""
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    sub = cols[vox]
+    rpo, colo, valo = oracle.csr_from_columns(sub, thr)
+    ties = (flags[vox] & oracle.F_TIES) != 0
+    near = np.abs(sub - thr) <= 1e-4 * thr
+    exact_rows = ~ties & ~near.any(axis=1)
+    for r in range(len(vox)):
+        g = col[rp[r]:rp[r + 1]]
+        o = colo[rpo[r]:rpo[r + 1]]
+        if exact_rows[r]:
+            assert np.array_equal(g, o), f"row {vox[r]}: pattern differs"
+        gv = val[rp[r]:rp[r + 1]]
+        # every GPU entry's value against the oracle's dense column
+        np.testing.assert_allclose(gv, sub[r, g], rtol=RTOL, atol=0, err_msg=f"row {vox[r]}")
+    assert exact_rows.mean() > 0.95
+    return int(rp[-1])
+
+
+def test_sysmat_full_config(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=CFG["threshold"])
+    torch.cuda.synchronize()
+    nnz = _compare_csr(oracle, rp, col, val, cols, flags, CFG["threshold"], np.arange(64 * 64))
+    assert nnz == int(oracle.csr_from_columns(cols, CFG["threshold"])[0][-1])
+
+
+@pytest.mark.parametrize("vb,ve", [(0, 1), (5, 6), (1000, 1337), (4000, 4096)])
+def test_sysmat_voxel_ranges(torch, oracle, ref1, vb, ve):
+    """Slabs of voxels, including a ragged tail and a single voxel."""
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=CFG["threshold"], vox_begin=vb, vox_end=ve)
+    _compare_csr(oracle, rp, col, val, cols, flags, CFG["threshold"], np.arange(vb, ve))
+
+
+def test_sysmat_no_threshold_narrow_gap(torch, oracle, refn):
+    """Two-block penetration active; every non-zero kept."""
+    tab_o, cols, flags = refn
+    sc = _scanner(NARROW)
+    t = sc.build_table(61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0)
+    n = NARROW["nx"] * NARROW["ny"]
+    _compare_csr(oracle, rp, col, val, cols, flags, 1e-30, np.arange(n))
+
+
+def test_sysmat_random_table(torch, oracle):
+    """A table with no zero entries (every neighbour and remap path used)."""
+    td = S.random_table((61, 4, 5), seed=11)
+    tab_o = oracle.TableRef(td, 61, 4, 1.0)
+    vox = np.arange(0, 44 * 44, 7)
+    cols, flags = oracle.columns_2d(NARROW, tab_o, vox)
+    sc = _scanner(NARROW)
+    t = sc.table_from(td, 61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0)
+    full = np.zeros((44 * 44, cols.shape[1]))
+    full[vox] = cols
+    fl = np.zeros(44 * 44, np.int32)
+    fl[vox] = flags
+    rp_c, col_c, val_c = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    for k, v in enumerate(vox):
+        g = col_c[rp_c[v]:rp_c[v + 1]]
+        o = np.nonzero(cols[k] > 0)[0]
+        if flags[k] & oracle.F_TIES == 0:
+            assert np.array_equal(g, o)
+        np.testing.assert_allclose(val_c[rp_c[v]:rp_c[v + 1]], cols[k][g], rtol=RTOL)
+
+
+def test_forward_projection(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    x = S.phantom_uniform(CFG, seed=1, batch=3)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo = oracle.project_fwd(cols, x.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    assert np.array_equal(y != 0, yo != 0)
+
+
+def test_back_projection_and_adjoint(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    x = S.phantom_uniform(CFG, seed=3, batch=2)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    y_ref = oracle.project_fwd(cols, x)
+    yc = S.poisson_counts(1e3 * y_ref / y_ref.max(), seed=200)
+    yd = torch.tensor(yc, dtype=torch.float32, device="cuda")
+    xb = sc.project_adj(t, yd).cpu().numpy()
+    xbo = oracle.project_adj(cols, yc.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(xb, xbo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xbo).max())
+    # <A x, y> = <x, A^T y> on the GPU path itself
+    yf = sc.project_fwd(t, xd).double()
+    lhs = float((yf * yd.double()).sum())
+    rhs = float((xd.double() * torch.tensor(xb, dtype=torch.float64, device="cuda")).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_sensitivity(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    s = sc.sensitivity(t).cpu().numpy()
+    np.testing.assert_allclose(s, oracle.sensitivity(cols), rtol=RTOL)
+
+
+def test_table_gradient(torch, oracle):
+    """d <g, A x> / d table against the oracle's, and the autograd wrapper
+    against it."""
+    from paper_1607_06170_amd import PsfProject
+    cfg = NARROW
+    n = cfg["nx"] * cfg["ny"]
+    td = S.random_table((61, 4, 5), seed=5)
+    rng = np.random.default_rng(201)
+    x = np.zeros((2, n))
+    vox = rng.choice(n, 40, replace=False)
+    x[:, vox] = rng.random((2, 40))
+    nb = oracle.n_bins_2d(cfg)
+    gy = rng.random((2, nb))
+    tab_o = oracle.TableRef(td, 61, 4, 1.0)
+    xf = x.astype(np.float32).astype(np.float64)
+    gf = gy.astype(np.float32).astype(np.float64)
+    ref = oracle.table_grad_2d(cfg, tab_o, xf[0], gf[0]) + oracle.table_grad_2d(cfg, tab_o, xf[1], gf[1])
+    sc = _scanner(cfg)
+    t = sc.table_from(td, 61, 4, 1.0)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    gyd = torch.tensor(gy, dtype=torch.float32, device="cuda")
+    xb, grad = sc.project_adj(t, gyd, xt=xd, want_table_grad=True)
+    grad = grad.cpu().numpy().reshape(ref.shape)
+    np.testing.assert_allclose(grad, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+    # autograd: backward of <g, y(x, table)>
+    tdat = t.data.clone().requires_grad_(True)
+    xr = xd.clone().requires_grad_(True)
+    y = PsfProject.apply(xr, tdat, sc, (61, 4, 1.0))
+    (y * gyd).sum().backward()
+    np.testing.assert_allclose(tdat.grad.cpu().numpy().reshape(ref.shape), ref, rtol=1e-5,
+                               atol=1e-6 * np.abs(ref).max())
+    np.testing.assert_allclose(xr.grad.cpu().numpy(), xb.cpu().numpy(), rtol=1e-6)
+
+
+def test_autograd_fd_on_gpu(torch):
+    """Central differences of the GPU forward in x and in table entries
+    (float64 sums of the float32 outputs) agree with the hand-written adjoint."""
+    from paper_1607_06170_amd import PsfProject
+    cfg = NARROW
+    n = cfg["nx"] * cfg["ny"]
+    sc = _scanner(cfg)
+    td = S.random_table((61, 4, 5), seed=9)
+    t = sc.table_from(td, 61, 4, 1.0)
+    rng = np.random.default_rng(4)
+    x = torch.tensor(rng.random((1, n)), dtype=torch.float32, device="cuda")
+    g = torch.tensor(rng.random((1, sc.n_bins)), dtype=torch.float32, device="cuda")
+    tdat = t.data.clone().requires_grad_(True)
+    y = PsfProject.apply(x, tdat, sc, (61, 4, 1.0))
+    (y * g).sum().backward()
+    gt = tdat.grad.cpu().numpy()
+    h = 1e-2
+    for e in rng.choice(np.nonzero(gt)[0], 6, replace=False):
+        tp = t.data.clone(); tp[e] += h
+        tm = t.data.clone(); tm[e] -= h
+        from paper_1607_06170_amd import Table
+        yp = sc.project_fwd(Table(tp, 61, 4, 1.0), x).double()
+        ym = sc.project_fwd(Table(tm, 61, 4, 1.0), x).double()
+        fd = float(((yp - ym) * g.double()).sum()) / (2 * h)
+        assert abs(fd - gt[e]) <= 2e-3 * abs(gt[e]) + 1e-3 * np.abs(gt).max(), (e, fd, gt[e])
+
+
+@pytest.mark.parametrize("prec,elem_tol,proj_tol", [(1, 1e-2, 1e-2), (2, 1e-4, 1e-4)])
+def test_precision_forms(torch, oracle, ref1, prec, elem_tol, proj_tol):
+    """BF16 operand forms: per-element and per-projection error against FP64."""
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    vb, ve = 2000, 2100
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, precision=prec)
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    for r in range(ve - vb):
+        c = col[rp[r]:rp[r + 1]]
+        ref = cols[vb + r][c]
+        rel = np.abs(val[rp[r]:rp[r + 1]] - ref) / ref
+        assert rel.max() <= elem_tol
+    x = S.phantom_uniform(CFG, seed=1)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda"), precision=prec).cpu().numpy()
+    yo = oracle.project_fwd(cols, x)
+    big = yo > 1e-3 * yo.max()
+    assert (np.abs(y - yo)[big] / yo[big]).max() <= proj_tol
+
+
+def test_range_error_reported(torch):
+    """A table too short for the incidence angles in use: PSF_ERANGE."""
+    from paper_1607_06170_amd import PsfError
+    sc = _scanner(CFG)
+    t = sc.build_table(20, 4, 1.0)   # rows up to 19 degrees; the ring needs ~50
+    with pytest.raises(PsfError) as e:
+        sc.build_psf_sysmat(t, threshold=1e-6, vox_begin=0, vox_end=8)
+    assert e.value.code == -3
