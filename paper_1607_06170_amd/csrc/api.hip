@@ -205,15 +205,45 @@ static int read_status(void* ws, hipStream_t st) {
     if (s & kStatOverflow) return PSF_EOVERFLOW;
     if (s & kStatRange) return PSF_ERANGE;
     if (s & kStatGeom) return PSF_EGEOM;
+    if (s & kStatEventBad) return PSF_EINVAL;
     return PSF_OK;
 }
 
-// workspace: header | FP64 bin accumulator [batch][n_bins] | FP64 table gradient
-static size_t ws_need(const psf_handle* h, const psf_table* t, int batch) {
-    size_t b = kWsHeader;
-    b += align256(sizeof(double) * (size_t)(batch > 0 ? batch : 1) * (size_t)h->n_bins);
-    b += align256(sizeof(double) * (size_t)table_elems(h, t));
-    return b;
+// Workspace layout, all regions 256-byte aligned:
+//   header   status word (+ spare)
+//   y64      FP64 bin accumulator [batch][n_bins]   (forward; list-mode rows)
+//   g64      FP64 table-gradient accumulator [table entries]
+//   h64      FP64 bin histogram [batch][n_bins]      (list-mode only)
+//   h32      FP32 copy of h64                        (list-mode only)
+//   back     FP32 back projection [n_voxels]         (LM-OSEM only)
+struct WsLayout {
+    size_t y64, g64, h64, h32, back, total;
+};
+
+static WsLayout ws_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
+    WsLayout L;
+    const size_t b = (size_t)(batch > 0 ? batch : 1);
+    size_t off = kWsHeader;
+    L.y64 = off;
+    off += align256(sizeof(double) * b * (size_t)h->n_bins);
+    L.g64 = off;
+    off += align256(sizeof(double) * (size_t)table_elems(h, t));
+    L.h64 = L.h32 = L.back = off;
+    if (n_events > 0) {
+        L.h64 = off;
+        off += align256(sizeof(double) * b * (size_t)h->n_bins);
+        L.h32 = off;
+        off += align256(sizeof(float) * b * (size_t)h->n_bins);
+        L.back = off;
+        off += align256(sizeof(float) * (size_t)h->n_vox);
+    }
+    L.total = off;
+    return L;
+}
+
+template <class T>
+static T* at(void* ws, size_t off) {
+    return (T*)((char*)ws + off);
 }
 
 extern "C" {
@@ -221,9 +251,8 @@ extern "C" {
 int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
                        int64_t n_events, size_t* bytes) {
     (void)opts;
-    (void)n_events;
-    if (!h || !table || !bytes || batch < 0) return PSF_EINVAL;
-    *bytes = ws_need(h, table, batch);
+    if (!h || !table || !bytes || batch < 0 || n_events < 0) return PSF_EINVAL;
+    *bytes = ws_layout(h, table, batch, n_events).total;
     return PSF_OK;
 }
 
@@ -282,19 +311,14 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
     return read_status(ws, s);
 }
 
-int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int32_t batch,
-                const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, void* stream) {
-    if (!h || !x || !y || !ws || batch < 1) return PSF_EINVAL;
-    int st = check_table(h, table);
-    if (st) return st;
-    if ((st = check_opts(opts))) return st;
-    if (h->mode3d || events) return PSF_EUNSUPPORTED;
-    (void)n_events;
-    if (ws_bytes < ws_need(h, table, batch)) return PSF_ESIZE;
-    const hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+// y64[batch][n_bins] = A x (FP64 accumulation), on the fly
+static int fwd_bins(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int batch,
+                    double* y64, void* ws, hipStream_t s) {
     Ring2D G = make_ring2d(h, table, opts);
-    if ((st = check_2d_support(h, G, kModeFwd))) return st;
-    double* y64 = (double*)((char*)ws + kWsHeader);
+    int st = check_2d_support(h, G, kModeFwd);
+    if (st) return st;
     VoxArgs2D a;
     memset(&a, 0, sizeof(a));
     a.vox_begin = 0;
@@ -303,30 +327,21 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     a.x = x;
     a.y64 = y64;
     a.status = (int*)ws;
-    if ((st = zero_header(ws, s))) return st;
     HIP_TRY(launch_zero_f64(y64, (int64_t)batch * h->n_bins, s));
     HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
-    HIP_TRY(launch_finalize(y64, y, (int64_t)batch * h->n_bins, opts->accumulate, s));
     return PSF_OK;
 }
 
-static int adj_common(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int ones,
-                      int32_t batch, float* x, const float* xt, float* grad, void* ws, size_t ws_bytes,
-                      hipStream_t s) {
-    int st = check_table(h, table);
-    if (st) return st;
-    if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
-    if (ws_bytes < ws_need(h, table, batch)) return PSF_ESIZE;
+// x[batch][n_voxels] = A^T y (y FP32 [batch][n_bins], or all ones), optionally
+// with the table gradient accumulated into g64
+static int adj_bins(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int ones,
+                    int batch, float* x, const float* xt, double* g64, int accumulate, void* ws, hipStream_t s) {
     Ring2D G = make_ring2d(h, table, opts);
-    const int mode = grad ? kModeAdjGrad : kModeAdj;
-    if ((st = check_2d_support(h, G, mode))) return st;
-    double* g64 = (double*)((char*)ws + kWsHeader + align256(sizeof(double) * (size_t)batch * h->n_bins));
-    if ((st = zero_header(ws, s))) return st;
-    const int64_t tsize = table_elems(h, table);
-    if (grad) HIP_TRY(launch_zero_f64(g64, tsize, s));
+    const int mode = g64 ? kModeAdjGrad : kModeAdj;
+    int st = check_2d_support(h, G, mode);
+    if (st) return st;
     // the table-gradient kernel keeps up to 8 images' voxel values in registers
-    const int chunk = grad ? 8 : batch;
+    const int chunk = g64 ? 8 : batch;
     for (int b0 = 0; b0 < batch; b0 += chunk) {
         const int nb = batch - b0 < chunk ? batch - b0 : chunk;
         VoxArgs2D a;
@@ -340,35 +355,106 @@ static int adj_common(psf_handle* h, const psf_table* table, const psf_opts* opt
         a.x = xt ? xt + (int64_t)b0 * h->n_vox : nullptr;
         a.grad64 = g64;
         a.status = (int*)ws;
-        a.accumulate = opts->accumulate;
+        a.accumulate = accumulate;
         HIP_TRY(launch_voxel2d(mode, G, a, s));
     }
-    if (grad) HIP_TRY(launch_finalize(g64, grad, tsize, 1, s));
+    return PSF_OK;
+}
+
+extern "C" {
+
+int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int32_t batch,
+                const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !x || !y || !ws || batch < 1 || n_events < 0) return PSF_EINVAL;
+    if (events && n_events == 0) return PSF_OK;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    const WsLayout L = ws_layout(h, table, batch, events ? n_events : 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    double* y64 = at<double>(ws, L.y64);
+    if ((st = fwd_bins(h, table, opts, x, batch, y64, ws, s))) return st;
+    if (events) {
+        HIP_TRY(launch_lm_gather(y64, h->n_bins, events, n_events, batch, h->n_crystals, y, opts->accumulate,
+                                 (int*)ws, s));
+    } else {
+        HIP_TRY(launch_finalize(y64, y, (int64_t)batch * h->n_bins, opts->accumulate, s));
+    }
     return PSF_OK;
 }
 
 int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int32_t batch,
                 const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
                 size_t ws_bytes, void* stream) {
-    if (!h || !y || !x || !ws || batch < 1) return PSF_EINVAL;
+    if (!h || !y || !x || !ws || batch < 1 || n_events < 0) return PSF_EINVAL;
     if (grad && !xt) return PSF_EINVAL;
-    if (events) return PSF_EUNSUPPORTED;
-    (void)n_events;
-    return adj_common(h, table, opts, y, 0, batch, x, xt, grad, ws, ws_bytes, (hipStream_t)stream);
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    const WsLayout L = ws_layout(h, table, batch, events ? n_events : 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    const float* ybins = y;
+    if (events) {
+        double* h64 = at<double>(ws, L.h64);
+        float* h32 = at<float>(ws, L.h32);
+        const int64_t n = (int64_t)batch * h->n_bins;
+        HIP_TRY(launch_zero_f64(h64, n, s));
+        HIP_TRY(launch_lm_scatter(y, n_events, events, batch, h->n_crystals, h->n_bins, h64, (int*)ws, s));
+        HIP_TRY(launch_finalize(h64, h32, n, 0, s));
+        ybins = h32;
+    }
+    double* g64 = grad ? at<double>(ws, L.g64) : nullptr;
+    const int64_t tsize = table_elems(h, table);
+    if (grad) HIP_TRY(launch_zero_f64(g64, tsize, s));
+    if ((st = adj_bins(h, table, opts, ybins, 0, batch, x, xt, g64, opts->accumulate, ws, s))) return st;
+    if (grad) HIP_TRY(launch_finalize(g64, grad, tsize, 1, s));
+    return PSF_OK;
 }
 
 int psf_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts, float* s_dev, void* ws,
                     size_t ws_bytes, void* stream) {
     if (!h || !s_dev || !ws) return PSF_EINVAL;
-    return adj_common(h, table, opts, nullptr, 1, 1, s_dev, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream);
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (ws_bytes < ws_layout(h, table, 1, 0).total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    return adj_bins(h, table, opts, nullptr, 1, 1, s_dev, nullptr, nullptr, 0, ws, s);
 }
 
 int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* opts, const int32_t* events,
                        int64_t n_events, float randoms, const float* sens, int32_t n_subsets, const float* x_in,
                        float* x_out, void* ws, size_t ws_bytes, void* stream) {
-    (void)h; (void)table; (void)opts; (void)events; (void)n_events; (void)randoms; (void)sens;
-    (void)n_subsets; (void)x_in; (void)x_out; (void)ws; (void)ws_bytes; (void)stream;
-    return PSF_EUNSUPPORTED;
+    if (!h || !events || !sens || !x_in || !x_out || !ws || n_events < 1 || n_subsets < 1) return PSF_EINVAL;
+    if (!(randoms >= 0.0f)) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    const WsLayout L = ws_layout(h, table, 1, n_events);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    double* y64 = at<double>(ws, L.y64);
+    double* h64 = at<double>(ws, L.h64);
+    float* h32 = at<float>(ws, L.h32);
+    float* back = at<float>(ws, L.back);
+    // q_e = a_e^T x + r  ->  h[bin] += 1 / q_e  ->  back = A^T h  ->  update
+    if ((st = fwd_bins(h, table, opts, x_in, 1, y64, ws, s))) return st;
+    HIP_TRY(launch_zero_f64(h64, h->n_bins, s));
+    HIP_TRY(launch_lm_ratio(y64, events, n_events, h->n_crystals, (double)randoms, h64, (int*)ws, s));
+    HIP_TRY(launch_finalize(h64, h32, h->n_bins, 0, s));
+    if ((st = adj_bins(h, table, opts, h32, 0, 1, back, nullptr, nullptr, 0, ws, s))) return st;
+    HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
+    return PSF_OK;
 }
 
 int psf_check(psf_handle* h, void* ws, void* stream) {

@@ -18,6 +18,7 @@ constexpr int kNb = 5;  // neighbour crystals per axis: offsets -2..2
 constexpr int kStatRange = 1;     // an incidence angle beyond the last table row was used
 constexpr int kStatOverflow = 2;  // fill phase wanted more entries than allotted
 constexpr int kStatGeom = 4;
+constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or the same crystal twice
 
 // Workspace header: status word, nnz total, padding to 256 bytes.
 constexpr size_t kWsHeader = 256;
@@ -69,6 +70,14 @@ hipError_t launch_scan_rowptr(int64_t* row_ptr, int64_t n, hipStream_t st);
 hipError_t launch_finalize(const double* src, float* dst, int64_t n, int accumulate, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 size_t voxel2d_smem_bytes(const Ring2D& G, int mode);
+hipError_t launch_lm_gather(const double* y64, int64_t nbins, const int32_t* ev, int64_t ne, int batch, int64_t N,
+                            float* out, int accumulate, int* status, hipStream_t st);
+hipError_t launch_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t N, int64_t nbins,
+                             double* hist, int* status, hipStream_t st);
+hipError_t launch_lm_ratio(const double* y64, const int32_t* ev, int64_t ne, int64_t N, double randoms, double* hist,
+                           int* status, hipStream_t st);
+hipError_t launch_lm_update(const float* x_in, const float* back, const float* sens, int n_subsets, int64_t nvox,
+                            float* x_out, hipStream_t st);
 
 enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad = 4 };
 

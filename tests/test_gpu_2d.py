@@ -257,3 +257,68 @@ def test_range_error_reported(torch):
     with pytest.raises(PsfError) as e:
         sc.build_psf_sysmat(t, threshold=1e-6, vox_begin=0, vox_end=8)
     assert e.value.code == -3
+
+
+# ---------------------------------------------------------------------------
+# list-mode rows and one LM-OSEM subset update
+# ---------------------------------------------------------------------------
+
+def _events(oracle, cols, x, n_true, n_rand, seed):
+    """Events drawn from the oracle's forward projection of x (plus uniform
+    randoms); half of them with the crystal order swapped."""
+    yo = oracle.project_fwd(cols, x)[0]
+    bins = S.sample_events(yo, n_true, n_rand, seed=seed)
+    i, j = S.bin_to_pair(bins, 128)
+    rng = np.random.default_rng(seed + 1)
+    swap = rng.random(len(bins)) < 0.5
+    ev = np.stack([np.where(swap, j, i), np.where(swap, i, j)], 1).astype(np.int32)
+    return bins, ev
+
+
+def test_listmode_rows(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    x = S.phantom_uniform(CFG, seed=1)
+    bins, ev = _events(oracle, cols, x, 45_000, 5_000, 300)
+    evd = torch.tensor(ev, device="cuda")
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    q = sc.project_fwd(t, xd, events=evd).cpu().numpy()[0]
+    qo = oracle.listmode_fwd(cols, bins, x.astype(np.float32).astype(np.float64)[0])
+    np.testing.assert_allclose(q, qo, rtol=RTOL, atol=RTOL * 1e-2 * qo.max())
+    h = np.random.default_rng(5).random(len(bins))
+    back = sc.project_adj(t, torch.tensor(h[None], dtype=torch.float32, device="cuda"), events=evd)
+    sc.check()
+    bo = oracle.listmode_adj(cols, bins, h.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(back.cpu().numpy()[0], bo, rtol=RTOL, atol=RTOL * 1e-2 * bo.max())
+
+
+def test_lm_osem_update(torch, oracle, ref1):
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    x_true = S.phantom_uniform(CFG, seed=1)
+    bins, ev = _events(oracle, cols, x_true, 90_000, 10_000, 302)
+    sens_o = oracle.sensitivity(cols)
+    M = 10
+    sub = slice(0, 10_000)
+    randoms = 0.1 * float(oracle.project_fwd(cols, x_true).mean())
+    x0 = np.full(sc.n_voxels, 1.0)
+    xo = oracle.lm_osem_update(cols, bins[sub], x0, sens_o, M, randoms)
+    sens = sc.sensitivity(t)
+    xg = sc.lm_osem_update(t, torch.tensor(ev[sub], device="cuda"), torch.tensor(x0, dtype=torch.float32,
+                           device="cuda"), sens, M, randoms)
+    sc.check()
+    np.testing.assert_allclose(xg.cpu().numpy(), xo, rtol=2e-5, atol=2e-5 * xo.max())
+
+
+def test_listmode_bad_event_reported(torch):
+    from paper_1607_06170_amd import PsfError
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    ev = torch.tensor([[0, 5], [3, 3], [1, 200]], dtype=torch.int32, device="cuda")
+    q = sc.project_fwd(t, torch.ones(1, sc.n_voxels, device="cuda"), events=ev)
+    with pytest.raises(PsfError) as e:
+        sc.check()
+    assert e.value.code == -1
+    assert q[0, 1].item() == 0.0 and q[0, 2].item() == 0.0
