@@ -106,14 +106,27 @@ def lib():
             L.og_table_grad_2d.argtypes = [G, T, I, _dp, _dp, C.c_int, _dp, C.c_int]
             L.og_gauss_legendre.restype = None
             L.og_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
-            if hasattr(L, "og_table_3d"):
+            if hasattr(L, "og_table3_rows"):
                 _bind3d(L, G, I, T)
             _lib = L
     return _lib
 
 
 def _bind3d(L, G, I, T):
-    pass
+    L.og_rho_point3.restype = C.c_double
+    L.og_rho_point3.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int] + [C.c_double] * 4
+    L.og_rho_sub3.restype = C.c_double
+    L.og_rho_sub3.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [C.c_double] * 4
+    L.og_table3_rows.restype = None
+    L.og_table3_rows.argtypes = [G, C.c_int, C.c_double, _i32p, _i32p, C.c_int, _dp, C.c_int]
+    L.og_uv_row_3d.restype = C.c_int
+    L.og_uv_row_3d.argtypes = [G, T, _dp, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _i32p]
+    L.og_columns_3d.restype = None
+    L.og_columns_3d.argtypes = [G, T, I, _i64p, C.c_int64, C.c_int64, _i64p, _dp, _i64p, _i32p, C.c_int]
+    L.og_table_grad_3d.restype = None
+    L.og_table_grad_3d.argtypes = [G, T, I, _i64p, _dp, C.c_int64, _i64p, _dp, C.c_int64, _dp, C.c_int]
+    L.og_w3_pair.restype = C.c_double
+    L.og_w3_pair.argtypes = [G, C.c_int, _dp, C.c_int, C.c_int, C.c_int, C.c_int]
 
 
 # ---------------------------------------------------------------------------
@@ -281,6 +294,78 @@ def lm_osem_update(cols: np.ndarray, ev_bins: np.ndarray, x: np.ndarray, sens: n
     nz = sens > 0
     out[nz] = x[nz] / (sens[nz] / n_subsets) * back[nz]
     return out
+
+
+# ---------------------------------------------------------------------------
+# 3D scanner (extension of Sec 2 to block rings; see psf_oracle3d.c)
+# ---------------------------------------------------------------------------
+
+def n_rings(cfg: dict) -> int:
+    return int(cfg.get("n_cz", 1)) * int(cfg.get("n_brings", 1))
+
+
+def n_crystals_3d(cfg: dict) -> int:
+    return n_crystals_ring(cfg) * n_rings(cfg)
+
+
+def rho_point3(tt, tz, ut, uz, at, az, lt, lz, depth, mu):
+    return lib().og_rho_point3(tt, tz, ut, uz, at, az, lt, lz, depth, mu)
+
+
+def rho_sub3(alpha_t, alpha_z, pt, pz, P, at, az, lt, lz, depth, mu):
+    return lib().og_rho_sub3(alpha_t, alpha_z, pt, pz, P, at, az, lt, lz, depth, mu)
+
+
+def table3_rows(cfg: dict, rows_t, rows_z, n_sub: int = 4, step_deg: float = 1.0, nthreads: int = 0):
+    """Analytic 3D table entries for the listed (row_t, row_z) pairs:
+    array [n][n_sub][n_sub][5][5]."""
+    rt = np.ascontiguousarray(rows_t, dtype=np.int32)
+    rz = np.ascontiguousarray(rows_z, dtype=np.int32)
+    out = np.zeros(len(rt) * n_sub * n_sub * 25)
+    lib().og_table3_rows(C.byref(geom(cfg)), n_sub, step_deg, rt, rz, len(rt), out, nthreads)
+    return out.reshape(len(rt), n_sub, n_sub, 5, 5)
+
+
+def uv_row_3d(cfg: dict, tab: TableRef, c, g: int, pt: int, r: int, pz: int):
+    val = np.zeros(25)
+    src = np.zeros(25, dtype=np.int32)
+    fl = lib().og_uv_row_3d(C.byref(geom(cfg)), C.byref(tab.c), np.ascontiguousarray(c, dtype=np.float64), g, pt, r,
+                            pz, val, src)
+    return val.reshape(5, 5), src.reshape(5, 5), fl
+
+
+def w3_pair(cfg: dict, n_sub: int, c, s1: int, q1: int, s2: int, q2: int) -> float:
+    return lib().og_w3_pair(C.byref(geom(cfg)), n_sub, np.ascontiguousarray(c, dtype=np.float64), s1, q1, s2, q2)
+
+
+def columns_3d(cfg: dict, tab: TableRef, vox, cap: int = 1 << 20, nthreads: int = 0):
+    """Sparse FP64 columns for the voxels in vox: list of (bins int64, vals), flags."""
+    vox = np.ascontiguousarray(np.asarray(vox, dtype=np.int64))
+    nv = len(vox)
+    bins = np.zeros(nv * cap, np.int64)
+    vals = np.zeros(nv * cap)
+    cnt = np.zeros(nv, np.int64)
+    flags = np.zeros(nv, np.int32)
+    lib().og_columns_3d(C.byref(geom(cfg)), C.byref(tab.c), C.byref(image(cfg)), vox, nv, cap, bins, vals, cnt,
+                        flags, nthreads)
+    out = []
+    for k in range(nv):
+        n = int(cnt[k])
+        assert n <= cap, "column capacity exceeded"
+        out.append((bins[k * cap:k * cap + n].copy(), vals[k * cap:k * cap + n].copy()))
+    return out, flags
+
+
+def table_grad_3d(cfg: dict, tab: TableRef, vox, xv, gy_bins, gy_vals, nthreads: int = 0):
+    """d <gy, A x> / d table for x supported on vox (values xv), gy sparse (sorted bins)."""
+    vox = np.ascontiguousarray(np.asarray(vox, dtype=np.int64))
+    order = np.argsort(gy_bins)
+    gb = np.ascontiguousarray(np.asarray(gy_bins, dtype=np.int64)[order])
+    gv = np.ascontiguousarray(np.asarray(gy_vals, dtype=np.float64)[order])
+    grad = np.zeros(tab.data.size)
+    lib().og_table_grad_3d(C.byref(geom(cfg)), C.byref(tab.c), C.byref(image(cfg)), vox,
+                           np.ascontiguousarray(xv, dtype=np.float64), len(vox), gb, gv, len(gb), grad, nthreads)
+    return grad.reshape(tab.data.shape)
 
 
 def pair_bin(i, j, n):

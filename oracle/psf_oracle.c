@@ -264,7 +264,7 @@ static double boundary_xi(const og_geom* G, int P, int k) {
 }
 
 /* true when (vx, vy) lies strictly inside every block's front-face line */
-static int inside_ring(const og_geom* G, double vx, double vy) {
+int og_inside_ring(const og_geom* G, double vx, double vy) {
     for (int b = 0; b < G->n_blocks; b++) {
         double phi = G->phi0 + 2.0 * OG_PI * b / G->n_blocks;
         if (!(cos(phi) * vx + sin(phi) * vy < G->r_face)) return 0;
@@ -358,7 +358,7 @@ static int64_t pair_bin(int64_t i, int64_t j, int64_t n) {
 }
 
 /* direction interval [lo, lo + len) of every sub-segment seen from (vx, vy) */
-static void seg_intervals(const og_geom* G, int P, double vx, double vy, double* lo, double* len) {
+void og_seg_intervals(const og_geom* G, int P, double vx, double vy, double* lo, double* len) {
     int nc = G->n_ct, R = G->n_blocks;
     for (int b = 0; b < R; b++) {
         for (int c = 0; c < nc; c++) {
@@ -378,7 +378,7 @@ static void seg_intervals(const og_geom* G, int P, double vx, double vy, double*
 }
 
 /* measure of the directions in I1 whose opposite direction lies in I2 */
-static double overlap_opposite(double lo1, double len1, double lo2, double len2) {
+double og_overlap_opposite(double lo1, double len1, double lo2, double len2) {
     double d = wrap_pm_pi(lo2 + OG_PI - lo1);
     double hi = fmin(len1, d + len2);
     double lo = fmax(0.0, d);
@@ -401,13 +401,13 @@ int og_samples_2d(const og_geom* G, int P, double vx, double vy, int homog_k, in
     int nseg = G->n_blocks * G->n_ct * P;
     double* lo = (double*)malloc(sizeof(double) * nseg);
     double* len = (double*)malloc(sizeof(double) * nseg);
-    if (!inside_ring(G, vx, vy)) flags |= OGF_GEOM;
-    seg_intervals(G, P, vx, vy, lo, len);
+    if (!og_inside_ring(G, vx, vy)) flags |= OGF_GEOM;
+    og_seg_intervals(G, P, vx, vy, lo, len);
     int64_t n = 0;
     if (homog_k == 0) {
         for (int s1 = 0; s1 < nseg; s1++) {
             for (int s2 = s1 + 1; s2 < nseg; s2++) {
-                double ov = overlap_opposite(lo[s1], len[s1], lo[s2], len[s2]);
+                double ov = og_overlap_opposite(lo[s1], len[s1], lo[s2], len[s2]);
                 if (fabs(ov - OG_EPS_OV) < 1e-13) flags |= OGF_OVERLAP_TIE;
                 if (!(ov > OG_EPS_OV)) continue;
                 if (n < max_out) {

@@ -32,6 +32,15 @@ CFG_3D = dict(n_blocks=32, n_ct=12, n_cz=12, n_brings=4, pitch_t=2.0, pitch_z=2.
               n_rows=61, n_sub=4, step_deg=1.0, threshold=0.0)
 
 
+# A small 3D scanner for element-by-element checks: 12 blocks of 4 x 4
+# crystals (2 mm, 10 mm deep), 2 block rings (8 crystal rings), faces 16 mm
+# from the axis (1.1 mm half-gap, so photons cross into the next block);
+# 10 x 10 x 6 image of 1 mm voxels; tables cover 0-90 degrees.
+CFG_3D_SMALL = dict(n_blocks=12, n_ct=4, n_cz=4, n_brings=2, pitch_t=2.0, pitch_z=2.0, depth=10.0, r_face=16.0,
+                    gap_z=0.0, mu=0.087, phi0=0.0, nx=10, ny=10, nz=6, dx=1.0, dy=1.0, dz=1.0,
+                    n_rows=91, n_sub=4, step_deg=1.0, threshold=0.0)
+
+
 def phantom_uniform(cfg: dict, seed: int = 1, batch: int = 1) -> np.ndarray:
     """Uniform [0, 1) random image(s), float64, shape [batch, n_voxels]."""
     rng = np.random.default_rng(seed)
