@@ -393,6 +393,8 @@ double og_w3(const w3_ctx* c, double th_a, double th_b) {
         for (int k = 0; k < NSUB; k++) {
             double a = th_a + (th_b - th_a) * k / NSUB, b = th_a + (th_b - th_a) * (k + 1) / NSUB;
             double ga = w3_g(c, a, which), gb = w3_g(c, b, which);
+            /* a kink exactly on an interior subdivision point is a cut too */
+            if (k > 0 && ga == 0.0) cuts[nc++] = a;
             if ((ga < 0.0 && gb > 0.0) || (ga > 0.0 && gb < 0.0)) {
                 for (int it = 0; it < 200 && b - a > 1e-17; it++) {
                     double m = 0.5 * (a + b), gm = w3_g(c, m, which);
@@ -458,13 +460,21 @@ static void hm_add(hmap* h, int64_t k, double v) {
     h->val[i] += v;
 }
 
-static int64_t pair_bin(int64_t i, int64_t j, int64_t n) {
-    if (i > j) {
-        int64_t t = i;
-        i = j;
-        j = t;
+/*
+ * 3D bin of the crystal pair (g1, r1), (g2, r2): the transaxial pair, ordered
+ * (g_i < g_j), then the rings in that order:
+ *     bin = tbin(g_i, g_j) * NR^2 + r_i * NR + r_j,
+ * tbin the 2D numbering of unordered transaxial pairs.  Pairs with g1 == g2
+ * (never joined by a line through the inside of the ring) have no bin: -1.
+ */
+static int64_t bin3(int64_t g1, int64_t r1, int64_t g2, int64_t r2, int64_t Nc, int64_t NR) {
+    if (g1 == g2) return -1;
+    if (g1 > g2) {
+        int64_t t = g1; g1 = g2; g2 = t;
+        t = r1; r1 = r2; r2 = t;
     }
-    return i * n - i * (i + 1) / 2 + (j - i - 1);
+    const int64_t tb = g1 * Nc - g1 * (g1 + 1) / 2 + (g2 - g1 - 1);
+    return (tb * NR + r1) * NR + r2;
 }
 
 typedef struct {
@@ -498,7 +508,6 @@ static int column3(const og_geom* G, const og_table* T, const double* c, int64_t
     int flags = 0;
     const int P = T->n_sub, nc = G->n_ct, R = G->n_blocks, Nc = R * nc, NR = n_rings(G), NZ = NR * P;
     const int nseg = Nc * P;
-    const int64_t Ntot = (int64_t)Nc * NR;
     const double lz = G->pitch_z, z0 = z_first(G);
     if (!og_inside_ring(G, c[0], c[1])) flags |= OGF_GEOM;
     double* lo = (double*)malloc(sizeof(double) * nseg);
@@ -609,9 +618,8 @@ static int column3(const og_geom* G, const og_table* T, const double* c, int64_t
                                         for (int ib = 0; ib < 25; ib++) {
                                             const int ct2 = ((g2 + ib / 5 - 2) % Nc + Nc) % Nc, rr2 = r2 + ib % 5 - 2;
                                             if (rr2 < 0 || rr2 >= NR) continue;
-                                            const int64_t id1 = (int64_t)rr1 * Nc + ct1, id2 = (int64_t)rr2 * Nc + ct2;
-                                            if (id1 == id2) continue;
-                                            const int64_t bin = pair_bin(id1, id2, Ntot);
+                                            const int64_t bin = bin3(ct1, rr1, ct2, rr2, Nc, NR);
+                                            if (bin < 0) continue;
                                             const int64_t* f = (const int64_t*)bsearch(&bin, gy_bins, n_gy,
                                                                                        sizeof(int64_t), cmp_i64);
                                             if (!f) continue;
@@ -640,9 +648,9 @@ static int column3(const og_geom* G, const og_table* T, const double* c, int64_t
                             if (t == 0.0) continue;
                             const int ct2 = ((g2 + ib / 5 - 2) % Nc + Nc) % Nc, rr2 = r2 + ib % 5 - 2;
                             if (rr2 < 0 || rr2 >= NR) continue;
-                            const int64_t id1 = (int64_t)rr1 * Nc + ct1, id2 = (int64_t)rr2 * Nc + ct2;
-                            if (id1 == id2) continue;
-                            hm_add(&hm, pair_bin(id1, id2, Ntot), t);
+                            const int64_t bin = bin3(ct1, rr1, ct2, rr2, Nc, NR);
+                            if (bin < 0) continue;
+                            hm_add(&hm, bin, t);
                         }
                     }
                 }
