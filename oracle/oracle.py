@@ -368,6 +368,21 @@ def table_grad_3d(cfg: dict, tab: TableRef, vox, xv, gy_bins, gy_vals, nthreads:
     return grad.reshape(tab.data.shape)
 
 
+def bin3(g1, r1, g2, r2, cfg: dict):
+    """3D bin numbering: transaxial pair (g_i < g_j) major, then (r_i, r_j)."""
+    Nc, NR = n_crystals_ring(cfg), n_rings(cfg)
+    g1, r1, g2, r2 = (np.asarray(a, dtype=np.int64) for a in (g1, r1, g2, r2))
+    sw = g1 > g2
+    gi, gj = np.where(sw, g2, g1), np.where(sw, g1, g2)
+    ri, rj = np.where(sw, r2, r1), np.where(sw, r1, r2)
+    tb = gi * Nc - gi * (gi + 1) // 2 + (gj - gi - 1)
+    return np.where(g1 == g2, -1, (tb * NR + ri) * NR + rj)
+
+
+def n_bins_3d(cfg: dict) -> int:
+    return n_bins_2d(cfg) * n_rings(cfg) ** 2
+
+
 def pair_bin(i, j, n):
     i, j = np.minimum(i, j), np.maximum(i, j)
     return i * n - i * (i + 1) // 2 + (j - i - 1)

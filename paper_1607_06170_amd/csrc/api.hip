@@ -6,32 +6,14 @@
 
 #include <new>
 
-#include "common.hpp"
+#include "api_internal.hpp"
 
 using namespace psf;
 
-struct psf_handle {
-    psf_geometry g;
-    psf_image im;
-    int mode3d;
-    int device;
-    int64_t n_crystals, n_bins, n_vox;
-    double sigma;
-    double* frames_dev;  // [R][2] cos, sin of each block's outward normal
-};
+namespace psf {
+thread_local int g_last_hip = 0;
+}
 
-static thread_local int g_last_hip = 0;
-
-#define HIP_TRY(expr)                         \
-    do {                                      \
-        hipError_t e_ = (expr);               \
-        if (e_ != hipSuccess) {               \
-            g_last_hip = (int)e_;             \
-            return PSF_EHIP;                  \
-        }                                     \
-    } while (0)
-
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 static int check_geometry(const psf_geometry* g, const psf_image* im, int mode3d) {
     if (g->n_blocks < 3 || g->n_cryst_t < 1 || g->n_cryst_z < 1 || g->n_block_rings < 1) return PSF_EINVAL;
@@ -73,7 +55,8 @@ int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, p
     const int64_t Nc = (int64_t)geom->n_blocks * geom->n_cryst_t;
     const int64_t rings = (int64_t)geom->n_cryst_z * geom->n_block_rings;
     h->n_crystals = mode3d ? Nc * rings : Nc;
-    h->n_bins = h->n_crystals * (h->n_crystals - 1) / 2;
+    // 2D: unordered crystal pairs; 3D: transaxial pair major, then the ring pair
+    h->n_bins = mode3d ? Nc * (Nc - 1) / 2 * rings * rings : h->n_crystals * (h->n_crystals - 1) / 2;
     h->n_vox = (int64_t)img->nx * img->ny * img->nz;
     h->sigma = geom->radius_face * tan(M_PI / geom->n_blocks) - 0.5 * geom->n_cryst_t * geom->pitch_t;
     double* fr = (double*)malloc(sizeof(double) * 2 * geom->n_blocks);
@@ -87,7 +70,7 @@ int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, p
     if (e == hipSuccess) e = hipMemcpy(h->frames_dev, fr, sizeof(double) * 2 * geom->n_blocks, hipMemcpyHostToDevice);
     free(fr);
     if (e != hipSuccess) {
-        g_last_hip = (int)e;
+        psf::g_last_hip = (int)e;
         if (h->frames_dev) (void)hipFree(h->frames_dev);
         delete h;
         return PSF_EHIP;
@@ -124,7 +107,7 @@ const char* psf_status_string(int s) {
     }
 }
 
-int psf_last_hip_error(void) { return g_last_hip; }
+int psf_last_hip_error(void) { return psf::g_last_hip; }
 
 }  // extern "C"
 
@@ -132,12 +115,12 @@ int psf_last_hip_error(void) { return g_last_hip; }
 // helpers
 // ---------------------------------------------------------------------------
 
-static int64_t table_elems(const psf_handle* h, const psf_table* t) {
+int64_t table_elems(const psf_handle* h, const psf_table* t) {
     if (h->mode3d) return (int64_t)t->n_rows * t->n_rows * t->n_sub * t->n_sub * kNb * kNb;
     return (int64_t)t->n_rows * t->n_sub * kNb;
 }
 
-static int check_table(const psf_handle* h, const psf_table* t) {
+int check_table(const psf_handle* h, const psf_table* t) {
     if (!t || !t->data) return PSF_EINVAL;
     if (t->n_rows < 1 || t->n_sub < 1 || !(t->step_deg > 0)) return PSF_EINVAL;
     return PSF_OK;
@@ -179,7 +162,7 @@ static int check_2d_support(const psf_handle* h, const Ring2D& G, int mode) {
     return PSF_OK;
 }
 
-static int check_opts(const psf_opts* o) {
+int check_opts(const psf_opts* o) {
     if (!o) return PSF_EINVAL;
     if (o->precision < PSF_FP32 || o->precision > PSF_BF16X2) return PSF_EINVAL;
     if (o->homog_k < 0) return PSF_EINVAL;
@@ -192,13 +175,13 @@ __global__ void k_zero_header(int* p) {
     if (threadIdx.x < kWsHeader / sizeof(int)) p[threadIdx.x] = 0;
 }
 
-static int zero_header(void* ws, hipStream_t st) {
+int zero_header(void* ws, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, (int*)ws);
     HIP_TRY(hipGetLastError());
     return PSF_OK;
 }
 
-static int read_status(void* ws, hipStream_t st) {
+int read_status(void* ws, hipStream_t st) {
     int s = 0;
     HIP_TRY(hipMemcpyAsync(&s, ws, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -252,13 +235,16 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
                        int64_t n_events, size_t* bytes) {
     (void)opts;
     if (!h || !table || !bytes || batch < 0 || n_events < 0) return PSF_EINVAL;
-    *bytes = ws_layout(h, table, batch, n_events).total;
+    *bytes = h->mode3d ? ws3_total(h, table, batch, n_events) : ws_layout(h, table, batch, n_events).total;
     return PSF_OK;
 }
 
 int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, float* table_dev, void* stream) {
     if (!h || !table_dev || n_rows < 1 || n_sub < 1 || !(step_deg > 0)) return PSF_EINVAL;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d) {
+        HIP_TRY(launch_table_3d(h->g, n_rows, n_sub, step_deg, table_dev, (hipStream_t)stream));
+        return PSF_OK;
+    }
     HIP_TRY(launch_table_2d(h->g, n_rows, n_sub, step_deg, table_dev, (hipStream_t)stream));
     return PSF_OK;
 }
@@ -269,7 +255,7 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d) return build_sysmat_3d(h, table, opts, ws, ws_bytes, csr, (hipStream_t)stream);
     if (ws_bytes < kWsHeader) return PSF_ESIZE;
     const int64_t vb = opts->vox_begin, ve = opts->vox_end > 0 ? opts->vox_end : h->n_vox;
     if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
@@ -370,7 +356,8 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d)
+        return project_fwd_3d(h, table, opts, x, batch, events, n_events, y, ws, ws_bytes, (hipStream_t)stream);
     const WsLayout L = ws_layout(h, table, batch, events ? n_events : 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
@@ -378,8 +365,8 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     double* y64 = at<double>(ws, L.y64);
     if ((st = fwd_bins(h, table, opts, x, batch, y64, ws, s))) return st;
     if (events) {
-        HIP_TRY(launch_lm_gather(y64, h->n_bins, events, n_events, batch, h->n_crystals, y, opts->accumulate,
-                                 (int*)ws, s));
+        HIP_TRY(launch_lm_gather(y64, nullptr, h->n_bins, events, n_events, batch, h->n_crystals, 1, y,
+                                 opts->accumulate, (int*)ws, s));
     } else {
         HIP_TRY(launch_finalize(y64, y, (int64_t)batch * h->n_bins, opts->accumulate, s));
     }
@@ -394,7 +381,10 @@ int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d) {
+        if (grad) return PSF_EUNSUPPORTED;  // the table gradient is built for the 2D ring
+        return project_adj_3d(h, table, opts, y, 0, batch, events, n_events, x, ws, ws_bytes, (hipStream_t)stream);
+    }
     const WsLayout L = ws_layout(h, table, batch, events ? n_events : 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
@@ -405,7 +395,7 @@ int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, con
         float* h32 = at<float>(ws, L.h32);
         const int64_t n = (int64_t)batch * h->n_bins;
         HIP_TRY(launch_zero_f64(h64, n, s));
-        HIP_TRY(launch_lm_scatter(y, n_events, events, batch, h->n_crystals, h->n_bins, h64, (int*)ws, s));
+        HIP_TRY(launch_lm_scatter(y, n_events, events, batch, h->n_crystals, 1, h->n_bins, h64, (int*)ws, s));
         HIP_TRY(launch_finalize(h64, h32, n, 0, s));
         ybins = h32;
     }
@@ -423,7 +413,8 @@ int psf_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts,
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d)
+        return project_adj_3d(h, table, opts, nullptr, 1, 1, nullptr, 0, s_dev, ws, ws_bytes, (hipStream_t)stream);
     if (ws_bytes < ws_layout(h, table, 1, 0).total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
     if ((st = zero_header(ws, s))) return st;
@@ -438,7 +429,9 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) return PSF_EUNSUPPORTED;
+    if (h->mode3d)
+        return lm_osem_3d(h, table, opts, events, n_events, randoms, sens, n_subsets, x_in, x_out, ws, ws_bytes,
+                          (hipStream_t)stream);
     const WsLayout L = ws_layout(h, table, 1, n_events);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
@@ -450,7 +443,7 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
     // q_e = a_e^T x + r  ->  h[bin] += 1 / q_e  ->  back = A^T h  ->  update
     if ((st = fwd_bins(h, table, opts, x_in, 1, y64, ws, s))) return st;
     HIP_TRY(launch_zero_f64(h64, h->n_bins, s));
-    HIP_TRY(launch_lm_ratio(y64, events, n_events, h->n_crystals, (double)randoms, h64, (int*)ws, s));
+    HIP_TRY(launch_lm_ratio(y64, nullptr, events, n_events, h->n_crystals, 1, (double)randoms, h64, (int*)ws, s));
     HIP_TRY(launch_finalize(h64, h32, h->n_bins, 0, s));
     if ((st = adj_bins(h, table, opts, h32, 0, 1, back, nullptr, nullptr, 0, ws, s))) return st;
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));

@@ -1,0 +1,309 @@
+// 3D-scanner halves of the C-ABI entry points: argument checks, workspace
+// carving and the batched launches of the cyl3d.hip kernels.
+#include <string.h>
+
+#include "api_internal.hpp"
+
+using namespace psf;
+
+namespace {
+
+constexpr int kBatchCsr = 16;     // voxels per batch of the matrix build (dense accumulators)
+constexpr int kBatchProj = 1024;  // voxels per batch of the projections
+constexpr int kCapSamples = 4096;
+constexpr int kCapPairs = 1024;
+constexpr int kCapSlots = 4096;
+
+Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
+    Cyl3D G;
+    G.R = h->g.n_blocks;
+    G.nc = h->g.n_cryst_t;
+    G.P = t->n_sub;
+    G.Nc = G.R * G.nc;
+    G.nseg = G.Nc * G.P;
+    G.n_rows = t->n_rows;
+    G.NR = h->g.n_cryst_z * h->g.n_block_rings;
+    G.nx = h->im.nx;
+    G.ny = h->im.ny;
+    G.nz = h->im.nz;
+    G.nvox = h->n_vox;
+    G.ntbins = (int64_t)G.Nc * (G.Nc - 1) / 2;
+    G.nbins = h->n_bins;
+    G.lam = h->g.pitch_t;
+    G.half_w = 0.5 * h->g.n_cryst_t * h->g.pitch_t;
+    G.rf = h->g.radius_face;
+    G.sigma = h->sigma;
+    G.step_deg = t->step_deg;
+    G.two_pi_R = 2.0 * M_PI / h->g.n_blocks;
+    G.sin_two_pi_R = sin(2.0 * M_PI / h->g.n_blocks);
+    G.lz = h->g.pitch_z;
+    G.z0 = -0.5 * G.NR * G.lz;
+    G.dx = h->im.dx;
+    G.dy = h->im.dy;
+    G.dz = h->im.dz;
+    G.cx = h->im.cx;
+    G.cy = h->im.cy;
+    G.cz = h->im.cz;
+    G.frames = h->frames_dev;
+    G.table = t->data;
+    G.precision = o ? o->precision : PSF_FP32;
+    return G;
+}
+
+int check3d(const psf_handle* h, const psf_table* t) {
+    if (t->n_sub > 4) return PSF_EUNSUPPORTED;  // tiles hold P^2 <= 16 sub-patches
+    const int64_t nseg = (int64_t)h->g.n_blocks * h->g.n_cryst_t * t->n_sub;
+    if (nseg >= 32768) return PSF_EUNSUPPORTED;
+    if (h->n_bins >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;  // bins are int32 CSR columns
+    return PSF_OK;
+}
+
+struct Ws3 {
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, x64, y32, h64, h32, back, total;
+    int bmax, bcsr, cap_slots;
+};
+
+Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
+    Ws3 L;
+    const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    const int64_t ntbins = Nc * (Nc - 1) / 2;
+    const size_t b = (size_t)(batch > 0 ? batch : 1);
+    L.bmax = (int)(h->n_vox < kBatchProj ? h->n_vox : kBatchProj);
+    L.bcsr = (int)(h->n_vox < kBatchCsr ? h->n_vox : kBatchCsr);
+    L.cap_slots = (int)(ntbins < kCapSlots ? ntbins : kCapSlots);
+    size_t off = kWsHeader;
+    L.counts = off;
+    off += align256(sizeof(int) * 3 * (size_t)L.bmax);
+    L.sidx = off;
+    off += align256(sizeof(int) * (size_t)L.bmax * kCapSamples);
+    L.sth = off;
+    off += align256(sizeof(double) * 2 * (size_t)L.bmax * kCapSamples);
+    L.pairs = off;
+    off += align256(sizeof(int4) * (size_t)L.bmax * kCapPairs);
+    L.slotmap = off;
+    off += align256(sizeof(int) * (size_t)L.bcsr * ntbins);
+    L.slot_tbin = off;
+    off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
+    L.dense = off;
+    off += align256(sizeof(double) * (size_t)L.bcsr * L.cap_slots * NR * NR);
+    L.x64 = off;
+    off += align256(sizeof(double) * b * (size_t)h->n_vox);
+    L.y32 = L.h64 = L.h32 = L.back = off;
+    if (n_events > 0) {
+        L.y32 = off;
+        off += align256(sizeof(float) * b * (size_t)h->n_bins);
+        L.h64 = off;
+        off += align256(sizeof(double) * b * (size_t)h->n_bins);
+        L.h32 = off;
+        off += align256(sizeof(float) * b * (size_t)h->n_bins);
+        L.back = off;
+        off += align256(sizeof(float) * (size_t)h->n_vox);
+    }
+    L.total = off;
+    return L;
+}
+
+template <class T>
+T* at3(void* ws, size_t off) {
+    return (T*)((char*)ws + off);
+}
+
+Scratch3D make_scratch(void* ws, const Ws3& L) {
+    Scratch3D S;
+    S.cap_samples = kCapSamples;
+    S.cap_pairs = kCapPairs;
+    S.cap_slots = L.cap_slots;
+    int* c = at3<int>(ws, L.counts);
+    S.n_samples = c;
+    S.n_pairs = c + L.bmax;
+    S.n_slots = c + 2 * L.bmax;
+    S.sidx = at3<int>(ws, L.sidx);
+    S.sth = at3<double>(ws, L.sth);
+    S.pairs = at3<int4>(ws, L.pairs);
+    S.slotmap = at3<int>(ws, L.slotmap);
+    S.slot_tbin = at3<int>(ws, L.slot_tbin);
+    S.dense = at3<double>(ws, L.dense);
+    return S;
+}
+
+// y[batch][n_bins] (FP32, accumulated with atomics) += A x over every voxel
+int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
+             void* ws, hipStream_t s) {
+    for (int b0 = 0; b0 < batch; b0 += 8) {
+        const int nb = batch - b0 < 8 ? batch - b0 : 8;
+        for (int64_t v0 = 0; v0 < h->n_vox; v0 += L.bmax) {
+            Args3D a;
+            memset(&a, 0, sizeof(a));
+            a.vox_begin = v0;
+            a.n_vox = (int)(h->n_vox - v0 < L.bmax ? h->n_vox - v0 : L.bmax);
+            a.batch = nb;
+            a.x = x + (int64_t)b0 * h->n_vox;
+            a.y = y + (int64_t)b0 * h->n_bins;
+            a.status = (int*)ws;
+            HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
+            HIP_TRY(launch_cyl3d_tiles(kModeFwd, G, S, a, s));
+        }
+    }
+    return PSF_OK;
+}
+
+// x64[batch][n_voxels] += A^T y (y FP32 [batch][n_bins], or all ones)
+int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
+             double* x64, void* ws, hipStream_t s) {
+    for (int b0 = 0; b0 < batch; b0 += 8) {
+        const int nb = batch - b0 < 8 ? batch - b0 : 8;
+        for (int64_t v0 = 0; v0 < h->n_vox; v0 += L.bmax) {
+            Args3D a;
+            memset(&a, 0, sizeof(a));
+            a.vox_begin = v0;
+            a.n_vox = (int)(h->n_vox - v0 < L.bmax ? h->n_vox - v0 : L.bmax);
+            a.batch = nb;
+            a.yin = ones ? nullptr : y + (int64_t)b0 * h->n_bins;
+            a.ones = ones;
+            a.x64 = x64 + (int64_t)b0 * h->n_vox;
+            a.status = (int*)ws;
+            HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
+            HIP_TRY(launch_cyl3d_tiles(kModeAdj, G, S, a, s));
+        }
+    }
+    return PSF_OK;
+}
+
+}  // namespace
+
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
+    return ws3_layout(h, t, batch, n_events).total;
+}
+
+int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
+                    hipStream_t s) {
+    int st = check3d(h, t);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, 1, 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
+    if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
+    if (!csr->row_ptr) return PSF_EINVAL;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    const int phase_fill = csr->col != nullptr;
+    csr->n_rows = ve - vb;
+    if ((st = zero_header(ws, s))) return st;
+    if (phase_fill) {
+        if (!csr->val) return PSF_EINVAL;
+        int64_t need = 0;
+        HIP_TRY(hipMemcpyAsync(&need, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (csr->nnz < need) {
+            csr->nnz = need;
+            return PSF_ESIZE;
+        }
+    }
+    // the dense accumulators start clean; the compaction leaves them clean
+    HIP_TRY(launch_zero_f64(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
+    for (int64_t v0 = vb; v0 < ve; v0 += L.bcsr) {
+        Args3D a;
+        memset(&a, 0, sizeof(a));
+        a.vox_begin = v0;
+        a.n_vox = (int)(ve - v0 < L.bcsr ? ve - v0 : L.bcsr);
+        a.row_base = v0 - vb;
+        a.batch = 1;
+        a.threshold = o->threshold;
+        a.row_ptr = csr->row_ptr;
+        a.col = csr->col;
+        a.val = csr->val;
+        a.status = (int*)ws;
+        HIP_TRY(launch_cyl3d_transaxial(G, S, a, 1, s));
+        HIP_TRY(launch_cyl3d_tiles(kModeCount, G, S, a, s));
+        HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, S, a, s));
+    }
+    if (!phase_fill) {
+        HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));
+        int64_t nnz = 0;
+        HIP_TRY(hipMemcpyAsync(&nnz, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        st = read_status(ws, s);
+        csr->nnz = nnz;
+        return st;
+    }
+    return read_status(ws, s);
+}
+
+int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* x, int batch,
+                   const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s) {
+    int st = check3d(h, t);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    if ((st = zero_header(ws, s))) return st;
+    const int64_t nout = (int64_t)batch * h->n_bins;
+    if (events) {
+        float* y32 = at3<float>(ws, L.y32);
+        HIP_TRY(launch_zero_f32(y32, nout, s));
+        if ((st = fwd3_all(h, G, S, L, x, batch, y32, ws, s))) return st;
+        const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+        HIP_TRY(launch_lm_gather(nullptr, y32, h->n_bins, events, n_events, batch, G.Nc, NR, y, o->accumulate,
+                                 (int*)ws, s));
+        return PSF_OK;
+    }
+    if (!o->accumulate) HIP_TRY(launch_zero_f32(y, nout, s));
+    return fwd3_all(h, G, S, L, x, batch, y, ws, s);
+}
+
+int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
+                   const int32_t* events, int64_t n_events, float* x, void* ws, size_t ws_bytes, hipStream_t s) {
+    int st = check3d(h, t);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    if ((st = zero_header(ws, s))) return st;
+    const float* ybins = y;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    if (events) {
+        double* h64 = at3<double>(ws, L.h64);
+        float* h32 = at3<float>(ws, L.h32);
+        const int64_t n = (int64_t)batch * h->n_bins;
+        HIP_TRY(launch_zero_f64(h64, n, s));
+        HIP_TRY(launch_lm_scatter(y, n_events, events, batch, G.Nc, NR, h->n_bins, h64, (int*)ws, s));
+        HIP_TRY(launch_finalize(h64, h32, n, 0, s));
+        ybins = h32;
+    }
+    double* x64 = at3<double>(ws, L.x64);
+    HIP_TRY(launch_zero_f64(x64, (int64_t)batch * h->n_vox, s));
+    if ((st = adj3_all(h, G, S, L, ybins, ones, batch, x64, ws, s))) return st;
+    HIP_TRY(launch_finalize(x64, x, (int64_t)batch * h->n_vox, ones ? 0 : o->accumulate, s));
+    return PSF_OK;
+}
+
+int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
+               float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
+               size_t ws_bytes, hipStream_t s) {
+    int st = check3d(h, t);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, 1, n_events);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    if ((st = zero_header(ws, s))) return st;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    float* y32 = at3<float>(ws, L.y32);
+    double* h64 = at3<double>(ws, L.h64);
+    float* h32 = at3<float>(ws, L.h32);
+    float* back = at3<float>(ws, L.back);
+    double* x64 = at3<double>(ws, L.x64);
+    // q_e = a_e^T x + r  ->  h[bin] += 1 / q_e  ->  back = A^T h  ->  update
+    HIP_TRY(launch_zero_f32(y32, h->n_bins, s));
+    if ((st = fwd3_all(h, G, S, L, x_in, 1, y32, ws, s))) return st;
+    HIP_TRY(launch_zero_f64(h64, h->n_bins, s));
+    HIP_TRY(launch_lm_ratio(nullptr, y32, events, n_events, G.Nc, NR, (double)randoms, h64, (int*)ws, s));
+    HIP_TRY(launch_finalize(h64, h32, h->n_bins, 0, s));
+    HIP_TRY(launch_zero_f64(x64, h->n_vox, s));
+    if ((st = adj3_all(h, G, S, L, h32, 0, 1, x64, ws, s))) return st;
+    HIP_TRY(launch_finalize(x64, back, h->n_vox, 0, s));
+    HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
+    return PSF_OK;
+}

@@ -1,0 +1,49 @@
+// Host-side internals shared by the C-ABI translation units (not part of the ABI).
+#pragma once
+
+#include <math.h>
+
+#include "common.hpp"
+
+struct psf_handle {
+    psf_geometry g;
+    psf_image im;
+    int mode3d;
+    int device;
+    int64_t n_crystals, n_bins, n_vox;
+    double sigma;
+    double* frames_dev;  // [R][2] cos, sin of each block's outward normal
+};
+
+namespace psf {
+extern thread_local int g_last_hip;
+}
+
+#define HIP_TRY(expr)                         \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) {               \
+            psf::g_last_hip = (int)e_;        \
+            return PSF_EHIP;                  \
+        }                                     \
+    } while (0)
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t table_elems(const psf_handle* h, const psf_table* t);
+int check_table(const psf_handle* h, const psf_table* t);
+int check_opts(const psf_opts* o);
+int zero_header(void* ws, hipStream_t st);
+int read_status(void* ws, hipStream_t st);
+
+// 3D entry points (api3d.hip)
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events);
+int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
+                    hipStream_t s);
+int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* x, int batch,
+                   const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s);
+int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
+                   const int32_t* events, int64_t n_events, float* x, void* ws, size_t ws_bytes, hipStream_t s);
+int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
+               float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
+               size_t ws_bytes, hipStream_t s);

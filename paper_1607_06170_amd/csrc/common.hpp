@@ -34,6 +34,49 @@ struct Ring2D {
     int precision;
 };
 
+// Everything a 3D-scanner kernel needs, passed by value.  Crystal (g, r):
+// transaxial index g = b * nc + c, ring r; axial sub-position q = r * P + pz.
+struct Cyl3D {
+    int R, nc, P, Nc, nseg, n_rows, NR, nx, ny, nz;
+    int64_t nvox, ntbins, nbins;
+    double lam, half_w, rf, sigma, step_deg, two_pi_R, sin_two_pi_R, lz, z0;
+    double dx, dy, dz, cx, cy, cz;
+    const double* frames;
+    const float* table;  // [n_rows][n_rows][P][P][5][5]
+    int precision;
+};
+
+// Per-voxel scratch of the 3D kernels (a batch of B voxels at a time).
+struct Scratch3D {
+    int cap_samples, cap_pairs, cap_slots;
+    int* n_samples;    // [B]
+    int* n_pairs;      // [B]
+    int* n_slots;      // [B]
+    int* sidx;         // [B][cap_samples]  s1 << 16 | s2
+    double* sth;       // [B][cap_samples][2]  direction interval of the sample
+    int4* pairs;       // [B][cap_pairs]  g1, g2, first sample, sample count
+    int* slotmap;      // [B][ntbins]  transaxial bin -> slot (-1: none)
+    int* slot_tbin;    // [B][cap_slots]
+    double* dense;     // [B][cap_slots][NR * NR]
+};
+
+struct Args3D {
+    int64_t vox_begin;  // first voxel of this batch
+    int n_vox;          // voxels in this batch
+    int64_t row_base;   // CSR row of the batch's first voxel
+    int batch;
+    double threshold;
+    const float* x;     // [batch][nvox]  forward input
+    float* y;           // [batch][nbins] forward output (FP32 atomics)
+    const float* yin;   // [batch][nbins] adjoint input
+    double* x64;        // [batch][nvox]  adjoint accumulator
+    int64_t* row_ptr;
+    int32_t* col;
+    float* val;
+    int* status;
+    int ones;           // adjoint with y == 1 (sensitivity)
+};
+
 // Device view of the handle (host struct defined in api.cpp).
 struct HandleView {
     psf_geometry g;
@@ -70,15 +113,25 @@ hipError_t launch_scan_rowptr(int64_t* row_ptr, int64_t n, hipStream_t st);
 hipError_t launch_finalize(const double* src, float* dst, int64_t n, int accumulate, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 size_t voxel2d_smem_bytes(const Ring2D& G, int mode);
-hipError_t launch_lm_gather(const double* y64, int64_t nbins, const int32_t* ev, int64_t ne, int batch, int64_t N,
-                            float* out, int accumulate, int* status, hipStream_t st);
-hipError_t launch_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t N, int64_t nbins,
-                             double* hist, int* status, hipStream_t st);
-hipError_t launch_lm_ratio(const double* y64, const int32_t* ev, int64_t ne, int64_t N, double randoms, double* hist,
-                           int* status, hipStream_t st);
+hipError_t launch_lm_gather(const double* y64, const float* y32, int64_t nbins, const int32_t* ev, int64_t ne,
+                            int batch, int64_t Nc, int64_t NR, float* out, int accumulate, int* status,
+                            hipStream_t st);
+hipError_t launch_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t Nc, int64_t NR,
+                             int64_t nbins, double* hist, int* status, hipStream_t st);
+hipError_t launch_lm_ratio(const double* y64, const float* y32, const int32_t* ev, int64_t ne, int64_t Nc, int64_t NR,
+                           double randoms, double* hist, int* status, hipStream_t st);
 hipError_t launch_lm_update(const float* x_in, const float* back, const float* sens, int n_subsets, int64_t nvox,
                             float* x_out, hipStream_t st);
 
 enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad = 4 };
+
+// 3D launchers (cyl3d.hip, table3d.hip)
+hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st);
+hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
+                                   hipStream_t st);
+hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+constexpr int kStatScratch = 16;  // a per-voxel scratch capacity was exceeded
 
 }  // namespace psf

@@ -1,0 +1,737 @@
+// 3D scanner (block rings): system matrix and on-the-fly projections.
+//
+// The paper builds the 2D matrix and names the 3D one as its next step
+// (Sec 4); this is that extension of Sec 2, voxel by voxel:
+//   K1 transaxial  one workgroup per voxel.  The 2D homogenization sweep of
+//                  Sec 2.3 over the transaxial sub-segments (Eq.11) gives the
+//                  line bundles (s1, s2, direction interval), grouped into
+//                  crystal pairs (g1, g2).  For the matrix build it also lists
+//                  the voxel's transaxial bins (sorted) and maps each to a slot.
+//   K2 tiles       one wavefront per (crystal pair, ring r1) task.  For each
+//                  ring r2 the lines reach: the P^2 x P^2 weights W3 between
+//                  sub-patches (solid angle of the lines, in closed form), the
+//                  response rows U, V (P^2 x 25, Eq.2-7 with the transaxial
+//                  two-block remap), and the tile T = U^T (W V) (Eq.10, 12),
+//                  then emission: forward atomics, adjoint gathers, or FP64
+//                  atomics into the voxel's dense slot x ring-pair accumulator.
+//   K3 compact     ordered compaction of the accumulator into CSR rows.
+//
+// Bins: bin = tbin(g_i, g_j) * NR^2 + r_i * NR + r_j with g_i < g_j (r_i the
+// ring of crystal g_i): the transaxial pair major, then the ring pair.
+//
+// The homogenization weight of the lines from sub-patch (s1, q1) to (s2, q2)
+// is (1/2pi) * integral over theta of [S(T_hi) - S(T_lo)]^+, S(T) = T/sqrt(1+T^2)
+// the sine of the elevation.  Every slope limit has the form A cos(theta - psi),
+// and S(A cos u) has the antiderivative asin(A sin u / sqrt(1 + A^2)); the
+// integral is exact once the interval is cut where the binding limits switch
+// (roots of p cos theta + q sin theta = 0).
+#include "common.hpp"
+
+namespace psf {
+
+constexpr double kEpsW3 = 1e-14;  // weights at or below this fraction of the sphere are empty
+constexpr int kMaxK = 16;         // P^2 sub-patches per crystal face (P <= 4)
+
+__device__ __forceinline__ double wrap2pi3(double a) {
+    while (a >= 2.0 * kPi) a -= 2.0 * kPi;
+    while (a < 0.0) a += 2.0 * kPi;
+    return a;
+}
+
+__device__ __forceinline__ double wrappm3(double a) {
+    while (a > kPi) a -= 2.0 * kPi;
+    while (a <= -kPi) a += 2.0 * kPi;
+    return a;
+}
+
+__device__ __forceinline__ double bangle3(const Cyl3D& G, int b, int k, double vx, double vy) {
+    const double c = G.frames[2 * b], s = G.frames[2 * b + 1];
+    const double xi = -G.half_w + k * (G.lam / G.P);
+    return atan2(G.rf * s + xi * c - vy, G.rf * c - xi * s - vx);
+}
+
+__device__ __forceinline__ int64_t tbin_of(int64_t gi, int64_t gj, int64_t Nc) {
+    return gi * Nc - gi * (gi + 1) / 2 + (gj - gi - 1);
+}
+
+__device__ __forceinline__ void voxel_xyz(const Cyl3D& G, int64_t v, double& x, double& y, double& z) {
+    const int64_t ix = v % G.nx, iy = (v / G.nx) % G.ny, iz = v / ((int64_t)G.nx * G.ny);
+    x = (ix - 0.5 * (G.nx - 1)) * G.dx + G.cx;
+    y = (iy - 0.5 * (G.ny - 1)) * G.dy + G.cy;
+    z = (iz - 0.5 * (G.nz - 1)) * G.dz + G.cz;
+}
+
+// ---------------------------------------------------------------------------
+// homogenization weight on the sphere, closed form
+// ---------------------------------------------------------------------------
+
+struct W3Geo {
+    double c1, s1, D1;  // photon 1's face: normal (c1, s1), distance D1 from the voxel
+    double c2, s2, D2;  // photon 2's face
+};
+
+__device__ double w3_closed(const W3Geo& g, double zv, double z1lo, double z1hi, double z2lo, double z2hi, double ta,
+                            double tb) {
+    // slope limits T_k(theta) = A_k cos(theta - psi_k): 0 T1lo, 1 T1hi, 2 T2lo, 3 T2hi
+    double A[4], C[4], S[4];
+    A[0] = (z1lo - zv) / g.D1;
+    A[1] = (z1hi - zv) / g.D1;
+    C[0] = C[1] = g.c1;
+    S[0] = S[1] = g.s1;
+    A[2] = (zv - z2hi) / g.D2;
+    A[3] = (zv - z2lo) / g.D2;
+    C[2] = C[3] = -g.c2;  // photon 2 travels along theta + pi
+    S[2] = S[3] = -g.s2;
+    double cut[6];
+    int n = 0;
+    cut[n++] = ta;
+    const double tm = 0.5 * (ta + tb);
+    const int ia[4] = {1, 0, 1, 3}, ib[4] = {3, 2, 2, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = ia[k], j = ib[k];
+        const double p = A[i] * C[i] - A[j] * C[j];
+        const double q = A[i] * S[i] - A[j] * S[j];
+        if (p == 0.0 && q == 0.0) continue;
+        const double th0 = atan2(-p, q);
+        const double r = th0 + rint((tm - th0) / kPi) * kPi;
+        if (r > ta && r < tb) cut[n++] = r;
+    }
+    cut[n++] = tb;
+    for (int i = 1; i < n; ++i) {  // insertion sort (n <= 6)
+        const double v = cut[i];
+        int j = i - 1;
+        while (j >= 0 && cut[j] > v) {
+            cut[j + 1] = cut[j];
+            --j;
+        }
+        cut[j + 1] = v;
+    }
+    double inv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inv[k] = 1.0 / sqrt(1.0 + A[k] * A[k]);
+    double sum = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        const double a = cut[i], b = cut[i + 1];
+        if (!(b > a)) continue;
+        const double m = 0.5 * (a + b), cm = cos(m), sm = sin(m);
+        double T[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) T[k] = A[k] * (cm * C[k] + sm * S[k]);
+        const int hi = T[1] < T[3] ? 1 : 3;
+        const int lo = T[0] > T[2] ? 0 : 2;
+        if (!(T[hi] > T[lo])) continue;
+        const double ca = cos(a), sa = sin(a), cb = cos(b), sb = sin(b);
+        // F(theta) = asin(A sin(theta - psi) / sqrt(1 + A^2)), sin(theta - psi) = sin th C - cos th S
+        const double fhb = asin(A[hi] * (sb * C[hi] - cb * S[hi]) * inv[hi]);
+        const double fha = asin(A[hi] * (sa * C[hi] - ca * S[hi]) * inv[hi]);
+        const double flb = asin(A[lo] * (sb * C[lo] - cb * S[lo]) * inv[lo]);
+        const double fla = asin(A[lo] * (sa * C[lo] - ca * S[lo]) * inv[lo]);
+        sum += (fhb - fha) - (flb - fla);
+    }
+    return sum / (2.0 * kPi);
+}
+
+// ---------------------------------------------------------------------------
+// response row of a sub-patch (3D form of Eq.2-7)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t tab3_idx(int nr, int P, int rt, int rz, int pt, int pz, int at, int az) {
+    return (((((int64_t)rt * nr + rz) * P + pt) * P + pz) * kNb + (at + 2)) * kNb + (az + 2);
+}
+
+// out[(a_t+2)*5 + (a_z+2)]: response of the crystal at transaxial offset a_t
+// and ring r + a_z to a photon entering sub-patch (g, pt; r, pz) from (cx, cy, cz).
+// Returns 1 when an angle row beyond the table had to be clamped.
+__device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, int pt, int r, int pz, float* out) {
+    int range = 0;
+    const int b = g / G.nc, c = g - b * G.nc, P = G.P, nr = G.n_rows;
+    const double cs = G.frames[2 * b], sn = G.frames[2 * b + 1];
+    const double xi_m = -G.half_w + (c + (pt + 0.5) / P) * G.lam;
+    const double z_m = G.z0 + (r + (pz + 0.5) / P) * G.lz;
+    const double D = G.rf - (cs * cx + sn * cy);
+    const double tan_t = (xi_m - (-sn * cx + cs * cy)) / D;
+    const double tan_z = (z_m - cz) / D;
+    const double at = atan(tan_t), az = atan(tan_z);
+    const bool mt = at < 0.0, mz = az < 0.0;
+    const double aat = fabs(at), aaz = fabs(az);
+    int row_t = (int)floor(aat * 180.0 / kPi / G.step_deg + 0.5);
+    int row_z = (int)floor(aaz * 180.0 / kPi / G.step_deg + 0.5);
+    if (row_t > nr - 1) { range = 1; row_t = nr - 1; }
+    if (row_z > nr - 1) { range = 1; row_z = nr - 1; }
+    const int cm = mt ? G.nc - 1 - c : c;
+    const int ptm = mt ? P - 1 - pt : pt;
+    const int pzm = mz ? P - 1 - pz : pz;
+    const double nu = mt ? xi_m + G.half_w : G.half_w - xi_m;
+    bool remap = false;
+    int kv = 0, pt1 = 0, pz1 = 0, dr = 0, row_bt = 0, row_bz = 0;
+    const double beta = aat - G.two_pi_R;
+    if (beta > 0.0 && cm + 2 >= G.nc) {
+        const double ca = cos(aat), cb = cos(beta);
+        const double ap1 = G.sigma + ca / cb * (G.sigma + nu);
+        const double n = ap1 / G.lam;
+        kv = (int)ceil(n) - 1;
+        pt1 = (int)floor(((kv + 1) - n) * P);
+        const double atz = fabs(tan_z);
+        const double tzb = atz * ca / cb;
+        const double ell = (G.sigma + nu) * G.sin_two_pi_R / cb;
+        const double u = (pzm + 0.5) * G.lz / P + ell * atz * ca;
+        dr = (int)floor(u / G.lz);
+        const double uz1 = u - dr * G.lz;
+        pz1 = (int)floor(uz1 * P / G.lz);
+        if (pz1 > P - 1) pz1 = P - 1;
+        row_bt = (int)floor(beta * 180.0 / kPi / G.step_deg + 0.5);
+        row_bz = (int)floor(atan(tzb) * 180.0 / kPi / G.step_deg + 0.5);
+        if (row_bt > nr - 1) { range = 1; row_bt = nr - 1; }
+        if (row_bz > nr - 1) { range = 1; row_bz = nr - 1; }
+        remap = true;
+    }
+    for (int amt = -2; amt <= 2; ++amt) {
+        const int a_t = mt ? -amt : amt, cc = cm + amt;
+        for (int amz = -2; amz <= 2; ++amz) {
+            const int a_z = mz ? -amz : amz, ring = r + a_z;
+            float v = 0.0f;
+            if (ring >= 0 && ring < G.NR) {
+                if (cc >= 0 && cc < G.nc) {
+                    v = G.table[tab3_idx(nr, P, row_t, row_z, ptm, pzm, amt, amz)];
+                } else if (cc >= G.nc && remap) {
+                    const int idx = kv + 1 + (cc - G.nc), az1 = amz - dr;
+                    if (idx <= 2 && az1 >= -2 && az1 <= 2) v = G.table[tab3_idx(nr, P, row_bt, row_bz, pt1, pz1, idx, az1)];
+                }
+            }
+            out[(a_t + 2) * kNb + (a_z + 2)] = v;
+        }
+    }
+    return range;
+}
+
+// ---------------------------------------------------------------------------
+// K1: transaxial sweep, crystal pairs, transaxial bins
+// ---------------------------------------------------------------------------
+
+constexpr int kBlockT = 512;
+
+__global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D S, Args3D A, int want_slots) {
+    extern __shared__ __align__(16) unsigned char smem3[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int vb = blockIdx.x;
+    const int64_t v = A.vox_begin + vb;
+    const int M1 = G.nc * G.P + 1, spb = G.nc * G.P;
+    double* th = (double*)smem3;                    // [R * M1]
+    double* unw = th + G.R * M1;                    // [nseg]
+    int* cnt = (int*)(unw + G.nseg);                // [nseg + 1]
+    __shared__ int red[kBlockT / 64 + 1];
+    __shared__ int s_total;
+    double vx, vy, vz;
+    voxel_xyz(G, v, vx, vy, vz);
+    for (int i = tid; i < G.R * M1; i += bs) {
+        const int b = i / M1, k = i - b * M1;
+        th[i] = bangle3(G, b, k, vx, vy);
+    }
+    __syncthreads();
+    const double lo0 = th[0];
+    for (int s = tid; s < G.nseg; s += bs) {
+        const int b = s / spb, k = s - b * spb;
+        unw[s] = lo0 + wrap2pi3(th[b * M1 + k] - lo0);
+    }
+    __syncthreads();
+    int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
+    double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
+    // two passes over the sweep: count the bundles of each s1, then write them
+    // in (s1, s2) order at the scanned offsets
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int s1 = tid; s1 < G.nseg; s1 += bs) {
+            const int b1 = s1 / spb, k1 = s1 - b1 * spb;
+            const double lo1 = th[b1 * M1 + k1];
+            const double len1 = wrap2pi3(th[b1 * M1 + k1 + 1] - lo1);
+            double x = unw[s1] + kPi;
+            if (x >= lo0 + 2.0 * kPi) x -= 2.0 * kPi;
+            int lo = 0, hi = G.nseg;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (unw[mid] <= x) lo = mid + 1;
+                else hi = mid;
+            }
+            const int j0 = lo > 0 ? lo - 1 : 0;
+            int n = 0, out = pass ? cnt[s1] : 0;
+            for (int c = 0; c < G.nseg; ++c) {
+                const int jj = j0 + c;
+                const int s2 = jj >= G.nseg ? jj - G.nseg : jj;
+                const double base = unw[s2] + (jj >= G.nseg ? 2.0 * kPi : 0.0);
+                if (c > 0 && base >= x + len1) break;
+                if (s2 <= s1) continue;
+                const int b2 = s2 / spb, k2 = s2 - b2 * spb;
+                const double lo2 = th[b2 * M1 + k2];
+                const double len2 = wrap2pi3(th[b2 * M1 + k2 + 1] - lo2);
+                const double d = wrappm3(lo2 + kPi - lo1);
+                const double ov = fmin(len1, d + len2) - fmax(0.0, d);
+                if (!(ov > kEpsOverlap)) continue;
+                if (pass && out < S.cap_samples) {
+                    sidx[out] = (s1 << 16) | s2;
+                    sth[2 * out] = lo1 + fmax(0.0, d);
+                    sth[2 * out + 1] = lo1 + fmin(len1, d + len2);
+                }
+                ++n;
+                ++out;
+            }
+            if (!pass) cnt[s1] = n;
+        }
+        __syncthreads();
+        if (!pass) {  // exclusive scan of cnt (serial over chunks of the block)
+            if (tid == 0) {
+                int run = 0;
+                for (int s = 0; s < G.nseg; ++s) {
+                    const int c = cnt[s];
+                    cnt[s] = run;
+                    run += c;
+                }
+                cnt[G.nseg] = run;
+                s_total = run;
+            }
+            __syncthreads();
+        }
+    }
+    const int ns = s_total;
+    if (ns > S.cap_samples) {
+        if (tid == 0) atomicOr(A.status, kStatScratch);
+        if (tid == 0) { S.n_samples[vb] = 0; S.n_pairs[vb] = 0; if (S.n_slots) S.n_slots[vb] = 0; }
+        return;
+    }
+    // group each g1's bundles by g2 (insertion sort of <= P * few entries)
+    for (int g1 = tid; g1 < G.Nc; g1 += bs) {
+        const int a = cnt[g1 * G.P], e = cnt[g1 * G.P + G.P];
+        for (int i = a + 1; i < e; ++i) {
+            const int key = sidx[i];
+            const double t0 = sth[2 * i], t1 = sth[2 * i + 1];
+            const int k2 = (key & 0xffff) / G.P;
+            int j = i - 1;
+            while (j >= a && (sidx[j] & 0xffff) / G.P > k2) {
+                sidx[j + 1] = sidx[j];
+                sth[2 * (j + 1)] = sth[2 * j];
+                sth[2 * (j + 1) + 1] = sth[2 * j + 1];
+                --j;
+            }
+            sidx[j + 1] = key;
+            sth[2 * (j + 1)] = t0;
+            sth[2 * (j + 1) + 1] = t1;
+        }
+    }
+    __syncthreads();
+    // pairs: runs of equal (g1, g2).  Count per g1, scan, write.
+    int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
+    int* pc = cnt;  // reuse: per-g1 pair counts live past the sample offsets
+    __syncthreads();
+    __shared__ int s_np;
+    // count
+    int* gcnt = (int*)(unw);  // unw is free now: [Nc] ints
+    for (int g1 = tid; g1 < G.Nc; g1 += bs) {
+        const int a = pc[g1 * G.P], e = pc[g1 * G.P + G.P];
+        int n = 0, last = -1;
+        for (int i = a; i < e; ++i) {
+            const int g2 = (sidx[i] & 0xffff) / G.P;
+            if (g2 != last) { ++n; last = g2; }
+        }
+        gcnt[g1] = n;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int g = 0; g < G.Nc; ++g) {
+            const int c = gcnt[g];
+            gcnt[g] = run;
+            run += c;
+        }
+        s_np = run;
+    }
+    __syncthreads();
+    const int np = s_np;
+    if (np > S.cap_pairs) {
+        if (tid == 0) { atomicOr(A.status, kStatScratch); S.n_samples[vb] = 0; S.n_pairs[vb] = 0; if (S.n_slots) S.n_slots[vb] = 0; }
+        return;
+    }
+    for (int g1 = tid; g1 < G.Nc; g1 += bs) {
+        const int a = pc[g1 * G.P], e = pc[g1 * G.P + G.P];
+        int o = gcnt[g1], last = -1, first = a;
+        for (int i = a; i <= e; ++i) {
+            const int g2 = i < e ? (sidx[i] & 0xffff) / G.P : -2;
+            if (g2 != last) {
+                if (last >= 0) pairs[o++] = make_int4(g1, last, first, i - first);
+                last = g2;
+                first = i;
+            }
+        }
+    }
+    if (tid == 0) {
+        S.n_samples[vb] = ns;
+        S.n_pairs[vb] = np;
+    }
+    if (!want_slots) return;
+    __syncthreads();
+    // transaxial bins of this voxel: mark, then scan in bin order into slots
+    int* smap = S.slotmap + (int64_t)vb * G.ntbins;
+    for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
+    __syncthreads();
+    for (int p = tid; p < np; p += bs) {
+        const int4 pr = pairs[p];
+        for (int at = -2; at <= 2; ++at)
+            for (int bt = -2; bt <= 2; ++bt) {
+                int gi = pr.x + at, gj = pr.y + bt;
+                gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
+                gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
+                if (gi == gj) continue;
+                const int lo_ = gi < gj ? gi : gj, hi_ = gi < gj ? gj : gi;
+                smap[tbin_of(lo_, hi_, G.Nc)] = 1;
+            }
+    }
+    __syncthreads();
+    // block scan over the marks (chunks of bs), writing slot indices
+    int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
+    __shared__ int s_run;
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
+    for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
+        const int64_t i = b0 + tid;
+        const int mk = i < G.ntbins ? smap[i] : 0;
+        const unsigned long long m = __ballot(mk != 0);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) red[wid] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            off += w < wid ? red[w] : 0;
+            tot += red[w];
+        }
+        const int run = s_run;
+        if (i < G.ntbins) {
+            if (mk) {
+                const int slot = run + off + pre;
+                smap[i] = slot < S.cap_slots ? slot : -1;
+                if (slot < S.cap_slots) stb[slot] = (int)i;
+            } else {
+                smap[i] = -1;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_run = run + tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int nsl = s_run;
+        if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
+        S.n_slots[vb] = nsl < S.cap_slots ? nsl : S.cap_slots;
+    }
+}
+
+size_t cyl3d_transaxial_smem(const Cyl3D& G) {
+    return sizeof(double) * (size_t)(G.R * (G.nc * G.P + 1) + G.nseg) + sizeof(int) * (size_t)(G.nseg + 1) + 64;
+}
+
+hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
+                                   hipStream_t st) {
+    if (a.n_vox <= 0) return hipSuccess;
+    const size_t smem = cyl3d_transaxial_smem(G);
+    hipFuncSetAttribute((const void*)k_cyl3d_transaxial, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    hipLaunchKernelGGL(k_cyl3d_transaxial, dim3(a.n_vox), dim3(kBlockT), smem, st, G, S, a, want_slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K2: tiles
+// ---------------------------------------------------------------------------
+
+constexpr int kWavesT = 4;
+constexpr int kPairsPerWG = 8;
+
+struct WaveLds {
+    float W[kMaxK][kMaxK + 1];
+    float U[kMaxK][25];
+    float V[kMaxK][25];
+    float X[kMaxK][25];
+    double ta[kMaxK], tb[kMaxK];
+    int pt1[kMaxK], pt2[kMaxK];
+    int urange[2 * kMaxK];
+};
+
+__device__ __forceinline__ float bf16r(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D S, Args3D A) {
+    __shared__ WaveLds wl[kWavesT];
+    __shared__ double xacc[kWavesT][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int vb = blockIdx.y;
+    const int64_t v = A.vox_begin + vb;
+    WaveLds& L = wl[wid];
+    const int np = S.n_pairs[vb];
+    const int pair0 = blockIdx.x * kPairsPerWG;
+    if (pair0 >= np) return;
+    const int pair1 = min(np, pair0 + kPairsPerWG);
+    const int P = G.P, K = P * P;
+    const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
+    const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
+    const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
+    double vx, vy, vz;
+    voxel_xyz(G, v, vx, vy, vz);
+    double xv[8];
+    double acc[8];
+    const int nb = A.batch < 8 ? A.batch : 8;
+    for (int bb = 0; bb < 8; ++bb) {
+        acc[bb] = 0.0;
+        xv[bb] = 0.0;
+    }
+    if (MODE == kModeFwd)
+        for (int bb = 0; bb < nb; ++bb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
+    const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
+    double* dense = (MODE == kModeCount || MODE == kModeFill)
+                        ? S.dense + (int64_t)vb * S.cap_slots * G.NR * G.NR : nullptr;
+    int flag = 0;
+    const int ntask = (pair1 - pair0) * G.NR;
+    for (int t = wid; t < ntask; t += kWavesT) {
+        const int4 pr = pairs[pair0 + t / G.NR];
+        const int r1 = t % G.NR;
+        const int g1 = pr.x, g2 = pr.y, nsmp = pr.w;
+        if (nsmp > kMaxK) { flag |= kStatScratch; continue; }
+        if (lane < nsmp) {
+            const int key = sidx[pr.z + lane];
+            L.pt1[lane] = (key >> 16) - g1 * P;
+            L.pt2[lane] = (key & 0xffff) - g2 * P;
+            L.ta[lane] = sth[2 * (pr.z + lane)];
+            L.tb[lane] = sth[2 * (pr.z + lane) + 1];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int b1 = g1 / G.nc, b2 = g2 / G.nc;
+        W3Geo wg;
+        wg.c1 = G.frames[2 * b1];
+        wg.s1 = G.frames[2 * b1 + 1];
+        wg.c2 = G.frames[2 * b2];
+        wg.s2 = G.frames[2 * b2 + 1];
+        wg.D1 = G.rf - (wg.c1 * vx + wg.s1 * vy);
+        wg.D2 = G.rf - (wg.c2 * vx + wg.s2 * vy);
+        // rings r2 reached from ring r1: photon 2 lands at zv - (d2/d1)(z1 - zv)
+        double zmin = 1e300, zmax = -1e300;
+        for (int k = 0; k < nsmp; ++k) {
+            for (int e = 0; e < 2; ++e) {
+                const double th_ = e ? L.tb[k] : L.ta[k];
+                const double ct = cos(th_), st = sin(th_);
+                const double ratio = (wg.D2 / wg.D1) * (ct * wg.c1 + st * wg.s1) / -(ct * wg.c2 + st * wg.s2);
+                for (int f = 0; f < 2; ++f) {
+                    const double z1 = G.z0 + (r1 + f) * G.lz;
+                    const double z2 = vz - ratio * (z1 - vz);
+                    zmin = fmin(zmin, z2);
+                    zmax = fmax(zmax, z2);
+                }
+            }
+        }
+        int r2a = (int)floor((zmin - G.z0) / G.lz) - 1, r2b = (int)floor((zmax - G.z0) / G.lz) + 1;
+        r2a = r2a < 0 ? 0 : r2a;
+        r2b = r2b > G.NR - 1 ? G.NR - 1 : r2b;
+        for (int r2 = r2a; r2 <= r2b; ++r2) {
+            // W: P^2 x P^2 weights between sub-patches of (g1, r1) and (g2, r2)
+            for (int e = lane; e < kMaxK * kMaxK; e += 64) L.W[e >> 4][e & 15] = 0.0f;
+            __builtin_amdgcn_wave_barrier();
+            int any = 0;
+            for (int e = lane; e < nsmp * K; e += 64) {
+                const int k = e / K, pz1 = (e / P) % P, pz2 = e % P;
+                const double z1lo = G.z0 + (r1 + (double)pz1 / P) * G.lz;
+                const double z1hi = G.z0 + (r1 + (double)(pz1 + 1) / P) * G.lz;
+                const double z2lo = G.z0 + (r2 + (double)pz2 / P) * G.lz;
+                const double z2hi = G.z0 + (r2 + (double)(pz2 + 1) / P) * G.lz;
+                const double w = w3_closed(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ta[k], L.tb[k]);
+                if (w > kEpsW3) {
+                    L.W[L.pt1[k] * P + pz1][L.pt2[k] * P + pz2] = (float)w;
+                    any = 1;
+                }
+            }
+            if (!__any(any)) continue;
+            __builtin_amdgcn_wave_barrier();
+            // response rows: lanes 0..K-1 -> U (g1, r1), lanes 32..32+K-1 -> V (g2, r2)
+            if (lane < K) {
+                L.urange[lane] = uv_row3(G, vx, vy, vz, g1, lane / P, r1, lane % P, L.U[lane]);
+            } else if (lane >= 32 && lane < 32 + K) {
+                const int l = lane - 32;
+                L.urange[kMaxK + l] = uv_row3(G, vx, vy, vz, g2, l / P, r2, l % P, L.V[l]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // range errors count only for rows that carry weight
+            if (lane < K) {
+                float rs = 0.0f, cs_ = 0.0f;
+                for (int q = 0; q < K; ++q) {
+                    rs += L.W[lane][q];
+                    cs_ += L.W[q][lane];
+                }
+                if ((rs != 0.0f && L.urange[lane]) || (cs_ != 0.0f && L.urange[kMaxK + lane])) flag |= kStatRange;
+            }
+            // X = W V (K x 25)
+            for (int e = lane; e < K * 25; e += 64) {
+                const int p = e / 25, bq = e % 25;
+                float s = 0.0f;
+                for (int q = 0; q < K; ++q) s = fmaf(L.W[p][q], L.V[q][bq], s);
+                L.X[p][bq] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // T = U^T X (25 x 25), emitted entry by entry
+            for (int e = lane; e < 625; e += 64) {
+                const int a = e / 25, bq = e % 25;
+                float t = 0.0f;
+                if (G.precision == PSF_FP32) {
+                    for (int p = 0; p < K; ++p) t = fmaf(L.U[p][a], L.X[p][bq], t);
+                } else if (G.precision == PSF_BF16) {
+                    for (int p = 0; p < K; ++p) t = fmaf(bf16r(L.U[p][a]), bf16r(L.X[p][bq]), t);
+                } else {
+                    for (int p = 0; p < K; ++p) {
+                        const float uh = bf16r(L.U[p][a]), ul = bf16r(L.U[p][a] - uh);
+                        const float xh = bf16r(L.X[p][bq]), xl = bf16r(L.X[p][bq] - xh);
+                        t = fmaf(uh, xh, fmaf(uh, xl, fmaf(ul, xh, t)));
+                    }
+                }
+                if (t == 0.0f) continue;
+                const int at = a / 5 - 2, az = a % 5 - 2, bt = bq / 5 - 2, bz = bq % 5 - 2;
+                const int ra = r1 + az, rb = r2 + bz;
+                if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) continue;
+                int ga = g1 + at, gb = g2 + bt;
+                ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                if (ga == gb) continue;
+                const bool sw = ga > gb;
+                const int gi = sw ? gb : ga, gj = sw ? ga : gb, ri = sw ? rb : ra, rj = sw ? ra : rb;
+                const int64_t tb_ = tbin_of(gi, gj, G.Nc);
+                if (MODE == kModeFwd) {
+                    const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
+                    for (int bb = 0; bb < nb; ++bb)
+                        if (xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
+                } else if (MODE == kModeAdj) {
+                    const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
+                    for (int bb = 0; bb < nb; ++bb)
+                        acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
+                } else {
+                    const int slot = smap[tb_];
+                    if (slot < 0) {
+                        flag |= kStatScratch;
+                        continue;
+                    }
+                    atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], (double)t);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (flag) atomicOr(A.status, flag);
+    if (MODE == kModeAdj) {
+        for (int bb = 0; bb < nb; ++bb) {
+            double s = acc[bb];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+            if (lane == 0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], s);
+        }
+    }
+}
+
+hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
+    if (a.n_vox <= 0) return hipSuccess;
+    const dim3 grid((S.cap_pairs + kPairsPerWG - 1) / kPairsPerWG, a.n_vox), block(64 * kWavesT);
+    switch (mode) {
+        case kModeCount:
+        case kModeFill:
+            hipLaunchKernelGGL(k_cyl3d_tiles<kModeCount>, grid, block, 0, st, G, S, a);
+            break;
+        case kModeFwd:
+            hipLaunchKernelGGL(k_cyl3d_tiles<kModeFwd>, grid, block, 0, st, G, S, a);
+            break;
+        case kModeAdj:
+            hipLaunchKernelGGL(k_cyl3d_tiles<kModeAdj>, grid, block, 0, st, G, S, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K3: compaction of the dense accumulator into CSR rows (ascending bins)
+// ---------------------------------------------------------------------------
+
+constexpr int kBlockC = 512;
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S, Args3D A) {
+    __shared__ int wave_tot[kBlockC / 64];
+    __shared__ int64_t s_run;
+    const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
+    const int vb = blockIdx.x;
+    const int64_t row = A.row_base + vb;
+    const int nsl = S.n_slots[vb];
+    const int64_t nrr = (int64_t)G.NR * G.NR;
+    double* dense = S.dense + (int64_t)vb * S.cap_slots * nrr;
+    const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
+    const int64_t total = (int64_t)nsl * nrr;
+    int64_t start = 0, cap = 0;
+    if (MODE == kModeFill) {
+        start = A.row_ptr[row];
+        cap = A.row_ptr[row + 1] - start;
+    }
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < total; b0 += bs) {
+        const int64_t i = b0 + tid;
+        double a = 0.0;
+        if (i < total) {
+            a = dense[i];
+            dense[i] = 0.0;  // leave the accumulator clean for the next batch
+        }
+        const bool keep = a > 0.0 && a >= A.threshold;
+        const unsigned long long m = __ballot(keep);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wid] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            off += w < wid ? wave_tot[w] : 0;
+            tot += wave_tot[w];
+        }
+        const int64_t run = s_run;
+        if (MODE == kModeFill && keep) {
+            const int64_t pos = run + off + pre;
+            if (pos < cap) {
+                const int64_t slot = i / nrr, rr = i - slot * nrr;
+                A.col[start + pos] = (int32_t)((int64_t)stb[slot] * nrr + rr);
+                A.val[start + pos] = (float)a;
+            } else {
+                atomicOr(A.status, kStatOverflow);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_run = run + tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (MODE == kModeCount) A.row_ptr[row + 1] = s_run;
+        else if (s_run != cap) atomicOr(A.status, kStatOverflow);
+    }
+}
+
+hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
+    if (a.n_vox <= 0) return hipSuccess;
+    if (mode == kModeCount)
+        hipLaunchKernelGGL(k_cyl3d_compact<kModeCount>, dim3(a.n_vox), dim3(kBlockC), 0, st, G, S, a);
+    else
+        hipLaunchKernelGGL(k_cyl3d_compact<kModeFill>, dim3(a.n_vox), dim3(kBlockC), 0, st, G, S, a);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_f32(float* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace psf

@@ -13,33 +13,47 @@ namespace psf {
 
 constexpr int kStatEvent = kStatEventBad;
 
-__device__ __forceinline__ bool event_bin(const int32_t* ev, int64_t e, int64_t N, int64_t& bin) {
+// Crystal ids: id = ring * Nc + g.  2D (NR == 1): bin of the unordered pair;
+// 3D: transaxial pair (g_i < g_j) major, then the rings (r_i, r_j).
+struct EvGeo {
+    int64_t Nc, NR;
+};
+
+__device__ __forceinline__ bool event_bin(const int32_t* ev, int64_t e, EvGeo g, int64_t& bin) {
+    const int64_t N = g.Nc * g.NR;
     int64_t i = ev[2 * e], j = ev[2 * e + 1];
     if (i < 0 || j < 0 || i >= N || j >= N || i == j) return false;
-    if (i > j) {
-        const int64_t t = i;
-        i = j;
-        j = t;
+    int64_t gi = i % g.Nc, ri = i / g.Nc, gj = j % g.Nc, rj = j / g.Nc;
+    if (g.NR == 1) {
+        if (i > j) { const int64_t t = i; i = j; j = t; }
+        bin = i * N - i * (i + 1) / 2 + (j - i - 1);
+        return true;
     }
-    bin = i * N - i * (i + 1) / 2 + (j - i - 1);
+    if (gi == gj) return false;  // no line through the inside joins them
+    if (gi > gj) {
+        int64_t t = gi; gi = gj; gj = t;
+        t = ri; ri = rj; rj = t;
+    }
+    bin = ((gi * g.Nc - gi * (gi + 1) / 2 + (gj - gi - 1)) * g.NR + ri) * g.NR + rj;
     return true;
 }
 
-__global__ void k_lm_gather(const double* y64, int64_t nbins, const int32_t* ev, int64_t ne, int batch, int64_t N,
+__global__ void k_lm_gather(const double* y64, const float* y32, int64_t nbins, const int32_t* ev, int64_t ne, int batch, EvGeo N,
                             float* out, int accumulate, int* status) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
         int64_t bin = 0;
         const bool ok = event_bin(ev, e, N, bin);
         if (!ok) atomicOr(status, kStatEvent);
         for (int bb = 0; bb < batch; ++bb) {
-            const float v = ok ? (float)y64[(int64_t)bb * nbins + bin] : 0.0f;
+            const int64_t k = (int64_t)bb * nbins + bin;
+            const float v = ok ? (y64 ? (float)y64[k] : y32[k]) : 0.0f;
             float* o = out + (int64_t)bb * ne + e;
             *o = accumulate ? *o + v : v;
         }
     }
 }
 
-__global__ void k_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t N, int64_t nbins,
+__global__ void k_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, EvGeo N, int64_t nbins,
                              double* hist, int* status) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
         int64_t bin = 0;
@@ -54,7 +68,7 @@ __global__ void k_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int 
     }
 }
 
-__global__ void k_lm_ratio(const double* y64, const int32_t* ev, int64_t ne, int64_t N, double randoms, double* hist,
+__global__ void k_lm_ratio(const double* y64, const float* y32, const int32_t* ev, int64_t ne, EvGeo N, double randoms, double* hist,
                            int* status) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
         int64_t bin = 0;
@@ -62,7 +76,7 @@ __global__ void k_lm_ratio(const double* y64, const int32_t* ev, int64_t ne, int
             atomicOr(status, kStatEvent);
             continue;
         }
-        const double q = y64[bin] + randoms;
+        const double q = (y64 ? y64[bin] : (double)y32[bin]) + randoms;
         if (q > 0.0) atomicAdd(&hist[bin], 1.0 / q);
     }
 }
@@ -80,25 +94,28 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)(b < 1 ? 1 : (b < 65536 ? b : 65536));
 }
 
-hipError_t launch_lm_gather(const double* y64, int64_t nbins, const int32_t* ev, int64_t ne, int batch, int64_t N,
-                            float* out, int accumulate, int* status, hipStream_t st) {
+hipError_t launch_lm_gather(const double* y64, const float* y32, int64_t nbins, const int32_t* ev, int64_t ne,
+                            int batch, int64_t Nc, int64_t NR, float* out, int accumulate, int* status,
+                            hipStream_t st) {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lm_gather, dim3(grid_for(ne)), dim3(256), 0, st, y64, nbins, ev, ne, batch, N, out,
-                       accumulate, status);
+    hipLaunchKernelGGL(k_lm_gather, dim3(grid_for(ne)), dim3(256), 0, st, y64, y32, nbins, ev, ne, batch,
+                       EvGeo{Nc, NR}, out, accumulate, status);
     return hipGetLastError();
 }
 
-hipError_t launch_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t N, int64_t nbins,
-                             double* hist, int* status, hipStream_t st) {
+hipError_t launch_lm_scatter(const float* h, int64_t ne, const int32_t* ev, int batch, int64_t Nc, int64_t NR,
+                             int64_t nbins, double* hist, int* status, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lm_scatter, dim3(grid_for(ne)), dim3(256), 0, st, h, ne, ev, batch, N, nbins, hist, status);
+    hipLaunchKernelGGL(k_lm_scatter, dim3(grid_for(ne)), dim3(256), 0, st, h, ne, ev, batch, EvGeo{Nc, NR}, nbins,
+                       hist, status);
     return hipGetLastError();
 }
 
-hipError_t launch_lm_ratio(const double* y64, const int32_t* ev, int64_t ne, int64_t N, double randoms, double* hist,
-                           int* status, hipStream_t st) {
+hipError_t launch_lm_ratio(const double* y64, const float* y32, const int32_t* ev, int64_t ne, int64_t Nc, int64_t NR,
+                           double randoms, double* hist, int* status, hipStream_t st) {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lm_ratio, dim3(grid_for(ne)), dim3(256), 0, st, y64, ev, ne, N, randoms, hist, status);
+    hipLaunchKernelGGL(k_lm_ratio, dim3(grid_for(ne)), dim3(256), 0, st, y64, y32, ev, ne, EvGeo{Nc, NR}, randoms,
+                       hist, status);
     return hipGetLastError();
 }
 

@@ -1,0 +1,194 @@
+"""GPU parity of the 3D-scanner path against the FP64 oracle, through the C ABI.
+
+Bar: bins and the CSR sparsity pattern bit-exact (voxels whose decisions the
+oracle flags as within a hair of a boundary are excused from the pattern
+check only); values within 1e-5 relative (FP32 plain form); projections
+within 1e-5 relative to the largest entry.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06170_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+SMALL = S.CFG_3D_SMALL
+CFG3 = S.CFG_3D
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _scanner(cfg):
+    from paper_1607_06170_amd import Scanner
+    return Scanner(cfg, mode3d=True)
+
+
+def _unbin3(b, cfg):
+    Nc = cfg["n_blocks"] * cfg["n_ct"]
+    NR = cfg["n_cz"] * cfg["n_brings"]
+    tb, rest = b // (NR * NR), b % (NR * NR)
+    gi, gj = S.bin_to_pair(tb, Nc)
+    return gi.astype(np.int64), rest // NR, gj.astype(np.int64), rest % NR
+
+
+@pytest.fixture(scope="module")
+def small_ref(oracle):
+    nr = SMALL["n_rows"]
+    td = S.random_table((nr, nr, 4, 4, 5, 5), seed=12)
+    tab = oracle.TableRef(td, nr, 4, 1.0)
+    n = SMALL["nx"] * SMALL["ny"] * SMALL["nz"]
+    cols, flags = oracle.columns_3d(SMALL, tab, np.arange(n), cap=1 << 16)
+    return td, cols, flags
+
+
+def _sparse(cols, nbins):
+    import scipy.sparse as sp
+    rows = np.concatenate([np.full(len(b), k) for k, (b, _) in enumerate(cols)])
+    cidx = np.concatenate([b for b, _ in cols])
+    vals = np.concatenate([v for _, v in cols])
+    return sp.csr_matrix((vals, (rows, cidx)), shape=(len(cols), nbins))
+
+
+def test_table3_parity(torch, oracle):
+    sc = _scanner(CFG3)
+    t = sc.build_table(61, 4, 1.0)
+    got = t.data.cpu().numpy().reshape(61, 61, 4, 4, 5, 5).astype(np.float64)
+    rng = np.random.default_rng(3)
+    rt = np.concatenate([[0, 0, 60, 60, 45, 1], rng.integers(0, 61, 40)])
+    rz = np.concatenate([[0, 60, 0, 60, 45, 0], rng.integers(0, 61, 40)])
+    ref = oracle.table3_rows(CFG3, rt, rz)
+    np.testing.assert_allclose(got[rt, rz], ref, rtol=1e-6, atol=1e-9)
+
+
+def _check_rows(oracle, rp, col, val, cols, flags, vox):
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    exact = 0
+    for r, v in enumerate(vox):
+        g = col[rp[r]:rp[r + 1]].astype(np.int64)
+        gv = val[rp[r]:rp[r + 1]]
+        ob, ov = cols[v]
+        if flags[v] & oracle.F_TIES == 0:
+            assert np.array_equal(g, ob), f"voxel {v}: pattern differs ({len(g)} vs {len(ob)})"
+            np.testing.assert_allclose(gv, ov, rtol=RTOL, atol=0, err_msg=f"voxel {v}")
+            exact += 1
+        else:
+            m = dict(zip(ob.tolist(), ov.tolist()))
+            common = [k for k in range(len(g)) if int(g[k]) in m]
+            np.testing.assert_allclose(gv[common], [m[int(g[k])] for k in common], rtol=RTOL)
+    assert exact >= 0.95 * len(vox)
+
+
+def test_sysmat_small_scanner(torch, oracle, small_ref):
+    td, cols, flags = small_ref
+    nr = SMALL["n_rows"]
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, nr, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0)
+    _check_rows(oracle, rp, col, val, cols, flags, np.arange(len(cols)))
+
+
+@pytest.mark.parametrize("vb,ve", [(0, 1), (17, 50), (583, 600)])
+def test_sysmat_small_ranges(torch, oracle, small_ref, vb, ve):
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve)
+    _check_rows(oracle, rp, col, val, cols, flags, np.arange(vb, ve))
+
+
+def test_projections_small_scanner(torch, oracle, small_ref):
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    A_T = _sparse(cols, sc.n_bins)          # voxels x bins
+    x = S.phantom_uniform(SMALL, seed=7, batch=2)
+    xf = x.astype(np.float32).astype(np.float64)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo = (A_T.T @ xf.T).T
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    rng = np.random.default_rng(8)
+    yc = rng.poisson(50.0 * yo / yo.max()).astype(np.float64)
+    xb = sc.project_adj(t, torch.tensor(yc, dtype=torch.float32, device="cuda")).cpu().numpy()
+    xbo = (A_T @ yc.T).T
+    np.testing.assert_allclose(xb, xbo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xbo).max())
+    s = sc.sensitivity(t).cpu().numpy()
+    np.testing.assert_allclose(s, np.asarray(A_T.sum(axis=1)).ravel(), rtol=RTOL)
+    sc.check()
+
+
+def test_precision_forms_small_scanner(torch, oracle, small_ref):
+    """BF16 operands (U and X = W V rounded) with FP32 accumulation, and the
+    hi/lo split: error against FP64, per element and per projection."""
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    A_T = _sparse(cols, sc.n_bins)
+    x = S.phantom_uniform(SMALL, seed=7)
+    yo = (A_T.T @ x[0])
+    big = yo > 1e-3 * yo.max()
+    for prec, e_tol, p_tol in [(1, 1e-2, 1e-2), (2, 1e-4, 1e-4)]:
+        rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=100, vox_end=140, precision=prec)
+        rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+        for r in range(40):
+            b, v = cols[100 + r]
+            g = col[rp[r]:rp[r + 1]]
+            assert np.array_equal(g, b)
+            assert (np.abs(val[rp[r]:rp[r + 1]] - v) / v).max() <= e_tol
+        y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda"), precision=prec).cpu().numpy()[0]
+        assert (np.abs(y - yo)[big] / yo[big]).max() <= p_tol
+
+
+def _events3(oracle, cfg, A_T, x, n_true, n_rand, seed):
+    yo = A_T.T @ x
+    bins = S.sample_events(yo, n_true, n_rand, seed=seed)
+    gi, ri, gj, rj = _unbin3(bins, cfg)
+    Nc = cfg["n_blocks"] * cfg["n_ct"]
+    i, j = ri * Nc + gi, rj * Nc + gj
+    rng = np.random.default_rng(seed + 1)
+    sw = rng.random(len(bins)) < 0.5
+    return bins, np.stack([np.where(sw, j, i), np.where(sw, i, j)], 1).astype(np.int32)
+
+
+def test_listmode_small_scanner(torch, oracle, small_ref):
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    A_T = _sparse(cols, sc.n_bins)
+    x = S.phantom_uniform(SMALL, seed=9)[0]
+    bins, ev = _events3(oracle, SMALL, A_T, x, 20_000, 2_000, 300)
+    evd = torch.tensor(ev, device="cuda")
+    q = sc.project_fwd(t, torch.tensor(x[None], dtype=torch.float32, device="cuda"), events=evd).cpu().numpy()[0]
+    qo = A_T[:, bins].T @ x.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(q, qo, rtol=RTOL, atol=RTOL * 1e-2 * qo.max())
+    sens = sc.sensitivity(t)
+    M, r = 10, 0.1 * float((A_T.T @ x).mean())
+    x0 = np.ones(sc.n_voxels)
+    sub = slice(0, 5_000)
+    xg = sc.lm_osem_update(t, evd[sub], torch.tensor(x0, dtype=torch.float32, device="cuda"), sens, M, r)
+    sc.check()
+    s_o = np.asarray(A_T.sum(axis=1)).ravel()
+    q0 = A_T[:, bins[sub]].T @ x0 + r
+    back = A_T[:, bins[sub]] @ (1.0 / q0)
+    xo = np.where(s_o > 0, x0 / (s_o / M) * back, 0.0)
+    np.testing.assert_allclose(xg.cpu().numpy(), xo, rtol=2e-5, atol=2e-5 * xo.max())
+
+
+@pytest.mark.parametrize("ijk", [(64, 64, 48), (20, 100, 3)])
+def test_sysmat_full_scanner_sampled(torch, oracle, ijk):
+    """The 128 x 128 x 96 configuration: single voxels' rows against the oracle."""
+    ix, iy, iz = ijk
+    v = (iz * 128 + iy) * 128 + ix
+    td = S.random_table((61, 61, 4, 4, 5, 5), seed=13, scale=0.3)
+    tab = oracle.TableRef(td, 61, 4, 1.0)
+    cols, flags = oracle.columns_3d(CFG3, tab, [v], cap=1 << 22)
+    sc = _scanner(CFG3)
+    t = sc.table_from(td, 61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=v, vox_end=v + 1)
+    _check_rows(oracle, rp, col, val, {v: cols[0]}, {v: flags[0]}, [v])

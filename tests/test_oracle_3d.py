@@ -127,8 +127,8 @@ def test_w3_geometric_projector_vs_monte_carlo(oracle, vid):
     n = 2_000_000
     i1, i2 = _mc_lines_3d(SMALL, c, n, rng)
     ok = (i1 >= 0) & (i2 >= 0)
-    N = oracle.n_crystals_3d(SMALL)
-    mb = oracle.pair_bin(i1[ok], i2[ok], N)
+    Nc = SMALL["n_blocks"] * SMALL["n_ct"]
+    mb = oracle.bin3(i1[ok] % Nc, i1[ok] // Nc, i2[ok] % Nc, i2[ok] // Nc, SMALL)
     ub, cnt = np.unique(mb, return_counts=True)
     ref = dict(zip(bins.tolist(), vals.tolist()))
     tot_ref = vals.sum()
@@ -148,12 +148,20 @@ def rtab(oracle):
     return oracle.TableRef(td, nr, 4, 1.0)
 
 
+def _unbin3(b, cfg):
+    Nc = cfg["n_blocks"] * cfg["n_ct"]
+    NR = cfg["n_cz"] * cfg["n_brings"]
+    tb, rest = b // (NR * NR), b % (NR * NR)
+    gi, gj = S.bin_to_pair(tb, Nc)
+    return gi.astype(np.int64), (rest // NR), gj.astype(np.int64), (rest % NR)
+
+
 def _sym_check(oracle, rtab, v, vr, cmap):
-    N = oracle.n_crystals_3d(SMALL)
+    Nc = SMALL["n_blocks"] * SMALL["n_ct"]
     (b0, v0), (b1, v1) = oracle.columns_3d(SMALL, rtab, [v, vr])[0]
-    i, j = S.bin_to_pair(b0, N)
-    fi, fj = cmap(i.astype(np.int64)), cmap(j.astype(np.int64))
-    mb = oracle.pair_bin(fi, fj, N)
+    gi, ri, gj, rj = _unbin3(b0, SMALL)
+    fi, fj = cmap(ri * Nc + gi), cmap(rj * Nc + gj)
+    mb = oracle.bin3(fi % Nc, fi // Nc, fj % Nc, fj // Nc, SMALL)
     order = np.argsort(mb)
     assert np.array_equal(mb[order], b1)
     np.testing.assert_allclose(v0[order], v1, rtol=1e-12, atol=1e-18)
@@ -228,3 +236,49 @@ def test_table3_gradient_exact_fd(oracle, rtab):
         tm = rtab.data.copy().reshape(-1); tm[e] -= h
         fd = (loss(tp.reshape(rtab.data.shape)) - loss(tm.reshape(rtab.data.shape))) / (2 * h)
         assert abs(fd - flat[e]) <= 1e-9 * max(1.0, abs(fd)), (e, fd, flat[e])
+
+
+def test_w3_vs_brute_force_integration(oracle):
+    """The solid-angle weight against a fine midpoint rule on its definition
+    (1/2pi) * integral [S(T_hi) - S(T_lo)]^+ dtheta, over bundles of a voxel
+    whose symmetric position puts slope-limit switches at the bundle middle."""
+    cfg = SMALL
+    P, R, nc, rf = 4, cfg["n_blocks"], cfg["n_ct"], cfg["r_face"]
+    NR, lz = 8, 2.0
+    z0 = -0.5 * NR * lz
+    hw = 0.5 * nc * 2.0
+    for vid in (588, 0, 333):
+        c = oracle.voxel_centre(cfg, vid)
+        s1s, s2s, _, _ = oracle.samples_2d(cfg, P, c[:2])
+        rng = np.random.default_rng(vid)
+        pick = list(rng.choice(len(s1s), 6, replace=False))
+        if vid == 588:  # a bundle whose slope-limit switch sits exactly at its middle
+            pick += [int(np.nonzero((s1s == 70) & (s2s == 185))[0][0])]
+
+        def ang(s, e):
+            g, p = s // P, s % P
+            b, cc = g // nc, g % nc
+            xi = -hw + (cc * P + p + e) * (2.0 / P)
+            ph = 2 * np.pi * b / R
+            return math.atan2(rf * math.sin(ph) + xi * math.cos(ph) - c[1], rf * math.cos(ph) - xi * math.sin(ph) - c[0])
+
+        for k in pick:
+            a, b = int(s1s[k]), int(s2s[k])
+            lo1, lo2 = ang(a, 0), ang(b, 0)
+            len1, len2 = (ang(a, 1) - lo1) % (2 * np.pi), (ang(b, 1) - lo2) % (2 * np.pi)
+            d = (lo2 + np.pi - lo1 + np.pi) % (2 * np.pi) - np.pi
+            ta, tb = lo1 + max(0.0, d), lo1 + min(len1, d + len2)
+            ph1, ph2 = 2 * np.pi * ((a // P) // nc) / R, 2 * np.pi * ((b // P) // nc) / R
+            D1 = rf - (math.cos(ph1) * c[0] + math.sin(ph1) * c[1])
+            D2 = rf - (math.cos(ph2) * c[0] + math.sin(ph2) * c[1])
+            n = 400_000
+            th = ta + (np.arange(n) + 0.5) * (tb - ta) / n
+            d1, d2 = D1 / np.cos(th - ph1), D2 / -np.cos(th - ph2)
+            qs = [(9, 31), (10, 31), (11, 30)] if (a, b) == (70, 185) else []
+            for q1, q2 in list(rng.integers(0, NR * P, size=(40, 2))) + qs:
+                w = oracle.w3_pair(cfg, P, c, a, int(q1), b, int(q2))
+                lo = np.maximum((z0 + q1 * lz / P - c[2]) / d1, (c[2] - (z0 + (q2 + 1) * lz / P)) / d2)
+                hi = np.minimum((z0 + (q1 + 1) * lz / P - c[2]) / d1, (c[2] - (z0 + q2 * lz / P)) / d2)
+                f = np.where(hi > lo, hi / np.sqrt(1 + hi * hi) - lo / np.sqrt(1 + lo * lo), 0.0)
+                ref = f.sum() * (tb - ta) / n / (2 * np.pi)
+                assert abs(w - ref) <= 1e-7 * max(ref, 1e-12), (vid, a, b, q1, q2, w, ref)
