@@ -2,14 +2,20 @@
 """Throughput of the P-SPIR system-matrix hot path on one MI355X.
 
 One step = one pass of the whole path over one synthetic input:
-  build_psf_sysmat (count + fill phases, CSR of A^T over the voxel range),
+  build_psf_sysmat (count + fill phases: CSR of A^T over the voxel range),
   project_fwd (y = A x on the fly) and project_adj (A^T y on the fly).
-Prints ONE JSON line (rank 0).  ``value`` is system-matrix elements (CSR
-non-zeros) written per second of the build; the same line carries the
-forward+adjoint projection rate in LORs/s, a roofline object for the
-dominant kernel and the FP64 oracle timed on the host cores.
+Prints ONE JSON line.  ``value`` is system-matrix elements (CSR non-zeros)
+produced per second of the build; the same line carries the forward+adjoint
+projection rate in LORs/s, a roofline object for the dominant kernel (timed
+with HIP events around its launches, on the stream it runs on) and the FP64
+oracle timed on the host cores.
 
-Inputs are synthetic, seeded, and resident in HBM before timing starts.
+Workloads (all inputs seeded and synthetic, resident in HBM before timing):
+  cyl3d_sub16  3D scanner of 32 blocks x 12 x 12 crystals (2 x 2 x 15 mm),
+               4 block rings, faces at 130 mm; the central 16 x 16 x 16 voxels
+               (1 mm) of its 128 x 128 x 96 image; analytic 61x61x4x4x5x5 table.
+  ring2d_64    2D ring of 16 blocks x 8 crystals, faces at 65 mm; 64 x 64 image;
+               61 x 4 x 5 table; CSR threshold 1e-6.
 """
 from __future__ import annotations
 
@@ -24,140 +30,179 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
-FP64_VALU_TFLOPS = 78.6     # MI355X vector FP64 peak
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32
+FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ring2d_64")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="cyl3d_sub16", choices=["cyl3d_sub16", "ring2d_64"])
+    ap.add_argument("--precision", type=int, default=0, help="0 FP32 plain, 1 BF16, 2 BF16 hi/lo")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
 
-def workload_ring2d(name):
+def workload(name):
     from paper_1607_06170_amd import synth
+    if name == "cyl3d_sub16":
+        cfg = dict(synth.CFG_3D, nx=16, ny=16, nz=16)
+        desc = ("3D: 32 blocks x 12x12 LYSO crystals (2x2x15 mm), 4 block rings (48 crystal rings), faces at "
+                "130 mm; central 16x16x16 voxels (1 mm) of the 128x128x96 image; analytic 61x61x4x4x5x5 table; "
+                "all non-zeros kept")
+        return cfg, dict(workload=desc, mode3d=True, batch=1, steps=3, warmup=1)
     cfg = dict(synth.CFG_2D)
-    return cfg, dict(workload="2D ring: 16 blocks x 8 LYSO crystals (2 mm, 15 mm deep), faces at 65 mm; "
-                              "64x64 image of 1 mm voxels; 61 x 4 x 5 response table; threshold 1e-6",
-                     batch=1, seed=1)
+    desc = ("2D ring: 16 blocks x 8 LYSO crystals (2 mm, 15 mm deep), faces at 65 mm; 64x64 image of 1 mm "
+            "voxels; 61 x 4 x 5 table; threshold 1e-6")
+    return cfg, dict(workload=desc, mode3d=False, batch=1, steps=20, warmup=3)
+
+
+def phantom(cfg, meta):
+    from paper_1607_06170_amd import synth
+    if meta["mode3d"]:
+        full = dict(cfg, nx=128, ny=128, nz=96)
+        img = synth.phantom_blobs(full, seed=2).reshape(96, 128, 128)
+        sub = img[40:56, 56:72, 56:72]   # the central 16^3 voxels
+        return np.ascontiguousarray(sub.reshape(1, -1))
+    return synth.phantom_uniform(cfg, seed=1, batch=meta["batch"])
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path (voxel sharding plus one "
-                                   "all-reduce of the sinogram) is described in the design notes, not built"}))
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU layout (voxel sharding plus "
+                                   "one all-reduce of the sinogram) is described in the design notes, not built"}))
         sys.exit(2)
     import torch
-    from paper_1607_06170_amd import Scanner, synth
+    from paper_1607_06170_amd import Scanner
 
-    cfg, meta = workload_ring2d(args.workload)
+    cfg, meta = workload(args.workload)
+    steps = args.steps if args.steps is not None else meta["steps"]
+    warmup = args.warmup if args.warmup is not None else meta["warmup"]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sc = Scanner(cfg)
+    sc = Scanner(cfg, mode3d=meta["mode3d"])
     tab = sc.build_table(cfg["n_rows"], cfg["n_sub"], cfg["step_deg"])
-    x_np = synth.phantom_uniform(cfg, seed=meta["seed"], batch=meta["batch"])
+    x_np = phantom(cfg, meta)
     x = torch.tensor(x_np, dtype=torch.float32, device=dev)
     thr = cfg["threshold"]
-    sens = sc.sensitivity(tab)
-    lors = int((sc.project_fwd(tab, torch.ones(1, sc.n_voxels, device=dev)) > 0).sum().item())
+    prec = args.precision
+    ones = torch.ones(1, sc.n_voxels, device=dev)
+    lors = int((sc.project_fwd(tab, ones) > 0).sum().item())   # bins with sensitivity > 0
     torch.cuda.synchronize()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    t_build, t_fwd, t_adj, nnz_tot = [], [], [], 0
+    rec = dict(build=[], fwd=[], adj=[], nnz=0, tiles=0)
 
     def step(record):
-        nonlocal nnz_tot
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
         e0.record()
-        rp, col, val = sc.build_psf_sysmat(tab, threshold=thr)
+        rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=prec)
         e1.record()
-        y = sc.project_fwd(tab, x)
+        t_build = sc.tiles_last_call() if meta["mode3d"] and record else 0
+        y = sc.project_fwd(tab, x, precision=prec)
         e2.record()
-        xb = sc.project_adj(tab, y)
+        t_fwd = sc.tiles_last_call() if meta["mode3d"] and record else 0
+        xb = sc.project_adj(tab, y, precision=prec)
         e3.record()
         if record:
             torch.cuda.synchronize()
-            t_build.append(e0.elapsed_time(e1))
-            t_fwd.append(e1.elapsed_time(e2))
-            t_adj.append(e2.elapsed_time(e3))
-            nnz_tot += int(col.numel())
+            t_adj = sc.tiles_last_call() if meta["mode3d"] else 0
+            rec["build"].append(e0.elapsed_time(e1))
+            rec["fwd"].append(e1.elapsed_time(e2))
+            rec["adj"].append(e2.elapsed_time(e3))
+            rec["nnz"] += int(col.numel())
+            # the count and fill phases contract the same tiles
+            rec["tiles"] += 2 * t_build + t_fwd + t_adj
         return xb
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
+    sc.profile_start()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    k_ms, k_launches = sc.profile_stop()
 
-    ms_step = 1e3 * wall / args.steps
-    build_s = sum(t_build) / 1e3
-    proj_s = (sum(t_fwd) + sum(t_adj)) / 1e3
-    elements_per_s = nnz_tot / build_s
-    lors_per_s = lors * meta["batch"] * args.steps / proj_s
-    nnz = nnz_tot // args.steps
-    n_rows = sc.n_voxels
-
-    # dominant kernel: the voxel sweep of the build (count + fill launches).
-    # Algorithmic HBM bytes per build: CSR output (4 B column + 4 B value per
-    # non-zero, 8 B per row pointer) -- the kernel reads nothing else from HBM
-    # but the 4.9 KB table.
-    algo_bytes = nnz * 8 + (n_rows + 1) * 8
-    build_ms = float(np.mean(t_build))
-    achieved = algo_bytes / (build_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_voxel2d<count>+k_voxel2d<fill> (one build_psf_sysmat call, HIP events)",
-            "avg_ms": build_ms}
-
+    build_s = sum(rec["build"]) / 1e3
+    proj_s = (sum(rec["fwd"]) + sum(rec["adj"])) / 1e3
+    nnz = rec["nnz"] // steps
     out = {
         "metric": "PSF sysmat elements/s; fwd+adjoint projection LORs/s at stated rel-err vs FP64",
-        "value": elements_per_s,
+        "value": rec["nnz"] / build_s,
         "unit": "elements/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 tiles, f64 geometry and bin sums",
-        "data": "synthetic (seeded uniform phantom, analytic response table)",
-        "config": {"workload": meta["workload"], "voxels": n_rows, "bins": sc.n_bins, "batch": meta["batch"],
-                   "nnz": nnz, "lors": lors},
-        "fwd_adj_lors_per_s": lors_per_s,
-        "build_ms": build_ms, "fwd_ms": float(np.mean(t_fwd)), "adj_ms": float(np.mean(t_adj)),
-        "rel_err_vs_fp64": "<= 1e-5 per element (tests/test_gpu_2d.py)",
-        "roofline": roof,
+        "dtype": ["f32", "bf16", "bf16x2"][prec] + " tiles, f64 geometry and weights",
+        "data": "synthetic (seeded phantom, analytic response table)",
+        "config": {"workload": meta["workload"], "voxels": sc.n_voxels, "bins": sc.n_bins,
+                   "batch": meta["batch"], "nnz": nnz, "lors": lors},
+        "fwd_adj_lors_per_s": lors * meta["batch"] * steps / proj_s,
+        "build_ms": float(np.mean(rec["build"])), "fwd_ms": float(np.mean(rec["fwd"])),
+        "adj_ms": float(np.mean(rec["adj"])),
+        "rel_err_vs_fp64": "<= 1e-5 per element, FP32 form (tests/test_gpu_2d.py, tests/test_gpu_3d.py)",
     }
+    avg_ms = k_ms / max(k_launches, 1)
+    if meta["mode3d"]:
+        K = cfg["n_sub"] ** 2
+        flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X
+        tiles_per_launch = rec["tiles"] / max(k_launches, 1)
+        achieved = tiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / FP32_VALU_TFLOPS, "traffic": None,
+                           "kernel": "k_cyl3d_tiles (tile contraction T = U^T W V, FP32 VALU)",
+                           "avg_launch_ms": avg_ms, "launches": k_launches,
+                           "tiles_per_launch": tiles_per_launch, "flops_per_tile": flops_tile}
+    else:
+        # the per-voxel sweep kernel; algorithmic HBM bytes = the CSR it writes
+        algo = nnz * 8 + (sc.n_voxels + 1) * 8
+        gbs = algo / 2 / (avg_ms * 1e-3) / 1e9   # count + fill launches per build
+        out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_voxel2d (per-voxel sweep, all modes)", "avg_launch_ms": avg_ms,
+                           "launches": k_launches}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, x_np, thr)
+        out["cpu_baseline"] = cpu_baseline(cfg, meta, x_np, thr)
     print(json.dumps(out))
 
 
-def cpu_baseline(cfg, x_np, thr):
-    """The FP64 oracle, as it stands, on the host cores: full build (dense
-    columns + CSR) and forward + adjoint for the same workload."""
+def cpu_baseline(cfg, meta, x_np, thr):
+    """The FP64 oracle, as it stands, on the host cores."""
     from oracle import oracle as O
     nthreads = min(16, os.cpu_count() or 1)
+    if meta["mode3d"]:
+        nr, P = cfg["n_rows"], cfg["n_sub"]
+        rt, rz = np.meshgrid(np.arange(nr), np.arange(nr), indexing="ij")
+        t0 = time.perf_counter()
+        tab = O.TableRef(O.table3_rows(cfg, rt.ravel(), rz.ravel(), P, cfg["step_deg"], nthreads), nr, P,
+                         cfg["step_deg"])
+        t_tab = time.perf_counter() - t0
+        vox = np.linspace(0, 16 ** 3 - 1, 2 * nthreads).astype(np.int64)
+        t0 = time.perf_counter()
+        cols, _ = O.columns_3d(cfg, tab, vox, cap=1 << 21, nthreads=nthreads)
+        t1 = time.perf_counter()
+        nnz = sum(len(b) for b, _ in cols)
+        return {"value": nnz / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
+                "sample": f"{len(vox)} voxels spread over the 16^3 sub-volume: FP64 sparse columns "
+                          f"(table build of {t_tab:.1f} s not counted)", "seconds": t1 - t0}
     t0 = time.perf_counter()
     tab = O.table_2d(cfg)
-    cols, flags = O.columns_2d(cfg, tab, np.arange(cfg["nx"] * cfg["ny"]), nthreads=nthreads)
+    cols, _ = O.columns_2d(cfg, tab, np.arange(cfg["nx"] * cfg["ny"]), nthreads=nthreads)
     rp, col, val = O.csr_from_columns(cols, thr)
     t1 = time.perf_counter()
-    y = O.project_fwd(cols, x_np)
-    xb = O.project_adj(cols, y)
-    t2 = time.perf_counter()
     return {"value": len(col) / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
-            "sample": "full workload: every voxel's FP64 column, CSR, then y = A x and A^T y in numpy",
-            "build_s": t1 - t0, "fwd_adj_s_after_build": t2 - t1}
+            "sample": "full workload: every voxel's FP64 column and the CSR", "seconds": t1 - t0}
 
 
 if __name__ == "__main__":

@@ -213,6 +213,21 @@ class Scanner:
                                         _stream()), "psf_lm_osem_update")
         return out
 
+    def profile_start(self):
+        """Start timing the contraction kernels with HIP events (psf_profile)."""
+        check(self.L.psf_profile(self.h, 1, None, None), "psf_profile")
+
+    def profile_stop(self):
+        """(milliseconds summed over recorded launches, number of launches)."""
+        ms, n = C.c_double(), C.c_int64()
+        check(self.L.psf_profile(self.h, 0, C.byref(ms), C.byref(n)), "psf_profile")
+        return ms.value, n.value
+
+    def tiles_last_call(self) -> int:
+        """Tiles contracted by the last 3D call (from the workspace header)."""
+        _torch().cuda.synchronize()
+        return int(self._ws[64:72].cpu().view(__import__("torch").int64).item()) if self._ws is not None else 0
+
     def check(self):
         """Synchronise and raise if a kernel flagged an error (e.g. angle range)."""
         ws = self._ws

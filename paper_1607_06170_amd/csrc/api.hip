@@ -49,6 +49,8 @@ int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, p
     if (st != PSF_OK) return st;
     psf_handle* h = new (std::nothrow) psf_handle();
     if (!h) return PSF_EINVAL;
+    h->prof_on = false;
+    h->frames_dev = nullptr;
     h->g = *geom;
     h->im = *img;
     h->mode3d = mode3d;
@@ -81,6 +83,10 @@ int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, p
 
 void psf_destroy(psf_handle* h) {
     if (!h) return;
+    for (auto& e : h->prof_ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     if (h->frames_dev) (void)hipFree(h->frames_dev);
     delete h;
 }
@@ -277,7 +283,10 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
     if ((st = check_2d_support(h, G, mode))) return st;
     if ((st = zero_header(ws, s))) return st;
     if (!csr->col) {
-        HIP_TRY(launch_voxel2d(kModeCount, G, a, s));
+        {
+            ProfScope ps_(h, s);
+            HIP_TRY(launch_voxel2d(kModeCount, G, a, s));
+        }
         HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));
         int64_t nnz = 0;
         HIP_TRY(hipMemcpyAsync(&nnz, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -293,7 +302,10 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
         csr->nnz = need;
         return PSF_ESIZE;
     }
-    HIP_TRY(launch_voxel2d(kModeFill, G, a, s));
+    {
+        ProfScope ps_(h, s);
+        HIP_TRY(launch_voxel2d(kModeFill, G, a, s));
+    }
     return read_status(ws, s);
 }
 
@@ -314,7 +326,10 @@ static int fwd_bins(psf_handle* h, const psf_table* table, const psf_opts* opts,
     a.y64 = y64;
     a.status = (int*)ws;
     HIP_TRY(launch_zero_f64(y64, (int64_t)batch * h->n_bins, s));
-    HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
+    {
+        ProfScope ps_(h, s);
+        HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
+    }
     return PSF_OK;
 }
 
@@ -342,7 +357,10 @@ static int adj_bins(psf_handle* h, const psf_table* table, const psf_opts* opts,
         a.grad64 = g64;
         a.status = (int*)ws;
         a.accumulate = accumulate;
-        HIP_TRY(launch_voxel2d(mode, G, a, s));
+        {
+            ProfScope ps_(h, s);
+            HIP_TRY(launch_voxel2d(mode, G, a, s));
+        }
     }
     return PSF_OK;
 }
@@ -448,6 +466,40 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
     if ((st = adj_bins(h, table, opts, h32, 0, 1, back, nullptr, nullptr, 0, ws, s))) return st;
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
     return PSF_OK;
+}
+
+int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches) {
+    if (!h) return PSF_EINVAL;
+    if (enable) {
+        for (auto& e : h->prof_ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        h->prof_ev.clear();
+        h->prof_on = true;
+        return PSF_OK;
+    }
+    double tot = 0.0;
+    int st = PSF_OK;
+    for (auto& e : h->prof_ev) {
+        float t = 0.0f;
+        hipError_t r = hipEventSynchronize(e.second);
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, e.first, e.second);
+        if (r != hipSuccess) {
+            psf::g_last_hip = (int)r;
+            st = PSF_EHIP;
+        }
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)h->prof_ev.size();
+    for (auto& e : h->prof_ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    h->prof_ev.clear();
+    h->prof_on = false;
+    return st;
 }
 
 int psf_check(psf_handle* h, void* ws, void* stream) {

@@ -59,8 +59,9 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, x64, y32, h64, h32, back, total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, x64, y32, h64, h32, back, total;
     int bmax, bcsr, cap_slots;
+    int64_t max_chunks;
 };
 
 Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
@@ -87,6 +88,9 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;
     off += align256(sizeof(double) * (size_t)L.bcsr * L.cap_slots * NR * NR);
+    L.chunks = off;
+    L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
+    off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.y32 = L.h64 = L.h32 = L.back = off;
@@ -124,6 +128,8 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.slotmap = at3<int>(ws, L.slotmap);
     S.slot_tbin = at3<int>(ws, L.slot_tbin);
     S.dense = at3<double>(ws, L.dense);
+    S.chunk_counts = at3<int>(ws, L.chunks);
+    S.max_chunks = L.max_chunks;
     return S;
 }
 
@@ -141,8 +147,13 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.x = x + (int64_t)b0 * h->n_vox;
             a.y = y + (int64_t)b0 * h->n_bins;
             a.status = (int*)ws;
+        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+            a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
-            HIP_TRY(launch_cyl3d_tiles(kModeFwd, G, S, a, s));
+            {
+                ProfScope ps_(h, s);
+                HIP_TRY(launch_cyl3d_tiles(kModeFwd, G, S, a, s));
+            }
         }
     }
     return PSF_OK;
@@ -163,8 +174,13 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
+        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+            a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
-            HIP_TRY(launch_cyl3d_tiles(kModeAdj, G, S, a, s));
+            {
+                ProfScope ps_(h, s);
+                HIP_TRY(launch_cyl3d_tiles(kModeAdj, G, S, a, s));
+            }
         }
     }
     return PSF_OK;
@@ -202,6 +218,8 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     }
     // the dense accumulators start clean; the compaction leaves them clean
     HIP_TRY(launch_zero_f64(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
+    // the count phase adds each chunk's count into row_ptr[row + 1]
+    if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     for (int64_t v0 = vb; v0 < ve; v0 += L.bcsr) {
         Args3D a;
         memset(&a, 0, sizeof(a));
@@ -214,8 +232,12 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         a.col = csr->col;
         a.val = csr->val;
         a.status = (int*)ws;
+        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
         HIP_TRY(launch_cyl3d_transaxial(G, S, a, 1, s));
-        HIP_TRY(launch_cyl3d_tiles(kModeCount, G, S, a, s));
+        {
+            ProfScope ps_(h, s);
+            HIP_TRY(launch_cyl3d_tiles(kModeCount, G, S, a, s));
+        }
         HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, S, a, s));
     }
     if (!phase_fill) {

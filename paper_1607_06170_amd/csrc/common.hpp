@@ -20,8 +20,9 @@ constexpr int kStatOverflow = 2;  // fill phase wanted more entries than allotte
 constexpr int kStatGeom = 4;
 constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or the same crystal twice
 
-// Workspace header: status word, nnz total, padding to 256 bytes.
+// Workspace header: status word at byte 0, tile counter (uint64) at byte 64, padding to 256 bytes.
 constexpr size_t kWsHeader = 256;
+constexpr size_t kWsTileCounter = 64;
 
 // Everything a 2D-ring kernel needs, passed by value.
 struct Ring2D {
@@ -58,6 +59,8 @@ struct Scratch3D {
     int* slotmap;      // [B][ntbins]  transaxial bin -> slot (-1: none)
     int* slot_tbin;    // [B][cap_slots]
     double* dense;     // [B][cap_slots][NR * NR]
+    int* chunk_counts; // [B][max_chunks]  kept entries per compaction chunk
+    int64_t max_chunks;
 };
 
 struct Args3D {
@@ -75,6 +78,7 @@ struct Args3D {
     float* val;
     int* status;
     int ones;           // adjoint with y == 1 (sensitivity)
+    unsigned long long* tiles;  // count of tiles contracted (workspace header)
 };
 
 // Device view of the handle (host struct defined in api.cpp).
@@ -132,6 +136,7 @@ hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Arg
 hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+int64_t cyl3d_max_chunks(int cap_slots, int NR);
 constexpr int kStatScratch = 16;  // a per-voxel scratch capacity was exceeded
 
 }  // namespace psf

@@ -449,6 +449,7 @@ struct WaveLds {
     float V[kMaxK][25];
     float X[kMaxK][25];
     double ta[kMaxK], tb[kMaxK];
+    double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
     int pt1[kMaxK], pt2[kMaxK];
     int urange[2 * kMaxK];
 };
@@ -512,6 +513,22 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
         wg.s2 = G.frames[2 * b2 + 1];
         wg.D1 = G.rf - (wg.c1 * vx + wg.s1 * vy);
         wg.D2 = G.rf - (wg.c2 * vx + wg.s2 * vy);
+        // range of cos(theta - psi) over each bundle, for both faces: the slope
+        // limits A cos(theta - psi) then lie within A times that range
+        if (lane < nsmp) {
+            const double ca = cos(L.ta[lane]), sa = sin(L.ta[lane]), cb = cos(L.tb[lane]), sb = sin(L.tb[lane]);
+            const double u1a = ca * wg.c1 + sa * wg.s1, u1b = cb * wg.c1 + sb * wg.s1;
+            const double u2a = -(ca * wg.c2 + sa * wg.s2), u2b = -(cb * wg.c2 + sb * wg.s2);
+            // the maximum 1 is reached inside when the face normal direction lies in the bundle
+            const double m1 = wrap2pi3(atan2(wg.s1, wg.c1) - L.ta[lane]);
+            const double m2 = wrap2pi3(atan2(-wg.s2, -wg.c2) - L.ta[lane]);
+            const double wdt = L.tb[lane] - L.ta[lane];
+            L.c1lo[lane] = fmin(u1a, u1b);
+            L.c1hi[lane] = m1 <= wdt ? 1.0 : fmax(u1a, u1b);
+            L.c2lo[lane] = fmin(u2a, u2b);
+            L.c2hi[lane] = m2 <= wdt ? 1.0 : fmax(u2a, u2b);
+        }
+        __builtin_amdgcn_wave_barrier();
         // rings r2 reached from ring r1: photon 2 lands at zv - (d2/d1)(z1 - zv)
         double zmin = 1e300, zmax = -1e300;
         for (int k = 0; k < nsmp; ++k) {
@@ -541,6 +558,17 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
                 const double z1hi = G.z0 + (r1 + (double)(pz1 + 1) / P) * G.lz;
                 const double z2lo = G.z0 + (r2 + (double)pz2 / P) * G.lz;
                 const double z2hi = G.z0 + (r2 + (double)(pz2 + 1) / P) * G.lz;
+                // skip pairs whose slope windows cannot meet anywhere in the bundle
+                // (the closed form is then exactly 0)
+                {
+                    const double a1lo = (z1lo - vz) / wg.D1, a1hi = (z1hi - vz) / wg.D1;
+                    const double a2lo = (vz - z2hi) / wg.D2, a2hi = (vz - z2lo) / wg.D2;
+                    const double t1hi_max = a1hi * (a1hi >= 0.0 ? L.c1hi[k] : L.c1lo[k]);
+                    const double t1lo_min = a1lo * (a1lo >= 0.0 ? L.c1lo[k] : L.c1hi[k]);
+                    const double t2hi_max = a2hi * (a2hi >= 0.0 ? L.c2hi[k] : L.c2lo[k]);
+                    const double t2lo_min = a2lo * (a2lo >= 0.0 ? L.c2lo[k] : L.c2hi[k]);
+                    if (t1hi_max <= t2lo_min || t2hi_max <= t1lo_min) continue;
+                }
                 const double w = w3_closed(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ta[k], L.tb[k]);
                 if (w > kEpsW3) {
                     L.W[L.pt1[k] * P + pz1][L.pt2[k] * P + pz2] = (float)w;
@@ -548,6 +576,7 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
                 }
             }
             if (!__any(any)) continue;
+            if (lane == 0 && A.tiles) atomicAdd(A.tiles, 1ull);
             __builtin_amdgcn_wave_barrier();
             // response rows: lanes 0..K-1 -> U (g1, r1), lanes 32..32+K-1 -> V (g2, r2)
             if (lane < K) {
@@ -653,34 +682,55 @@ hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, cons
 // ---------------------------------------------------------------------------
 // K3: compaction of the dense accumulator into CSR rows (ascending bins)
 // ---------------------------------------------------------------------------
+// A voxel's accumulator is cut into chunks of kChunk entries, one workgroup
+// each.  Count phase: each chunk adds its number of kept entries to the row
+// count.  Fill phase: a first pass stores the per-chunk counts, the second
+// writes each chunk at its offset (row start + counts of the chunks before
+// it), in order.  The last pass over a chunk clears it for the next batch.
 
 constexpr int kBlockC = 512;
+constexpr int64_t kChunk = 32768;
+
+enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ int wave_tot[kBlockC / 64];
     __shared__ int64_t s_run;
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
-    const int vb = blockIdx.x;
+    const int vb = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
     const int64_t row = A.row_base + vb;
     const int nsl = S.n_slots[vb];
     const int64_t nrr = (int64_t)G.NR * G.NR;
+    const int64_t total = (int64_t)nsl * nrr;
+    const int64_t c0 = chunk * kChunk;
+    if (c0 >= total) return;
+    const int64_t c1 = c0 + kChunk < total ? c0 + kChunk : total;
     double* dense = S.dense + (int64_t)vb * S.cap_slots * nrr;
     const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
-    const int64_t total = (int64_t)nsl * nrr;
+    int* ccount = S.chunk_counts + (int64_t)vb * S.max_chunks;
     int64_t start = 0, cap = 0;
-    if (MODE == kModeFill) {
+    if (MODE == kCompactFill) {
+        if (tid == 0) {
+            int64_t off = 0;
+            for (int64_t c = 0; c < chunk; ++c) off += ccount[c];
+            s_run = off;
+        }
+        __syncthreads();
         start = A.row_ptr[row];
         cap = A.row_ptr[row + 1] - start;
+    } else {
+        if (tid == 0) s_run = 0;
     }
-    if (tid == 0) s_run = 0;
     __syncthreads();
-    for (int64_t b0 = 0; b0 < total; b0 += bs) {
+    const int64_t run0 = s_run;
+    for (int64_t b0 = c0; b0 < c1; b0 += bs) {
         const int64_t i = b0 + tid;
         double a = 0.0;
-        if (i < total) {
+        if (i < c1) {
             a = dense[i];
-            dense[i] = 0.0;  // leave the accumulator clean for the next batch
+            if (MODE != kCompactChunks) dense[i] = 0.0;  // leave the accumulator clean
         }
         const bool keep = a > 0.0 && a >= A.threshold;
         const unsigned long long m = __ballot(keep);
@@ -693,7 +743,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             tot += wave_tot[w];
         }
         const int64_t run = s_run;
-        if (MODE == kModeFill && keep) {
+        if (MODE == kCompactFill && keep) {
             const int64_t pos = run + off + pre;
             if (pos < cap) {
                 const int64_t slot = i / nrr, rr = i - slot * nrr;
@@ -708,17 +758,26 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         __syncthreads();
     }
     if (tid == 0) {
-        if (MODE == kModeCount) A.row_ptr[row + 1] = s_run;
-        else if (s_run != cap) atomicOr(A.status, kStatOverflow);
+        const int64_t n = s_run - run0;
+        if (MODE == kCompactCount) atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
+        else if (MODE == kCompactChunks) ccount[chunk] = (int)n;
+        else if (c1 == total && s_run != cap) atomicOr(A.status, kStatOverflow);
     }
+}
+
+int64_t cyl3d_max_chunks(int cap_slots, int NR) {
+    return ((int64_t)cap_slots * NR * NR + kChunk - 1) / kChunk;
 }
 
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_vox <= 0) return hipSuccess;
-    if (mode == kModeCount)
-        hipLaunchKernelGGL(k_cyl3d_compact<kModeCount>, dim3(a.n_vox), dim3(kBlockC), 0, st, G, S, a);
-    else
-        hipLaunchKernelGGL(k_cyl3d_compact<kModeFill>, dim3(a.n_vox), dim3(kBlockC), 0, st, G, S, a);
+    const dim3 grid((unsigned)S.max_chunks, a.n_vox), block(kBlockC);
+    if (mode == kModeCount) {
+        hipLaunchKernelGGL(k_cyl3d_compact<kCompactCount>, grid, block, 0, st, G, S, a);
+    } else {
+        hipLaunchKernelGGL(k_cyl3d_compact<kCompactChunks>, grid, block, 0, st, G, S, a);
+        hipLaunchKernelGGL(k_cyl3d_compact<kCompactFill>, grid, block, 0, st, G, S, a);
+    }
     return hipGetLastError();
 }
 
