@@ -166,7 +166,7 @@ static double gl16_outer(const outer_ctx* c, double a, double b) {
 static double adapt_outer(const outer_ctx* c, double a, double b, double whole, int depth) {
     double m = 0.5 * (a + b);
     double l = gl16_outer(c, a, m), r = gl16_outer(c, m, b);
-    if (depth >= 30 || fabs(l + r - whole) <= 1e-14 * fabs(l + r) + 1e-18 * (b - a)) return l + r;
+    if (depth >= 30 || fabs(l + r - whole) <= 1e-14 * fabs(l + r) + 1e-17) return l + r;
     return adapt_outer(c, a, m, l, depth + 1) + adapt_outer(c, m, b, r, depth + 1);
 }
 
