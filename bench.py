@@ -119,13 +119,20 @@ def main():
             rec["tiles"] += 2 * t_build + t_fwd + t_adj
         return xb
 
-    for _ in range(warmup):
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"workload {args.workload}: {sc.n_voxels} voxels, {sc.n_bins} bins; warmup {warmup}, steps {steps}")
+    for i in range(warmup):
         step(False)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1} done")
     torch.cuda.synchronize()
     sc.profile_start()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         step(True)
+        log(f"step {i + 1}: build {rec['build'][-1]:.1f} ms, fwd {rec['fwd'][-1]:.1f} ms, adj {rec['adj'][-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     k_ms, k_launches = sc.profile_stop()
@@ -173,6 +180,7 @@ def main():
                            "kernel": "k_voxel2d (per-voxel sweep, all modes)", "avg_launch_ms": avg_ms,
                            "launches": k_launches}
     if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(cfg, meta, x_np, thr)
     print(json.dumps(out))
 
@@ -188,6 +196,7 @@ def cpu_baseline(cfg, meta, x_np, thr):
         tab = O.TableRef(O.table3_rows(cfg, rt.ravel(), rz.ravel(), P, cfg["step_deg"], nthreads), nr, P,
                          cfg["step_deg"])
         t_tab = time.perf_counter() - t0
+        print(f"[bench] oracle table: {t_tab:.1f} s", file=sys.stderr, flush=True)
         vox = np.linspace(0, 16 ** 3 - 1, 2 * nthreads).astype(np.int64)
         t0 = time.perf_counter()
         cols, _ = O.columns_3d(cfg, tab, vox, cap=1 << 21, nthreads=nthreads)

@@ -70,64 +70,70 @@ struct W3Geo {
     double c2, s2, D2;  // photon 2's face
 };
 
+__device__ __forceinline__ void cswap(double& a, double& b) {
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// one cut of the bundle: where A_i cos(theta - psi_i) = A_j cos(theta - psi_j),
+// i.e. p cos(theta) + q sin(theta) = 0, if that falls strictly inside (ta, tb);
+// otherwise tb (an empty piece)
+__device__ __forceinline__ double w3_cut(double Ai, double Ci, double Si, double Aj, double Cj, double Sj, double ta,
+                                         double tb) {
+    const double p = Ai * Ci - Aj * Cj, q = Ai * Si - Aj * Sj;
+    if (p == 0.0 && q == 0.0) return tb;
+    const double th0 = atan2(-p, q);
+    const double r = th0 + rint((0.5 * (ta + tb) - th0) / kPi) * kPi;
+    return (r > ta && r < tb) ? r : tb;
+}
+
+// asin(A sin(theta - psi) / sqrt(1 + A^2)) at (cos theta, sin theta)
+__device__ __forceinline__ double w3_F(double A, double C, double S, double inv, double ct, double st) {
+    return asin(A * (st * C - ct * S) * inv);
+}
+
 __device__ double w3_closed(const W3Geo& g, double zv, double z1lo, double z1hi, double z2lo, double z2hi, double ta,
                             double tb) {
-    // slope limits T_k(theta) = A_k cos(theta - psi_k): 0 T1lo, 1 T1hi, 2 T2lo, 3 T2hi
-    double A[4], C[4], S[4];
-    A[0] = (z1lo - zv) / g.D1;
-    A[1] = (z1hi - zv) / g.D1;
-    C[0] = C[1] = g.c1;
-    S[0] = S[1] = g.s1;
-    A[2] = (zv - z2hi) / g.D2;
-    A[3] = (zv - z2lo) / g.D2;
-    C[2] = C[3] = -g.c2;  // photon 2 travels along theta + pi
-    S[2] = S[3] = -g.s2;
-    double cut[6];
-    int n = 0;
-    cut[n++] = ta;
-    const double tm = 0.5 * (ta + tb);
-    const int ia[4] = {1, 0, 1, 3}, ib[4] = {3, 2, 2, 0};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = ia[k], j = ib[k];
-        const double p = A[i] * C[i] - A[j] * C[j];
-        const double q = A[i] * S[i] - A[j] * S[j];
-        if (p == 0.0 && q == 0.0) continue;
-        const double th0 = atan2(-p, q);
-        const double r = th0 + rint((tm - th0) / kPi) * kPi;
-        if (r > ta && r < tb) cut[n++] = r;
-    }
-    cut[n++] = tb;
-    for (int i = 1; i < n; ++i) {  // insertion sort (n <= 6)
-        const double v = cut[i];
-        int j = i - 1;
-        while (j >= 0 && cut[j] > v) {
-            cut[j + 1] = cut[j];
-            --j;
-        }
-        cut[j + 1] = v;
-    }
-    double inv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) inv[k] = 1.0 / sqrt(1.0 + A[k] * A[k]);
+    // slope limits T_k(theta) = A_k cos(theta - psi_k): 0 T1lo, 1 T1hi (photon 1, psi = its face normal),
+    // 2 T2lo, 3 T2hi (photon 2 travels along theta + pi: psi = its face normal + pi)
+    const double A0 = (z1lo - zv) / g.D1, A1 = (z1hi - zv) / g.D1;
+    const double A2 = (zv - z2hi) / g.D2, A3 = (zv - z2lo) / g.D2;
+    const double C1 = g.c1, S1 = g.s1, C2 = -g.c2, S2 = -g.s2;
+    // the binding limits switch where T1hi = T2hi, T1lo = T2lo, T1hi = T2lo or T2hi = T1lo
+    double r0 = w3_cut(A1, C1, S1, A3, C2, S2, ta, tb);
+    double r1 = w3_cut(A0, C1, S1, A2, C2, S2, ta, tb);
+    double r2 = w3_cut(A1, C1, S1, A2, C2, S2, ta, tb);
+    double r3 = w3_cut(A3, C2, S2, A0, C1, S1, ta, tb);
+    cswap(r0, r1);
+    cswap(r2, r3);
+    cswap(r0, r2);
+    cswap(r1, r3);
+    cswap(r1, r2);
+    const double i0 = 1.0 / sqrt(1.0 + A0 * A0), i1 = 1.0 / sqrt(1.0 + A1 * A1);
+    const double i2 = 1.0 / sqrt(1.0 + A2 * A2), i3 = 1.0 / sqrt(1.0 + A3 * A3);
     double sum = 0.0;
-    for (int i = 0; i + 1 < n; ++i) {
-        const double a = cut[i], b = cut[i + 1];
-        if (!(b > a)) continue;
-        const double m = 0.5 * (a + b), cm = cos(m), sm = sin(m);
-        double T[4];
+    double a = ta, ca = cos(ta), sa = sin(ta);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) T[k] = A[k] * (cm * C[k] + sm * S[k]);
-        const int hi = T[1] < T[3] ? 1 : 3;
-        const int lo = T[0] > T[2] ? 0 : 2;
-        if (!(T[hi] > T[lo])) continue;
-        const double ca = cos(a), sa = sin(a), cb = cos(b), sb = sin(b);
-        // F(theta) = asin(A sin(theta - psi) / sqrt(1 + A^2)), sin(theta - psi) = sin th C - cos th S
-        const double fhb = asin(A[hi] * (sb * C[hi] - cb * S[hi]) * inv[hi]);
-        const double fha = asin(A[hi] * (sa * C[hi] - ca * S[hi]) * inv[hi]);
-        const double flb = asin(A[lo] * (sb * C[lo] - cb * S[lo]) * inv[lo]);
-        const double fla = asin(A[lo] * (sa * C[lo] - ca * S[lo]) * inv[lo]);
-        sum += (fhb - fha) - (flb - fla);
+    for (int k = 0; k < 5; ++k) {
+        const double b = k == 0 ? r0 : (k == 1 ? r1 : (k == 2 ? r2 : (k == 3 ? r3 : tb)));
+        if (b > a) {
+            const double m = 0.5 * (a + b), cm = cos(m), sm = sin(m);
+            const double T0 = A0 * (cm * C1 + sm * S1), T1 = A1 * (cm * C1 + sm * S1);
+            const double T2 = A2 * (cm * C2 + sm * S2), T3 = A3 * (cm * C2 + sm * S2);
+            const bool h1 = T1 < T3, l0 = T0 > T2;
+            const double Th = h1 ? T1 : T3, Tl = l0 ? T0 : T2;
+            const double cb = cos(b), sb = sin(b);
+            if (Th > Tl) {
+                const double Ah = h1 ? A1 : A3, Ch = h1 ? C1 : C2, Sh = h1 ? S1 : S2, ih = h1 ? i1 : i3;
+                const double Al = l0 ? A0 : A2, Cl = l0 ? C1 : C2, Sl = l0 ? S1 : S2, il = l0 ? i0 : i2;
+                sum += (w3_F(Ah, Ch, Sh, ih, cb, sb) - w3_F(Ah, Ch, Sh, ih, ca, sa)) -
+                       (w3_F(Al, Cl, Sl, il, cb, sb) - w3_F(Al, Cl, Sl, il, ca, sa));
+            }
+            a = b;
+            ca = cb;
+            sa = sb;
+        }
     }
     return sum / (2.0 * kPi);
 }
@@ -461,7 +467,8 @@ __device__ __forceinline__ float bf16r(float x) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D S, Args3D A) {
+// two waves per SIMD: the FP64 geometry needs ~256 registers; fewer spills
+__global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_eu(2))) k_cyl3d_tiles(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ WaveLds wl[kWavesT];
     __shared__ double xacc[kWavesT][8];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -485,8 +492,11 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
         acc[bb] = 0.0;
         xv[bb] = 0.0;
     }
-    if (MODE == kModeFwd)
-        for (int bb = 0; bb < nb; ++bb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
+    if (MODE == kModeFwd) {
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb)
+            if (bb < nb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
+    }
     const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
     double* dense = (MODE == kModeCount || MODE == kModeFill)
                         ? S.dense + (int64_t)vb * S.cap_slots * G.NR * G.NR : nullptr;
@@ -552,6 +562,7 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
             for (int e = lane; e < kMaxK * kMaxK; e += 64) L.W[e >> 4][e & 15] = 0.0f;
             __builtin_amdgcn_wave_barrier();
             int any = 0;
+#pragma unroll 1
             for (int e = lane; e < nsmp * K; e += 64) {
                 const int k = e / K, pz1 = (e / P) % P, pz2 = e % P;
                 const double z1lo = G.z0 + (r1 + (double)pz1 / P) * G.lz;
@@ -631,12 +642,14 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
                 const int64_t tb_ = tbin_of(gi, gj, G.Nc);
                 if (MODE == kModeFwd) {
                     const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-                    for (int bb = 0; bb < nb; ++bb)
-                        if (xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
                 } else if (MODE == kModeAdj) {
                     const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-                    for (int bb = 0; bb < nb; ++bb)
-                        acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
                 } else {
                     const int slot = smap[tb_];
                     if (slot < 0) {
@@ -651,7 +664,9 @@ __global__ void __launch_bounds__(64 * kWavesT) k_cyl3d_tiles(Cyl3D G, Scratch3D
     }
     if (flag) atomicOr(A.status, flag);
     if (MODE == kModeAdj) {
-        for (int bb = 0; bb < nb; ++bb) {
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+            if (bb >= nb) break;
             double s = acc[bb];
             for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
             if (lane == 0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], s);
