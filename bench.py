@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32
 FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64
+FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix cores
+BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
 
 
 def parse():
@@ -135,7 +137,9 @@ def main():
         log(f"step {i + 1}: build {rec['build'][-1]:.1f} ms, fwd {rec['fwd'][-1]:.1f} ms, adj {rec['adj'][-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    k_ms, k_launches = sc.profile_stop()
+    prof = sc.profile_stop()
+    k_ms, k_launches = prof["contraction"]
+    g_ms, g_launches = prof["geometry"]
 
     build_s = sum(rec["build"]) / 1e3
     proj_s = (sum(rec["fwd"]) + sum(rec["adj"])) / 1e3
@@ -163,14 +167,19 @@ def main():
     avg_ms = k_ms / max(k_launches, 1)
     if meta["mode3d"]:
         K = cfg["n_sub"] ** 2
-        flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X
+        flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X (unpadded)
         tiles_per_launch = rec["tiles"] / max(k_launches, 1)
         achieved = tiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / FP32_VALU_TFLOPS, "traffic": None,
-                           "kernel": "k_cyl3d_tiles (tile contraction T = U^T W V, FP32 VALU)",
+        peak = [FP32_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS][prec]
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                           "frac": achieved / peak, "traffic": None,
+                           "kernel": "k_cyl3d_mma (tile contraction T = U^T (W V) on matrix cores, "
+                                     + ["FP32", "BF16", "BF16 hi/lo"][prec] + ")",
                            "avg_launch_ms": avg_ms, "launches": k_launches,
                            "tiles_per_launch": tiles_per_launch, "flops_per_tile": flops_tile}
+        out["geometry_kernel"] = {"kernel": "k_cyl3d_geom (FP64 homogenization weights and response rows)",
+                                  "total_ms_per_step": g_ms / steps, "launches": g_launches,
+                                  "contraction_total_ms_per_step": k_ms / steps}
     else:
         # the per-voxel sweep kernel; algorithmic HBM bytes = the CSR it writes
         algo = nnz * 8 + (sc.n_voxels + 1) * 8

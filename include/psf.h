@@ -180,12 +180,14 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
  * workspace (PSF_ERANGE if an incidence angle fell beyond the table). */
 int psf_check(psf_handle* h, void* workspace_dev, void* stream);
 
-/* Timing of the contraction kernels (the 2D per-voxel sweep kernel, the 3D
- * tile kernel), for measurement.  enable = 1 clears and starts recording a
- * pair of HIP events around each such launch on its stream; enable = 0 waits
- * for them, writes the summed elapsed milliseconds and the number of launches,
- * and stops recording.  In 3D the workspace holds at byte 64 a uint64 count of
- * the tiles contracted by the last call. */
+/* Timing of the kernels, for measurement.  enable = 1 clears and starts
+ * recording a pair of HIP events around each launch of the contraction
+ * kernels (the 2D per-voxel sweep, the 3D matrix-core tile contraction) and of
+ * the 3D tile-geometry kernel, on the stream they run on; enable = 0 waits for
+ * them and writes ms[0], launches[0] (contraction) and ms[1], launches[1]
+ * (3D geometry): summed elapsed milliseconds and launch counts.  ms and
+ * launches point to two entries each (either may be NULL).  In 3D the
+ * workspace holds at byte 64 a uint64 count of the tiles of the last call. */
 int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches);
 
 const char* psf_status_string(int status);

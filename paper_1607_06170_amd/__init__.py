@@ -218,10 +218,10 @@ class Scanner:
         check(self.L.psf_profile(self.h, 1, None, None), "psf_profile")
 
     def profile_stop(self):
-        """(milliseconds summed over recorded launches, number of launches)."""
-        ms, n = C.c_double(), C.c_int64()
-        check(self.L.psf_profile(self.h, 0, C.byref(ms), C.byref(n)), "psf_profile")
-        return ms.value, n.value
+        """{'contraction': (ms, launches), 'geometry': (ms, launches)} summed over recorded launches."""
+        ms, n = (C.c_double * 2)(), (C.c_int64 * 2)()
+        check(self.L.psf_profile(self.h, 0, C.cast(ms, C.c_void_p), C.cast(n, C.c_void_p)), "psf_profile")
+        return {"contraction": (ms[0], n[0]), "geometry": (ms[1], n[1])}
 
     def tiles_last_call(self) -> int:
         """Tiles contracted by the last 3D call (from the workspace header)."""

@@ -73,7 +73,7 @@ SIGNATURES = {
     "psf_lm_osem_update": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int64, C.c_float, _P,
                                      C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "psf_check": (C.c_int, [_H, _P, _P]),
-    "psf_profile": (C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "psf_profile": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_void_p]),
     "psf_status_string": (C.c_char_p, [C.c_int]),
     "psf_last_hip_error": (C.c_int, []),
 }

@@ -470,34 +470,43 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
 
 int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches) {
     if (!h) return PSF_EINVAL;
-    if (enable) {
+    auto clear = [h]() {
         for (auto& e : h->prof_ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
         h->prof_ev.clear();
+        h->prof_kind.clear();
+    };
+    if (enable) {
+        clear();
         h->prof_on = true;
         return PSF_OK;
     }
-    double tot = 0.0;
+    double tot[2] = {0.0, 0.0};
+    int64_t cnt[2] = {0, 0};
     int st = PSF_OK;
-    for (auto& e : h->prof_ev) {
+    for (size_t i = 0; i < h->prof_ev.size(); ++i) {
         float t = 0.0f;
-        hipError_t r = hipEventSynchronize(e.second);
-        if (r == hipSuccess) r = hipEventElapsedTime(&t, e.first, e.second);
+        hipError_t r = hipEventSynchronize(h->prof_ev[i].second);
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, h->prof_ev[i].first, h->prof_ev[i].second);
         if (r != hipSuccess) {
             psf::g_last_hip = (int)r;
             st = PSF_EHIP;
         }
-        tot += t;
+        const int k = h->prof_kind[i] ? 1 : 0;
+        tot[k] += t;
+        cnt[k] += 1;
     }
-    if (ms) *ms = tot;
-    if (launches) *launches = (int64_t)h->prof_ev.size();
-    for (auto& e : h->prof_ev) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+    if (ms) {
+        ms[0] = tot[0];
+        ms[1] = tot[1];
     }
-    h->prof_ev.clear();
+    if (launches) {
+        launches[0] = cnt[0];
+        launches[1] = cnt[1];
+    }
+    clear();
     h->prof_on = false;
     return st;
 }

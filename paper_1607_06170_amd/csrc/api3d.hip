@@ -9,10 +9,11 @@ using namespace psf;
 namespace {
 
 constexpr int kBatchCsr = 16;     // voxels per batch of the matrix build (dense accumulators)
-constexpr int kBatchProj = 1024;  // voxels per batch of the projections
+constexpr int kBatchProj = 64;    // voxels per batch of the projections (tile records)
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
+constexpr int64_t kRecsPerVoxel = 32768;  // tile-record capacity per voxel of a batch
 
 Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
     Cyl3D G;
@@ -55,13 +56,15 @@ int check3d(const psf_handle* h, const psf_table* t) {
     const int64_t nseg = (int64_t)h->g.n_blocks * h->g.n_cryst_t * t->n_sub;
     if (nseg >= 32768) return PSF_EUNSUPPORTED;
     if (h->n_bins >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;  // bins are int32 CSR columns
+    if ((int64_t)h->g.n_cryst_z * h->g.n_block_rings > 255) return PSF_EUNSUPPORTED;  // rings fit a byte of the tile record
     return PSF_OK;
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, x64, y32, h64, h32, back, total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, x64, y32, h64, h32, back, total;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
+    int64_t cap_recs;
 };
 
 Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
@@ -91,6 +94,14 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     L.chunks = off;
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
     off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
+    {
+        const int64_t per_vox = Nc * NR * 2 < kRecsPerVoxel ? (Nc * NR * 2 > 1024 ? Nc * NR * 2 : 1024) : kRecsPerVoxel;
+        L.cap_recs = per_vox * L.bmax;
+    }
+    L.recs = off;
+    off += align256(sizeof(float) * (size_t)L.cap_recs * kRecFloats);
+    L.reccount = off;
+    off += align256(sizeof(unsigned int));
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.y32 = L.h64 = L.h32 = L.back = off;
@@ -130,6 +141,9 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.dense = at3<double>(ws, L.dense);
     S.chunk_counts = at3<int>(ws, L.chunks);
     S.max_chunks = L.max_chunks;
+    S.recs = at3<float>(ws, L.recs);
+    S.rec_count = at3<unsigned int>(ws, L.reccount);
+    S.cap_recs = L.cap_recs;
     return S;
 }
 
@@ -151,8 +165,12 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
             {
-                ProfScope ps_(h, s);
-                HIP_TRY(launch_cyl3d_tiles(kModeFwd, G, S, a, s));
+                ProfScope pg_(h, s, 1);
+                HIP_TRY(launch_cyl3d_geom(G, S, a, s));
+            }
+            {
+                ProfScope pm_(h, s, 0);
+                HIP_TRY(launch_cyl3d_mma(kModeFwd, G, S, a, s));
             }
         }
     }
@@ -178,8 +196,12 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
             {
-                ProfScope ps_(h, s);
-                HIP_TRY(launch_cyl3d_tiles(kModeAdj, G, S, a, s));
+                ProfScope pg_(h, s, 1);
+                HIP_TRY(launch_cyl3d_geom(G, S, a, s));
+            }
+            {
+                ProfScope pm_(h, s, 0);
+                HIP_TRY(launch_cyl3d_mma(kModeAdj, G, S, a, s));
             }
         }
     }
@@ -235,8 +257,12 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
         HIP_TRY(launch_cyl3d_transaxial(G, S, a, 1, s));
         {
-            ProfScope ps_(h, s);
-            HIP_TRY(launch_cyl3d_tiles(kModeCount, G, S, a, s));
+            ProfScope pg_(h, s, 1);
+            HIP_TRY(launch_cyl3d_geom(G, S, a, s));
+        }
+        {
+            ProfScope pm_(h, s, 0);
+            HIP_TRY(launch_cyl3d_mma(kModeCount, G, S, a, s));
         }
         HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, S, a, s));
     }

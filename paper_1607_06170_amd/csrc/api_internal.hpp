@@ -16,9 +16,10 @@ struct psf_handle {
     int64_t n_crystals, n_bins, n_vox;
     double sigma;
     double* frames_dev;  // [R][2] cos, sin of each block's outward normal
-    // HIP-event timing of the contraction kernels (psf_profile)
+    // HIP-event timing of the contraction (kind 0) and 3D geometry (kind 1) kernels (psf_profile)
     bool prof_on;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    std::vector<int> prof_kind;
 };
 
 // bracket one launch of the contraction kernel with events when profiling
@@ -26,19 +27,20 @@ struct ProfScope {
     psf_handle* h;
     hipStream_t s;
     hipEvent_t e1;
-    ProfScope(psf_handle* h_, hipStream_t s_) : h(h_), s(s_), e1(nullptr) {
+    ProfScope(psf_handle* h_, hipStream_t s_, int kind = 0) : h(h_), s(s_), e1(nullptr) {
         if (h->prof_on) {
             hipEvent_t e0;
-            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-                hipEventRecord(e0, s);
+            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+                hipEventRecord(e0, s) == hipSuccess) {
                 h->prof_ev.emplace_back(e0, e1);
+                h->prof_kind.push_back(kind);
             } else {
                 e1 = nullptr;
             }
         }
     }
     ~ProfScope() {
-        if (e1) hipEventRecord(e1, s);
+        if (e1) (void)hipEventRecord(e1, s);
     }
 };
 

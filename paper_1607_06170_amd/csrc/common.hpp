@@ -61,7 +61,13 @@ struct Scratch3D {
     double* dense;     // [B][cap_slots][NR * NR]
     int* chunk_counts; // [B][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
+    float* recs;       // [cap_recs][kRecFloats]  tile records (header, W, U, V)
+    unsigned int* rec_count;
+    int64_t cap_recs;
 };
+
+// tile record: 4 header ints (g1, g2, r1 | r2 << 8 | voxel << 16, 0), W[16][16], U[16][25], V[16][25]
+constexpr int kRecFloats = 4 + 256 + 400 + 400;
 
 struct Args3D {
     int64_t vox_begin;  // first voxel of this batch
@@ -133,7 +139,8 @@ enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad =
 hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st);
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
                                    hipStream_t st);
-hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 int64_t cyl3d_max_chunks(int cap_slots, int NR);

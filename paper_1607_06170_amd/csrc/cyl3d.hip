@@ -29,6 +29,10 @@
 
 namespace psf {
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
 constexpr double kEpsW3 = 1e-14;  // weights at or below this fraction of the sphere are empty
 constexpr int kMaxK = 16;         // P^2 sub-patches per crystal face (P <= 4)
 
@@ -223,6 +227,7 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     const int vb = blockIdx.x;
     const int64_t v = A.vox_begin + vb;
     const int M1 = G.nc * G.P + 1, spb = G.nc * G.P;
+    if (vb == 0 && tid == 0) *S.rec_count = 0u;  // the batch's tile records start empty
     double* th = (double*)smem3;                    // [R * M1]
     double* unw = th + G.R * M1;                    // [nseg]
     int* cnt = (int*)(unw + G.nseg);                // [nseg + 1]
@@ -443,8 +448,12 @@ hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Arg
 }
 
 // ---------------------------------------------------------------------------
-// K2: tiles
+// K2a: tile geometry (FP64) -> tile records
 // ---------------------------------------------------------------------------
+// One wavefront per (crystal pair, ring r1) task.  For every ring r2 the lines
+// reach it computes the P^2 x P^2 weights W and, when any is non-zero, the
+// response rows U (g1, r1) and V (g2, r2); the tile is appended to the record
+// buffer for the contraction kernel.
 
 constexpr int kWavesT = 4;
 constexpr int kPairsPerWG = 8;
@@ -453,7 +462,6 @@ struct WaveLds {
     float W[kMaxK][kMaxK + 1];
     float U[kMaxK][25];
     float V[kMaxK][25];
-    float X[kMaxK][25];
     double ta[kMaxK], tb[kMaxK];
     double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
     int pt1[kMaxK], pt2[kMaxK];
@@ -466,11 +474,10 @@ __device__ __forceinline__ float bf16r(float x) {
     return __uint_as_float(u & 0xffff0000u);
 }
 
-template <int MODE>
-// two waves per SIMD: the FP64 geometry needs ~256 registers; fewer spills
-__global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_eu(2))) k_cyl3d_tiles(Cyl3D G, Scratch3D S, Args3D A) {
+// two waves per SIMD: the FP64 geometry needs ~256 registers
+__global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_eu(2)))
+k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ WaveLds wl[kWavesT];
-    __shared__ double xacc[kWavesT][8];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int vb = blockIdx.y;
     const int64_t v = A.vox_begin + vb;
@@ -485,21 +492,6 @@ __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_
     const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
     double vx, vy, vz;
     voxel_xyz(G, v, vx, vy, vz);
-    double xv[8];
-    double acc[8];
-    const int nb = A.batch < 8 ? A.batch : 8;
-    for (int bb = 0; bb < 8; ++bb) {
-        acc[bb] = 0.0;
-        xv[bb] = 0.0;
-    }
-    if (MODE == kModeFwd) {
-#pragma unroll
-        for (int bb = 0; bb < 8; ++bb)
-            if (bb < nb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
-    }
-    const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
-    double* dense = (MODE == kModeCount || MODE == kModeFill)
-                        ? S.dense + (int64_t)vb * S.cap_slots * G.NR * G.NR : nullptr;
     int flag = 0;
     const int ntask = (pair1 - pair0) * G.NR;
     for (int t = wid; t < ntask; t += kWavesT) {
@@ -587,7 +579,6 @@ __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_
                 }
             }
             if (!__any(any)) continue;
-            if (lane == 0 && A.tiles) atomicAdd(A.tiles, 1ull);
             __builtin_amdgcn_wave_barrier();
             // response rows: lanes 0..K-1 -> U (g1, r1), lanes 32..32+K-1 -> V (g2, r2)
             if (lane < K) {
@@ -595,6 +586,10 @@ __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_
             } else if (lane >= 32 && lane < 32 + K) {
                 const int l = lane - 32;
                 L.urange[kMaxK + l] = uv_row3(G, vx, vy, vz, g2, l / P, r2, l % P, L.V[l]);
+            } else if (lane < kMaxK) {  // rows beyond P^2 take no part in the contraction
+                for (int q = 0; q < 25; ++q) L.U[lane][q] = 0.0f;
+            } else if (lane >= 32 && lane < 32 + kMaxK) {
+                for (int q = 0; q < 25; ++q) L.V[lane - 32][q] = 0.0f;
             }
             __builtin_amdgcn_wave_barrier();
             // range errors count only for rows that carry weight
@@ -606,87 +601,197 @@ __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_
                 }
                 if ((rs != 0.0f && L.urange[lane]) || (cs_ != 0.0f && L.urange[kMaxK + lane])) flag |= kStatRange;
             }
-            // X = W V (K x 25)
-            for (int e = lane; e < K * 25; e += 64) {
-                const int p = e / 25, bq = e % 25;
-                float s = 0.0f;
-                for (int q = 0; q < K; ++q) s = fmaf(L.W[p][q], L.V[q][bq], s);
-                L.X[p][bq] = s;
+            // append the tile record: header, W (16 x 16), U (16 x 25), V (16 x 25)
+            unsigned int slot = 0;
+            if (lane == 0) slot = atomicAdd(S.rec_count, 1u);
+            slot = __shfl(slot, 0, 64);
+            if (slot >= (unsigned int)S.cap_recs) {
+                flag |= kStatScratch;
+                continue;
             }
-            __builtin_amdgcn_wave_barrier();
-            // T = U^T X (25 x 25), emitted entry by entry
-            for (int e = lane; e < 625; e += 64) {
-                const int a = e / 25, bq = e % 25;
-                float t = 0.0f;
-                if (G.precision == PSF_FP32) {
-                    for (int p = 0; p < K; ++p) t = fmaf(L.U[p][a], L.X[p][bq], t);
-                } else if (G.precision == PSF_BF16) {
-                    for (int p = 0; p < K; ++p) t = fmaf(bf16r(L.U[p][a]), bf16r(L.X[p][bq]), t);
-                } else {
-                    for (int p = 0; p < K; ++p) {
-                        const float uh = bf16r(L.U[p][a]), ul = bf16r(L.U[p][a] - uh);
-                        const float xh = bf16r(L.X[p][bq]), xl = bf16r(L.X[p][bq] - xh);
-                        t = fmaf(uh, xh, fmaf(uh, xl, fmaf(ul, xh, t)));
-                    }
-                }
-                if (t == 0.0f) continue;
-                const int at = a / 5 - 2, az = a % 5 - 2, bt = bq / 5 - 2, bz = bq % 5 - 2;
-                const int ra = r1 + az, rb = r2 + bz;
-                if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) continue;
-                int ga = g1 + at, gb = g2 + bt;
-                ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
-                gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-                if (ga == gb) continue;
-                const bool sw = ga > gb;
-                const int gi = sw ? gb : ga, gj = sw ? ga : gb, ri = sw ? rb : ra, rj = sw ? ra : rb;
-                const int64_t tb_ = tbin_of(gi, gj, G.Nc);
-                if (MODE == kModeFwd) {
-                    const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-#pragma unroll
-                    for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
-                } else if (MODE == kModeAdj) {
-                    const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-#pragma unroll
-                    for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
-                } else {
-                    const int slot = smap[tb_];
-                    if (slot < 0) {
-                        flag |= kStatScratch;
-                        continue;
-                    }
-                    atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], (double)t);
-                }
+            if (lane == 0 && A.tiles) atomicAdd(A.tiles, 1ull);
+            float* rec = S.recs + (int64_t)slot * kRecFloats;
+            if (lane == 0) {
+                int* h = (int*)rec;
+                h[0] = g1;
+                h[1] = g2;
+                h[2] = r1 | (r2 << 8) | (vb << 16);
+                h[3] = 0;
             }
+            for (int e = lane; e < 256; e += 64) rec[4 + e] = L.W[e >> 4][e & 15];
+            for (int e = lane; e < 400; e += 64) rec[260 + e] = L.U[e / 25][e % 25];
+            for (int e = lane; e < 400; e += 64) rec[660 + e] = L.V[e / 25][e % 25];
             __builtin_amdgcn_wave_barrier();
         }
     }
     if (flag) atomicOr(A.status, flag);
-    if (MODE == kModeAdj) {
-#pragma unroll
-        for (int bb = 0; bb < 8; ++bb) {
-            if (bb >= nb) break;
-            double s = acc[bb];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-            if (lane == 0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], s);
-        }
-    }
 }
 
-hipError_t launch_cyl3d_tiles(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// K2b: tile contraction on matrix cores, and emission
+// ---------------------------------------------------------------------------
+// Persistent wavefronts walk the record buffer.  Per tile:
+//   X = W V      (16 x 32, FP32 matrix cores: v_mfma_f32_16x16x4_f32, two column blocks)
+//   T = U^T X    (32 x 32 padded from 25 x 25): FP32 form v_mfma_f32_32x32x2_f32 (8 steps);
+//                BF16 form one v_mfma_f32_32x32x16_bf16 with U and X rounded to BF16;
+//                hi/lo form adds U_hi X_lo and U_lo X_hi (three bf16 MFMAs).
+// Lane l holds T[8(j/4) + 4(l/32) + j%4][l%32] in accumulator j: its column
+// b = l%32 fixes the photon-2 crystal, its 16 rows the photon-1 crystals.
+
+struct MmaLds {
+    float W[16][17];
+    float U[16][25];
+    float V[16][25];
+    float X[16][32];
+};
+
+constexpr int kWavesM = 4;
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
+    __shared__ MmaLds ml[kWavesM];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    MmaLds& L = ml[wid];
+    const unsigned int nrec = min(*S.rec_count, (unsigned int)S.cap_recs);
+    const unsigned int wave0 = blockIdx.x * kWavesM + wid, nwaves = gridDim.x * kWavesM;
+    const int nb = A.batch < 8 ? A.batch : 8;
+    int flag = 0;
+    const int m = lane & 31, hk = lane >> 5;
+    for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
+        const float* rec = S.recs + (int64_t)idx * kRecFloats;
+        const int* h = (const int*)rec;
+        const int g1 = h[0], g2 = h[1], r1 = h[2] & 0xff, r2 = (h[2] >> 8) & 0xff, vb = h[2] >> 16;
+        const int64_t v = A.vox_begin + vb;
+        for (int e = lane; e < 256; e += 64) L.W[e >> 4][e & 15] = rec[4 + e];
+        for (int e = lane; e < 400; e += 64) L.U[e / 25][e % 25] = rec[260 + e];
+        for (int e = lane; e < 400; e += 64) L.V[e / 25][e % 25] = rec[660 + e];
+        __builtin_amdgcn_wave_barrier();
+        // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
+#pragma unroll
+        for (int n0 = 0; n0 < 32; n0 += 16) {
+            v4f cx = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int col = n0 + (lane & 15);
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int k = kk + (lane >> 4);
+                const float a = L.W[lane & 15][k];
+                const float b = col < 25 ? L.V[k][col] : 0.0f;
+                cx = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cx, 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) L.X[4 * (lane >> 4) + j][col] = cx[j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        v16f ct;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) ct[j] = 0.0f;
+        if (G.precision == PSF_FP32) {
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 2) {
+                const float a = m < 25 ? L.U[kk + hk][m] : 0.0f;
+                ct = __builtin_amdgcn_mfma_f32_32x32x2f32(a, L.X[kk + hk][m], ct, 0, 0, 0);
+            }
+        } else {
+            v8bf ah, bh, al, bl;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float u = m < 25 ? L.U[8 * hk + i][m] : 0.0f;
+                const float x = L.X[8 * hk + i][m];
+                const float uh = bf16r(u), xh = bf16r(x);
+                ah[i] = (__bf16)uh;
+                bh[i] = (__bf16)xh;
+                al[i] = (__bf16)bf16r(u - uh);
+                bl[i] = (__bf16)bf16r(x - xh);
+            }
+            ct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, ct, 0, 0, 0);
+            if (G.precision == PSF_BF16X2) {
+                ct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, ct, 0, 0, 0);
+                ct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, ct, 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // emission
+        double xv[8], acc[8];
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+            acc[bb] = 0.0;
+            xv[bb] = (MODE == kModeFwd && bb < nb) ? (double)A.x[(int64_t)bb * G.nvox + v] : 0.0;
+        }
+        const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
+        double* dense = (MODE == kModeCount || MODE == kModeFill)
+                            ? S.dense + (int64_t)vb * S.cap_slots * G.NR * G.NR : nullptr;
+        const int bq = m;
+        const int bt = bq / 5 - 2, bz = bq % 5 - 2;
+        const int rb = r2 + bz;
+        int gb = g2 + bt;
+        gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+        const bool col_ok = bq < 25 && rb >= 0 && rb < G.NR;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
+            const float t = ct[j];
+            if (!col_ok || a >= 25 || t == 0.0f) continue;
+            const int at = a / 5 - 2, az = a % 5 - 2;
+            const int ra = r1 + az;
+            if (ra < 0 || ra >= G.NR) continue;
+            int ga = g1 + at;
+            ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+            if (ga == gb) continue;
+            const bool sw = ga > gb;
+            const int gi = sw ? gb : ga, gj = sw ? ga : gb, ri = sw ? rb : ra, rj = sw ? ra : rb;
+            const int64_t tb_ = tbin_of(gi, gj, G.Nc);
+            if (MODE == kModeFwd) {
+                const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb)
+                    if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
+            } else if (MODE == kModeAdj) {
+                const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb)
+                    if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
+            } else {
+                const int slot = smap[tb_];
+                if (slot < 0) {
+                    flag |= kStatScratch;
+                    continue;
+                }
+                atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], (double)t);
+            }
+        }
+        if (MODE == kModeAdj) {
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                if (bb >= nb) break;
+                double sacc = acc[bb];
+                for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
+                if (lane == 0 && sacc != 0.0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], sacc);
+            }
+        }
+    }
+    if (flag) atomicOr(A.status, flag);
+}
+
+hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_vox <= 0) return hipSuccess;
     const dim3 grid((S.cap_pairs + kPairsPerWG - 1) / kPairsPerWG, a.n_vox), block(64 * kWavesT);
+    hipLaunchKernelGGL(k_cyl3d_geom, grid, block, 0, st, G, S, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
+    if (a.n_vox <= 0) return hipSuccess;
+    const dim3 grid(2048), block(64 * kWavesM);
     switch (mode) {
         case kModeCount:
         case kModeFill:
-            hipLaunchKernelGGL(k_cyl3d_tiles<kModeCount>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeCount>, grid, block, 0, st, G, S, a);
             break;
         case kModeFwd:
-            hipLaunchKernelGGL(k_cyl3d_tiles<kModeFwd>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeFwd>, grid, block, 0, st, G, S, a);
             break;
         case kModeAdj:
-            hipLaunchKernelGGL(k_cyl3d_tiles<kModeAdj>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdj>, grid, block, 0, st, G, S, a);
             break;
         default:
             return hipErrorInvalidValue;
