@@ -1,6 +1,9 @@
 // 3D-scanner halves of the C-ABI entry points: argument checks, workspace
 // carving and the batched launches of the cyl3d.hip kernels.
+#include <math.h>
 #include <string.h>
+
+#include <vector>
 
 #include "api_internal.hpp"
 
@@ -8,12 +11,13 @@ using namespace psf;
 
 namespace {
 
-constexpr int kBatchCsr = 16;     // voxels per batch of the matrix build (dense accumulators)
-constexpr int kBatchProj = 64;    // voxels per batch of the projections (tile records)
+constexpr int kBatchCsr = 48;     // voxels per batch of the matrix build (dense accumulators)
+constexpr int kBatchProj = 128;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
-constexpr int64_t kRecsPerVoxel = 32768;  // tile-record capacity per voxel of a batch
+constexpr int64_t kRecsPerVoxel = 32768;   // tile records allowed for one voxel
+constexpr int64_t kRecBudget = 1 << 19;    // tile records per batch (4.2 KB each)
 
 Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
     Cyl3D G;
@@ -56,15 +60,18 @@ int check3d(const psf_handle* h, const psf_table* t) {
     const int64_t nseg = (int64_t)h->g.n_blocks * h->g.n_cryst_t * t->n_sub;
     if (nseg >= 32768) return PSF_EUNSUPPORTED;
     if (h->n_bins >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;  // bins are int32 CSR columns
-    if ((int64_t)h->g.n_cryst_z * h->g.n_block_rings > 255) return PSF_EUNSUPPORTED;  // rings fit a byte of the tile record
+    // tile records hold rings offset by 512 in 10 bits, and voxel ids are int32 in the batch plans
+    if ((int64_t)h->g.n_cryst_z * h->g.n_block_rings > 255) return PSF_EUNSUPPORTED;
+    if (h->n_vox >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;
     return PSF_OK;
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, x64, y32, h64, h32, back, total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, plan, x64, y32, h64, h32, back,
+        total;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
-    int64_t cap_recs;
+    int64_t cap_recs, per_vox;
 };
 
 Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
@@ -95,13 +102,16 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
     off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
     {
-        const int64_t per_vox = Nc * NR * 2 < kRecsPerVoxel ? (Nc * NR * 2 > 1024 ? Nc * NR * 2 : 1024) : kRecsPerVoxel;
-        L.cap_recs = per_vox * L.bmax;
+        L.per_vox = Nc * NR * 2 < kRecsPerVoxel ? (Nc * NR * 2 > 1024 ? Nc * NR * 2 : 1024) : kRecsPerVoxel;
+        L.cap_recs = L.per_vox * L.bmax < kRecBudget ? L.per_vox * L.bmax : kRecBudget;
+        if (L.cap_recs < L.per_vox) L.cap_recs = L.per_vox;
     }
     L.recs = off;
     off += align256(sizeof(float) * (size_t)L.cap_recs * kRecFloats);
     L.reccount = off;
     off += align256(sizeof(unsigned int));
+    L.plan = off;  // classes and members of every batch: two int4 per voxel at most
+    off += align256(2 * sizeof(int4) * (size_t)h->n_vox);
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.y32 = L.h64 = L.h32 = L.back = off;
@@ -147,21 +157,116 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     return S;
 }
 
+// ---------------------------------------------------------------------------
+// classes of voxels and batches
+// ---------------------------------------------------------------------------
+// A class is a run of voxels of one z-column, iz = iz0 + m s for s = 0, 1, ...,
+// where m dz is the ring pitch: the scanner seen from member s is the one seen
+// from the reference (s = 0) moved by s rings.  When the pitch is not a whole
+// number of voxels every voxel is its own class.  Classes are cut to at most
+// `cmax` members and packed into batches of at most `bmax` members whose tile
+// record estimates fit the record buffer.
+
+struct Batch3 {
+    int cls0, ncls, mem0, nmem;
+};
+
+struct Plan3 {
+    std::vector<int4> cls, mem;  // cls: reference voxel, first member (batch-relative), count, largest shift
+    std::vector<Batch3> batches; // mem: voxel, shift, class (batch-relative), CSR row
+};
+
+int64_t class_recs(const Ws3& L, int64_t NR, int n) {
+    return (L.per_vox * (NR + n - 1) + NR - 1) / NR;
+}
+
+Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax) {
+    Plan3 pl;
+    const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    int64_t m = 0;
+    const double q = nearbyint(h->g.pitch_z / h->im.dz);
+    if (q >= 1.0 && q < 1e6 && fabs(q * h->im.dz - h->g.pitch_z) <= 1e-12 * h->g.pitch_z) m = (int64_t)q;
+    int cmax = bmax;
+    while (cmax > 1 && class_recs(L, NR, cmax) > L.cap_recs) --cmax;
+    Batch3 cur = {0, 0, 0, 0};
+    int64_t cur_recs = 0;
+    auto add_class = [&](int64_t v0, int64_t step, int n) {
+        const int64_t need = class_recs(L, NR, n);
+        if (cur.nmem > 0 && (cur.nmem + n > bmax || cur_recs + need > L.cap_recs)) {
+            pl.batches.push_back(cur);
+            cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0};
+            cur_recs = 0;
+        }
+        pl.cls.push_back(make_int4((int)v0, cur.nmem, n, n - 1));
+        for (int k = 0; k < n; ++k) {
+            const int64_t v = v0 + k * step;
+            pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
+        }
+        cur.ncls += 1;
+        cur.nmem += n;
+        cur_recs += need;
+    };
+    for (int64_t ixy = 0; ixy < nxy; ++ixy) {
+        // z range of this column inside [vb, ve)
+        int64_t zlo = vb - ixy <= 0 ? 0 : (vb - ixy + nxy - 1) / nxy;
+        int64_t zhi = ve - 1 - ixy < 0 ? -1 : (ve - 1 - ixy) / nxy;
+        if (zhi > nz - 1) zhi = nz - 1;
+        if (zlo > zhi) continue;
+        if (m == 0) {
+            for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(ixy + iz * nxy, 0, 1);
+            continue;
+        }
+        for (int64_t c = 0; c < m && zlo + c <= zhi; ++c) {
+            const int64_t n_all = (zhi - (zlo + c)) / m + 1;
+            for (int64_t k0 = 0; k0 < n_all; k0 += cmax) {
+                const int n = (int)(n_all - k0 < cmax ? n_all - k0 : cmax);
+                add_class(ixy + (zlo + c + k0 * m) * nxy, m * nxy, n);
+            }
+        }
+    }
+    if (cur.nmem > 0) pl.batches.push_back(cur);
+    return pl;
+}
+
+// copies the plan into the workspace; returns the device arrays
+int upload_plan(const Plan3& pl, void* ws, const Ws3& L, hipStream_t s, const int4** dcls, const int4** dmem) {
+    int4* c = at3<int4>(ws, L.plan);
+    int4* mm = c + pl.cls.size();
+    if (!pl.cls.empty()) {
+        HIP_TRY(hipMemcpyAsync(c, pl.cls.data(), sizeof(int4) * pl.cls.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(mm, pl.mem.data(), sizeof(int4) * pl.mem.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope after the call
+    }
+    *dcls = c;
+    *dmem = mm;
+    return PSF_OK;
+}
+
+void set_batch(Args3D& a, const Batch3& b, const int4* dcls, const int4* dmem) {
+    a.cls = dcls + b.cls0;
+    a.mem = dmem + b.mem0;
+    a.n_cls = b.ncls;
+    a.n_mem = b.nmem;
+}
+
 // y[batch][n_bins] (FP32, accumulated with atomics) += A x over every voxel
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              void* ws, hipStream_t s) {
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
+    const int4 *dcls, *dmem;
+    int st = upload_plan(pl, ws, L, s, &dcls, &dmem);
+    if (st) return st;
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
-        for (int64_t v0 = 0; v0 < h->n_vox; v0 += L.bmax) {
+        for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
-            a.vox_begin = v0;
-            a.n_vox = (int)(h->n_vox - v0 < L.bmax ? h->n_vox - v0 : L.bmax);
+            set_batch(a, bt, dcls, dmem);
             a.batch = nb;
             a.x = x + (int64_t)b0 * h->n_vox;
             a.y = y + (int64_t)b0 * h->n_bins;
             a.status = (int*)ws;
-        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
             {
@@ -180,19 +285,21 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // x64[batch][n_voxels] += A^T y (y FP32 [batch][n_bins], or all ones)
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, void* ws, hipStream_t s) {
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
+    const int4 *dcls, *dmem;
+    int st = upload_plan(pl, ws, L, s, &dcls, &dmem);
+    if (st) return st;
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
-        for (int64_t v0 = 0; v0 < h->n_vox; v0 += L.bmax) {
+        for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
-            a.vox_begin = v0;
-            a.n_vox = (int)(h->n_vox - v0 < L.bmax ? h->n_vox - v0 : L.bmax);
+            set_batch(a, bt, dcls, dmem);
             a.batch = nb;
             a.yin = ones ? nullptr : y + (int64_t)b0 * h->n_bins;
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
-        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
             {
@@ -242,12 +349,13 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     HIP_TRY(launch_zero_f64(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
     // the count phase adds each chunk's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
-    for (int64_t v0 = vb; v0 < ve; v0 += L.bcsr) {
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
+    const int4 *dcls, *dmem;
+    if ((st = upload_plan(pl, ws, L, s, &dcls, &dmem))) return st;
+    for (const Batch3& bt : pl.batches) {
         Args3D a;
         memset(&a, 0, sizeof(a));
-        a.vox_begin = v0;
-        a.n_vox = (int)(ve - v0 < L.bcsr ? ve - v0 : L.bcsr);
-        a.row_base = v0 - vb;
+        set_batch(a, bt, dcls, dmem);
         a.batch = 1;
         a.threshold = o->threshold;
         a.row_ptr = csr->row_ptr;

@@ -50,29 +50,38 @@ struct Cyl3D {
 // Per-voxel scratch of the 3D kernels (a batch of B voxels at a time).
 struct Scratch3D {
     int cap_samples, cap_pairs, cap_slots;
-    int* n_samples;    // [B]
-    int* n_pairs;      // [B]
-    int* n_slots;      // [B]
-    int* sidx;         // [B][cap_samples]  s1 << 16 | s2
-    double* sth;       // [B][cap_samples][2]  direction interval of the sample
-    int4* pairs;       // [B][cap_pairs]  g1, g2, first sample, sample count
-    int* slotmap;      // [B][ntbins]  transaxial bin -> slot (-1: none)
-    int* slot_tbin;    // [B][cap_slots]
-    double* dense;     // [B][cap_slots][NR * NR]
-    int* chunk_counts; // [B][max_chunks]  kept entries per compaction chunk
+    // per class of the batch (index cb)
+    int* n_samples;    // [B_cls]
+    int* n_pairs;      // [B_cls]
+    int* n_slots;      // [B_cls]
+    int* sidx;         // [B_cls][cap_samples]  s1 << 16 | s2
+    double* sth;       // [B_cls][cap_samples][2]  direction interval of the sample
+    int4* pairs;       // [B_cls][cap_pairs]  g1, g2, first sample, sample count
+    int* slotmap;      // [B_cls][ntbins]  transaxial bin -> slot (-1: none)
+    int* slot_tbin;    // [B_cls][cap_slots]
+    // per member of the batch (index mi)
+    double* dense;     // [B_mem][cap_slots][NR * NR]
+    int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
     float* recs;       // [cap_recs][kRecFloats]  tile records (header, W, U, V)
     unsigned int* rec_count;
     int64_t cap_recs;
 };
 
-// tile record: 4 header ints (g1, g2, r1 | r2 << 8 | voxel << 16, 0), W[16][16], U[16][25], V[16][25]
+// tile record: 4 header ints (g1, g2, (r1 + 512) | (r2 + 512) << 10 | class << 20, 0), W[16][16], U[16][25],
+// V[16][25]; rings are relative to the class's reference member
 constexpr int kRecFloats = 4 + 256 + 400 + 400;
 
+// Voxels are processed in classes: voxels of one z-column whose z differ by a
+// whole number of ring pitches see the scanner identically up to a shift of
+// whole rings, so the class computes its line bundles, weights and response
+// rows once, for the ring offsets of its reference member (shift 0), and each
+// member takes the tiles shifted by its own ring shift.
 struct Args3D {
-    int64_t vox_begin;  // first voxel of this batch
-    int n_vox;          // voxels in this batch
-    int64_t row_base;   // CSR row of the batch's first voxel
+    const int4* cls;    // [n_cls]: reference voxel, first member, member count, largest shift
+    const int4* mem;    // [n_mem]: voxel, ring shift, class, CSR row
+    int n_cls;          // classes in this batch
+    int n_mem;          // members (voxels) in this batch
     int batch;
     double threshold;
     const float* x;     // [batch][nvox]  forward input

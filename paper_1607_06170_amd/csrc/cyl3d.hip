@@ -1,20 +1,26 @@
 // 3D scanner (block rings): system matrix and on-the-fly projections.
 //
 // The paper builds the 2D matrix and names the 3D one as its next step
-// (Sec 4); this is that extension of Sec 2, voxel by voxel:
-//   K1 transaxial  one workgroup per voxel.  The 2D homogenization sweep of
+// (Sec 4); this is that extension of Sec 2.  Voxels go in classes: the voxels
+// of one z-column whose z differ by whole ring pitches.  Everything below
+// depends on z only through z - z_voxel, so a class computes its tiles once,
+// for its reference voxel and ring offsets that reach every member, and each
+// member takes them shifted by its own number of rings.
+//   K1 transaxial  one workgroup per class.  The 2D homogenization sweep of
 //                  Sec 2.3 over the transaxial sub-segments (Eq.11) gives the
 //                  line bundles (s1, s2, direction interval), grouped into
 //                  crystal pairs (g1, g2).  For the matrix build it also lists
-//                  the voxel's transaxial bins (sorted) and maps each to a slot.
-//   K2 tiles       one wavefront per (crystal pair, ring r1) task.  For each
-//                  ring r2 the lines reach: the P^2 x P^2 weights W3 between
-//                  sub-patches (solid angle of the lines, in closed form), the
-//                  response rows U, V (P^2 x 25, Eq.2-7 with the transaxial
-//                  two-block remap), and the tile T = U^T (W V) (Eq.10, 12),
-//                  then emission: forward atomics, adjoint gathers, or FP64
-//                  atomics into the voxel's dense slot x ring-pair accumulator.
-//   K3 compact     ordered compaction of the accumulator into CSR rows.
+//                  the class's transaxial bins (sorted) and maps each to a slot.
+//   K2a geometry   one wavefront per (crystal pair, relative ring r1) task.  For
+//                  each ring r2 the lines reach: the P^2 x P^2 weights W3
+//                  between sub-patches (solid angle of the lines, in closed
+//                  form) and the response rows U, V (P^2 x 25, Eq.2-7 with the
+//                  transaxial two-block remap), appended as a tile record.
+//   K2b contract   the tile T = U^T (W V) (Eq.10, 12) on matrix cores, then
+//                  emission for every member: forward atomics, adjoint
+//                  gathers, or FP64 atomics into the member's dense slot x
+//                  ring-pair accumulator.
+//   K3 compact     ordered compaction of each member's accumulator into CSR rows.
 //
 // Bins: bin = tbin(g_i, g_j) * NR^2 + r_i * NR + r_j with g_i < g_j (r_i the
 // ring of crystal g_i): the transaxial pair major, then the ring pair.
@@ -152,7 +158,9 @@ __device__ __forceinline__ int64_t tab3_idx(int nr, int P, int rt, int rz, int p
 
 // out[(a_t+2)*5 + (a_z+2)]: response of the crystal at transaxial offset a_t
 // and ring r + a_z to a photon entering sub-patch (g, pt; r, pz) from (cx, cy, cz).
-// Returns 1 when an angle row beyond the table had to be clamped.
+// Rings outside the scanner are kept here (r may be a relative ring of a class);
+// the emission drops them.  Returns 1 when an angle row beyond the table had
+// to be clamped.
 __device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, int pt, int r, int pz, float* out) {
     int range = 0;
     const int b = g / G.nc, c = g - b * G.nc, P = G.P, nr = G.n_rows;
@@ -199,15 +207,13 @@ __device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, i
     for (int amt = -2; amt <= 2; ++amt) {
         const int a_t = mt ? -amt : amt, cc = cm + amt;
         for (int amz = -2; amz <= 2; ++amz) {
-            const int a_z = mz ? -amz : amz, ring = r + a_z;
+            const int a_z = mz ? -amz : amz;
             float v = 0.0f;
-            if (ring >= 0 && ring < G.NR) {
-                if (cc >= 0 && cc < G.nc) {
-                    v = G.table[tab3_idx(nr, P, row_t, row_z, ptm, pzm, amt, amz)];
-                } else if (cc >= G.nc && remap) {
-                    const int idx = kv + 1 + (cc - G.nc), az1 = amz - dr;
-                    if (idx <= 2 && az1 >= -2 && az1 <= 2) v = G.table[tab3_idx(nr, P, row_bt, row_bz, pt1, pz1, idx, az1)];
-                }
+            if (cc >= 0 && cc < G.nc) {
+                v = G.table[tab3_idx(nr, P, row_t, row_z, ptm, pzm, amt, amz)];
+            } else if (cc >= G.nc && remap) {
+                const int idx = kv + 1 + (cc - G.nc), az1 = amz - dr;
+                if (idx <= 2 && az1 >= -2 && az1 <= 2) v = G.table[tab3_idx(nr, P, row_bt, row_bz, pt1, pz1, idx, az1)];
             }
             out[(a_t + 2) * kNb + (a_z + 2)] = v;
         }
@@ -224,8 +230,8 @@ constexpr int kBlockT = 512;
 __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D S, Args3D A, int want_slots) {
     extern __shared__ __align__(16) unsigned char smem3[];
     const int tid = threadIdx.x, bs = blockDim.x;
-    const int vb = blockIdx.x;
-    const int64_t v = A.vox_begin + vb;
+    const int vb = blockIdx.x;  // class of the batch
+    const int64_t v = A.cls[vb].x;
     const int M1 = G.nc * G.P + 1, spb = G.nc * G.P;
     if (vb == 0 && tid == 0) *S.rec_count = 0u;  // the batch's tile records start empty
     double* th = (double*)smem3;                    // [R * M1]
@@ -378,7 +384,7 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     }
     if (!want_slots) return;
     __syncthreads();
-    // transaxial bins of this voxel: mark, then scan in bin order into slots
+    // transaxial bins of this class: mark, then scan in bin order into slots
     int* smap = S.slotmap + (int64_t)vb * G.ntbins;
     for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
     __syncthreads();
@@ -440,23 +446,27 @@ size_t cyl3d_transaxial_smem(const Cyl3D& G) {
 
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
                                    hipStream_t st) {
-    if (a.n_vox <= 0) return hipSuccess;
+    if (a.n_cls <= 0) return hipSuccess;
     const size_t smem = cyl3d_transaxial_smem(G);
     hipFuncSetAttribute((const void*)k_cyl3d_transaxial, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    hipLaunchKernelGGL(k_cyl3d_transaxial, dim3(a.n_vox), dim3(kBlockT), smem, st, G, S, a, want_slots);
+    hipLaunchKernelGGL(k_cyl3d_transaxial, dim3(a.n_cls), dim3(kBlockT), smem, st, G, S, a, want_slots);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // K2a: tile geometry (FP64) -> tile records
 // ---------------------------------------------------------------------------
-// One wavefront per (crystal pair, ring r1) task.  For every ring r2 the lines
-// reach it computes the P^2 x P^2 weights W and, when any is non-zero, the
-// response rows U (g1, r1) and V (g2, r2); the tile is appended to the record
-// buffer for the contraction kernel.
+// One wavefront per (crystal pair, ring r1) task, r1 relative to the class's
+// reference voxel and ranging over [-s_max, NR - 1] (s_max the largest member
+// shift), so that every member's rings are covered.  For every ring r2 the
+// lines reach, and that some member sees with both rings inside the scanner,
+// it computes the P^2 x P^2 weights W and, when any is non-zero, the response
+// rows U (g1, r1) and V (g2, r2); the tile is appended to the record buffer
+// for the contraction kernel.  The tasks of a class are dealt round-robin to
+// its workgroups; the batch gets about kGeomWG workgroups in all.
 
 constexpr int kWavesT = 4;
-constexpr int kPairsPerWG = 8;
+constexpr int kGeomWG = 1024;
 
 struct WaveLds {
     float W[kMaxK][kMaxK + 1];
@@ -479,13 +489,13 @@ __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_
 k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ WaveLds wl[kWavesT];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int vb = blockIdx.y;
-    const int64_t v = A.vox_begin + vb;
+    const int vb = blockIdx.y;  // class of the batch
+    const int4 cl = A.cls[vb];
+    const int64_t v = cl.x;
+    const int smax = cl.w;
     WaveLds& L = wl[wid];
     const int np = S.n_pairs[vb];
-    const int pair0 = blockIdx.x * kPairsPerWG;
-    if (pair0 >= np) return;
-    const int pair1 = min(np, pair0 + kPairsPerWG);
+    const int nr1 = G.NR + smax;
     const int P = G.P, K = P * P;
     const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
     const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
@@ -493,10 +503,10 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     double vx, vy, vz;
     voxel_xyz(G, v, vx, vy, vz);
     int flag = 0;
-    const int ntask = (pair1 - pair0) * G.NR;
-    for (int t = wid; t < ntask; t += kWavesT) {
-        const int4 pr = pairs[pair0 + t / G.NR];
-        const int r1 = t % G.NR;
+    const int ntask = np * nr1;
+    for (int t = blockIdx.x * kWavesT + wid; t < ntask; t += gridDim.x * kWavesT) {
+        const int4 pr = pairs[t / nr1];
+        const int r1 = t % nr1 - smax;
         const int g1 = pr.x, g2 = pr.y, nsmp = pr.w;
         if (nsmp > kMaxK) { flag |= kStatScratch; continue; }
         if (lane < nsmp) {
@@ -547,9 +557,12 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
             }
         }
         int r2a = (int)floor((zmin - G.z0) / G.lz) - 1, r2b = (int)floor((zmax - G.z0) / G.lz) + 1;
-        r2a = r2a < 0 ? 0 : r2a;
+        r2a = r2a < -smax ? -smax : r2a;
         r2b = r2b > G.NR - 1 ? G.NR - 1 : r2b;
         for (int r2 = r2a; r2 <= r2b; ++r2) {
+            // members (shifts s) that see both rings inside the scanner
+            const int slo = max(0, max(-r1, -r2)), shi = min(smax, min(G.NR - 1 - r1, G.NR - 1 - r2));
+            if (slo > shi) continue;
             // W: P^2 x P^2 weights between sub-patches of (g1, r1) and (g2, r2)
             for (int e = lane; e < kMaxK * kMaxK; e += 64) L.W[e >> 4][e & 15] = 0.0f;
             __builtin_amdgcn_wave_barrier();
@@ -615,7 +628,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                 int* h = (int*)rec;
                 h[0] = g1;
                 h[1] = g2;
-                h[2] = r1 | (r2 << 8) | (vb << 16);
+                h[2] = (r1 + 512) | ((r2 + 512) << 10) | (vb << 20);
                 h[3] = 0;
             }
             for (int e = lane; e < 256; e += 64) rec[4 + e] = L.W[e >> 4][e & 15];
@@ -637,6 +650,8 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
 //                hi/lo form adds U_hi X_lo and U_lo X_hi (three bf16 MFMAs).
 // Lane l holds T[8(j/4) + 4(l/32) + j%4][l%32] in accumulator j: its column
 // b = l%32 fixes the photon-2 crystal, its 16 rows the photon-1 crystals.
+// The transaxial part of each entry's bin is the same for every member of the
+// class; the emission then walks the members, each with its rings shifted.
 
 struct MmaLds {
     float W[16][17];
@@ -660,8 +675,9 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
     for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
         const float* rec = S.recs + (int64_t)idx * kRecFloats;
         const int* h = (const int*)rec;
-        const int g1 = h[0], g2 = h[1], r1 = h[2] & 0xff, r2 = (h[2] >> 8) & 0xff, vb = h[2] >> 16;
-        const int64_t v = A.vox_begin + vb;
+        const int g1 = h[0], g2 = h[1], hv = h[2];
+        const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
+        const int4 cl = A.cls[vb];
         for (int e = lane; e < 256; e += 64) L.W[e >> 4][e & 15] = rec[4 + e];
         for (int e = lane; e < 400; e += 64) L.U[e / 25][e % 25] = rec[260 + e];
         for (int e = lane; e < 400; e += 64) L.V[e / 25][e % 25] = rec[660 + e];
@@ -710,62 +726,83 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             }
         }
         __builtin_amdgcn_wave_barrier();
-        // emission
-        double xv[8], acc[8];
-#pragma unroll
-        for (int bb = 0; bb < 8; ++bb) {
-            acc[bb] = 0.0;
-            xv[bb] = (MODE == kModeFwd && bb < nb) ? (double)A.x[(int64_t)bb * G.nvox + v] : 0.0;
-        }
-        const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
-        double* dense = (MODE == kModeCount || MODE == kModeFill)
-                            ? S.dense + (int64_t)vb * S.cap_slots * G.NR * G.NR : nullptr;
+        // transaxial part of each entry: the bin of the crystal pair (or the
+        // class's slot for it) and whether photon 2's crystal comes first
         const int bq = m;
         const int bt = bq / 5 - 2, bz = bq % 5 - 2;
-        const int rb = r2 + bz;
         int gb = g2 + bt;
         gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-        const bool col_ok = bq < 25 && rb >= 0 && rb < G.NR;
+        const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
+        int key[16];
+        unsigned int live = 0u, swap = 0u;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
-            const float t = ct[j];
-            if (!col_ok || a >= 25 || t == 0.0f) continue;
-            const int at = a / 5 - 2, az = a % 5 - 2;
-            const int ra = r1 + az;
-            if (ra < 0 || ra >= G.NR) continue;
-            int ga = g1 + at;
+            key[j] = 0;
+            int ga = g1 + a / 5 - 2;
             ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
-            if (ga == gb) continue;
+            if (bq >= 25 || a >= 25 || ct[j] == 0.0f || ga == gb) continue;
             const bool sw = ga > gb;
-            const int gi = sw ? gb : ga, gj = sw ? ga : gb, ri = sw ? rb : ra, rj = sw ? ra : rb;
-            const int64_t tb_ = tbin_of(gi, gj, G.Nc);
-            if (MODE == kModeFwd) {
-                const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-#pragma unroll
-                for (int bb = 0; bb < 8; ++bb)
-                    if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
-            } else if (MODE == kModeAdj) {
-                const int64_t bin = (tb_ * G.NR + ri) * G.NR + rj;
-#pragma unroll
-                for (int bb = 0; bb < 8; ++bb)
-                    if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
-            } else {
-                const int slot = smap[tb_];
-                if (slot < 0) {
+            const int tb_ = (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
+            if (MODE == kModeCount || MODE == kModeFill) {
+                key[j] = smap[tb_];
+                if (key[j] < 0) {
                     flag |= kStatScratch;
                     continue;
                 }
-                atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], (double)t);
+            } else {
+                key[j] = tb_;
             }
+            live |= 1u << j;
+            swap |= sw ? 1u << j : 0u;
         }
-        if (MODE == kModeAdj) {
+        // emission, member by member
+        for (int mi = cl.y; mi < cl.y + cl.z; ++mi) {
+            const int4 me = A.mem[mi];
+            const int R1 = r1 + me.y, R2 = r2 + me.y;
+            if (R1 < 0 || R1 >= G.NR || R2 < 0 || R2 >= G.NR) continue;
+            const int64_t v = me.x;
+            const int rb = R2 + bz;
+            const bool col_ok = rb >= 0 && rb < G.NR;
+            double xv[8], acc[8];
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) {
-                if (bb >= nb) break;
-                double sacc = acc[bb];
-                for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
-                if (lane == 0 && sacc != 0.0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], sacc);
+                acc[bb] = 0.0;
+                xv[bb] = (MODE == kModeFwd && bb < nb) ? (double)A.x[(int64_t)bb * G.nvox + v] : 0.0;
+            }
+            double* dense = (MODE == kModeCount || MODE == kModeFill)
+                                ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (!col_ok || !((live >> j) & 1u)) continue;
+                const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
+                const int ra = R1 + a % 5 - 2;
+                if (ra < 0 || ra >= G.NR) continue;
+                const float t = ct[j];
+                const bool sw = (swap >> j) & 1u;
+                const int ri = sw ? rb : ra, rj = sw ? ra : rb;
+                if (MODE == kModeFwd) {
+                    const int64_t bin = ((int64_t)key[j] * G.NR + ri) * G.NR + rj;
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
+                } else if (MODE == kModeAdj) {
+                    const int64_t bin = ((int64_t)key[j] * G.NR + ri) * G.NR + rj;
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
+                } else {
+                    atomicAdd(&dense[((int64_t)key[j] * G.NR + ri) * G.NR + rj], (double)t);
+                }
+            }
+            if (MODE == kModeAdj) {
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb) {
+                    if (bb >= nb) break;
+                    double sacc = acc[bb];
+                    for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
+                    if (lane == 0 && sacc != 0.0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], sacc);
+                }
             }
         }
     }
@@ -773,14 +810,16 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
 }
 
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
-    if (a.n_vox <= 0) return hipSuccess;
-    const dim3 grid((S.cap_pairs + kPairsPerWG - 1) / kPairsPerWG, a.n_vox), block(64 * kWavesT);
+    if (a.n_cls <= 0) return hipSuccess;
+    int per_cls = (kGeomWG + a.n_cls - 1) / a.n_cls;
+    per_cls = per_cls < 8 ? 8 : (per_cls > 512 ? 512 : per_cls);
+    const dim3 grid(per_cls, a.n_cls), block(64 * kWavesT);
     hipLaunchKernelGGL(k_cyl3d_geom, grid, block, 0, st, G, S, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
-    if (a.n_vox <= 0) return hipSuccess;
+    if (a.n_cls <= 0) return hipSuccess;
     const dim3 grid(2048), block(64 * kWavesM);
     switch (mode) {
         case kModeCount:
@@ -802,7 +841,7 @@ hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const 
 // ---------------------------------------------------------------------------
 // K3: compaction of the dense accumulator into CSR rows (ascending bins)
 // ---------------------------------------------------------------------------
-// A voxel's accumulator is cut into chunks of kChunk entries, one workgroup
+// A member's accumulator is cut into chunks of kChunk entries, one workgroup
 // each.  Count phase: each chunk adds its number of kept entries to the row
 // count.  Fill phase: a first pass stores the per-chunk counts, the second
 // writes each chunk at its offset (row start + counts of the chunks before
@@ -818,18 +857,20 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     __shared__ int wave_tot[kBlockC / 64];
     __shared__ int64_t s_run;
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
-    const int vb = blockIdx.y;
+    const int mi = blockIdx.y;  // member of the batch
+    const int4 me = A.mem[mi];
+    const int vb = me.z;        // its class
     const int64_t chunk = blockIdx.x;
-    const int64_t row = A.row_base + vb;
+    const int64_t row = me.w;
     const int nsl = S.n_slots[vb];
     const int64_t nrr = (int64_t)G.NR * G.NR;
     const int64_t total = (int64_t)nsl * nrr;
     const int64_t c0 = chunk * kChunk;
     if (c0 >= total) return;
     const int64_t c1 = c0 + kChunk < total ? c0 + kChunk : total;
-    double* dense = S.dense + (int64_t)vb * S.cap_slots * nrr;
+    double* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
     const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
-    int* ccount = S.chunk_counts + (int64_t)vb * S.max_chunks;
+    int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     int64_t start = 0, cap = 0;
     if (MODE == kCompactFill) {
         if (tid == 0) {
@@ -890,8 +931,8 @@ int64_t cyl3d_max_chunks(int cap_slots, int NR) {
 }
 
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
-    if (a.n_vox <= 0) return hipSuccess;
-    const dim3 grid((unsigned)S.max_chunks, a.n_vox), block(kBlockC);
+    if (a.n_mem <= 0) return hipSuccess;
+    const dim3 grid((unsigned)S.max_chunks, a.n_mem), block(kBlockC);
     if (mode == kModeCount) {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactCount>, grid, block, 0, st, G, S, a);
     } else {
