@@ -16,8 +16,9 @@ constexpr int kBatchProj = 128;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
-constexpr int64_t kRecsPerVoxel = 32768;   // tile records allowed for one voxel
-constexpr int64_t kRecBudget = 1 << 19;    // tile records per batch (4.2 KB each)
+constexpr int64_t kRecsPerVoxel = 65536;   // tile records allowed for one voxel
+constexpr int64_t kRecBudget = 1 << 21;    // tile records per batch (1.1 KB each)
+constexpr int kUvRings = 16;               // response-row table: rings per batch beyond the members, in NR
 
 Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
     Cyl3D G;
@@ -67,11 +68,12 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, plan, x64, y32, h64, h32, back,
-        total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, plan, x64, y32,
+        h64, h32, back, total;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
+    int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
 };
 
 Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
@@ -110,8 +112,15 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(float) * (size_t)L.cap_recs * kRecFloats);
     L.reccount = off;
     off += align256(sizeof(unsigned int));
-    L.plan = off;  // classes and members of every batch: two int4 per voxel at most
-    off += align256(2 * sizeof(int4) * (size_t)h->n_vox);
+    // a batch's classes need NR + s_max ring slots each, s_max + 1 their members
+    L.cap_uv_rings = kUvRings * NR + (L.bmax > L.bcsr ? L.bmax : L.bcsr);
+    L.cap_uv = Nc * L.cap_uv_rings;
+    L.uvtab = off;
+    off += align256(sizeof(float) * 400 * (size_t)L.cap_uv);
+    L.uvmask = off;
+    off += align256(sizeof(int) * (size_t)L.cap_uv);
+    L.plan = off;  // classes, members and row-table offsets of every batch: at most 2 int4 + 1 int per voxel
+    off += align256((2 * sizeof(int4) + sizeof(int)) * (size_t)h->n_vox);
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.y32 = L.h64 = L.h32 = L.back = off;
@@ -154,6 +163,9 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.recs = at3<float>(ws, L.recs);
     S.rec_count = at3<unsigned int>(ws, L.reccount);
     S.cap_recs = L.cap_recs;
+    S.uvtab = at3<float>(ws, L.uvtab);
+    S.uvmask = at3<int>(ws, L.uvmask);
+    S.cap_uv = L.cap_uv;
     return S;
 }
 
@@ -165,15 +177,17 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
 // from the reference (s = 0) moved by s rings.  When the pitch is not a whole
 // number of voxels every voxel is its own class.  Classes are cut to at most
 // `cmax` members and packed into batches of at most `bmax` members whose tile
-// record estimates fit the record buffer.
+// record estimates fit the record buffer and whose response rows fit the table.
 
 struct Batch3 {
     int cls0, ncls, mem0, nmem;
+    int64_t uv_slots;  // response-row slots of the batch
 };
 
 struct Plan3 {
     std::vector<int4> cls, mem;  // cls: reference voxel, first member (batch-relative), count, largest shift
-    std::vector<Batch3> batches; // mem: voxel, shift, class (batch-relative), CSR row
+    std::vector<int> uvoff;      // mem: voxel, shift, class (batch-relative), CSR row
+    std::vector<Batch3> batches; // uvoff: first response-row slot of the class (batch-relative)
 };
 
 int64_t class_recs(const Ws3& L, int64_t NR, int n) {
@@ -187,18 +201,22 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax)
     int64_t m = 0;
     const double q = nearbyint(h->g.pitch_z / h->im.dz);
     if (q >= 1.0 && q < 1e6 && fabs(q * h->im.dz - h->g.pitch_z) <= 1e-12 * h->g.pitch_z) m = (int64_t)q;
+    const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     int cmax = bmax;
-    while (cmax > 1 && class_recs(L, NR, cmax) > L.cap_recs) --cmax;
-    Batch3 cur = {0, 0, 0, 0};
+    while (cmax > 1 && (class_recs(L, NR, cmax) > L.cap_recs || NR + cmax - 1 > L.cap_uv_rings)) --cmax;
+    Batch3 cur = {0, 0, 0, 0, 0};
     int64_t cur_recs = 0;
     auto add_class = [&](int64_t v0, int64_t step, int n) {
-        const int64_t need = class_recs(L, NR, n);
-        if (cur.nmem > 0 && (cur.nmem + n > bmax || cur_recs + need > L.cap_recs)) {
+        const int64_t need = class_recs(L, NR, n), uv = Nc * (NR + n - 1);
+        if (cur.nmem > 0 &&
+            (cur.nmem + n > bmax || cur_recs + need > L.cap_recs || cur.uv_slots + uv > L.cap_uv)) {
             pl.batches.push_back(cur);
-            cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0};
+            cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0, 0};
             cur_recs = 0;
         }
         pl.cls.push_back(make_int4((int)v0, cur.nmem, n, n - 1));
+        pl.uvoff.push_back((int)cur.uv_slots);
+        cur.uv_slots += uv;
         for (int k = 0; k < n; ++k) {
             const int64_t v = v0 + k * step;
             pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
@@ -229,50 +247,65 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax)
     return pl;
 }
 
+struct PlanDev {
+    const int4 *cls, *mem;
+    const int* uvoff;
+};
+
 // copies the plan into the workspace; returns the device arrays
-int upload_plan(const Plan3& pl, void* ws, const Ws3& L, hipStream_t s, const int4** dcls, const int4** dmem) {
+int upload_plan(const Plan3& pl, void* ws, const Ws3& L, hipStream_t s, PlanDev* d) {
     int4* c = at3<int4>(ws, L.plan);
     int4* mm = c + pl.cls.size();
+    int* uo = (int*)(mm + pl.mem.size());
     if (!pl.cls.empty()) {
         HIP_TRY(hipMemcpyAsync(c, pl.cls.data(), sizeof(int4) * pl.cls.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(mm, pl.mem.data(), sizeof(int4) * pl.mem.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(uo, pl.uvoff.data(), sizeof(int) * pl.uvoff.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope after the call
     }
-    *dcls = c;
-    *dmem = mm;
+    d->cls = c;
+    d->mem = mm;
+    d->uvoff = uo;
     return PSF_OK;
 }
 
-void set_batch(Args3D& a, const Batch3& b, const int4* dcls, const int4* dmem) {
-    a.cls = dcls + b.cls0;
-    a.mem = dmem + b.mem0;
+void set_batch(Args3D& a, const Batch3& b, const PlanDev& d) {
+    a.cls = d.cls + b.cls0;
+    a.mem = d.mem + b.mem0;
+    a.uvoff = d.uvoff + b.cls0;
     a.n_cls = b.ncls;
     a.n_mem = b.nmem;
+}
+
+// K1, K1b and K2a of one batch: line bundles, response rows, tile records
+int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args3D& a, const Batch3& b,
+                   int want_slots, hipStream_t s) {
+    HIP_TRY(launch_cyl3d_transaxial(G, S, a, want_slots, s));
+    HIP_TRY(launch_cyl3d_uvtab(G, S, a, b.uv_slots, s));
+    ProfScope pg_(h, s, 1);
+    HIP_TRY(launch_cyl3d_geom(G, S, a, s));
+    return PSF_OK;
 }
 
 // y[batch][n_bins] (FP32, accumulated with atomics) += A x over every voxel
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              void* ws, hipStream_t s) {
     const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
-    const int4 *dcls, *dmem;
-    int st = upload_plan(pl, ws, L, s, &dcls, &dmem);
+    PlanDev pd;
+    int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
         for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
-            set_batch(a, bt, dcls, dmem);
+            set_batch(a, bt, pd);
             a.batch = nb;
             a.x = x + (int64_t)b0 * h->n_vox;
             a.y = y + (int64_t)b0 * h->n_bins;
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
-            HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
-            {
-                ProfScope pg_(h, s, 1);
-                HIP_TRY(launch_cyl3d_geom(G, S, a, s));
-            }
+            if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
             {
                 ProfScope pm_(h, s, 0);
                 HIP_TRY(launch_cyl3d_mma(kModeFwd, G, S, a, s));
@@ -286,26 +319,22 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, void* ws, hipStream_t s) {
     const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
-    const int4 *dcls, *dmem;
-    int st = upload_plan(pl, ws, L, s, &dcls, &dmem);
+    PlanDev pd;
+    int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
         for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
-            set_batch(a, bt, dcls, dmem);
+            set_batch(a, bt, pd);
             a.batch = nb;
             a.yin = ones ? nullptr : y + (int64_t)b0 * h->n_bins;
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
-            HIP_TRY(launch_cyl3d_transaxial(G, S, a, 0, s));
-            {
-                ProfScope pg_(h, s, 1);
-                HIP_TRY(launch_cyl3d_geom(G, S, a, s));
-            }
+            if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
             {
                 ProfScope pm_(h, s, 0);
                 HIP_TRY(launch_cyl3d_mma(kModeAdj, G, S, a, s));
@@ -350,12 +379,12 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     // the count phase adds each chunk's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
-    const int4 *dcls, *dmem;
-    if ((st = upload_plan(pl, ws, L, s, &dcls, &dmem))) return st;
+    PlanDev pd;
+    if ((st = upload_plan(pl, ws, L, s, &pd))) return st;
     for (const Batch3& bt : pl.batches) {
         Args3D a;
         memset(&a, 0, sizeof(a));
-        set_batch(a, bt, dcls, dmem);
+        set_batch(a, bt, pd);
         a.batch = 1;
         a.threshold = o->threshold;
         a.row_ptr = csr->row_ptr;
@@ -363,11 +392,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         a.val = csr->val;
         a.status = (int*)ws;
         a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
-        HIP_TRY(launch_cyl3d_transaxial(G, S, a, 1, s));
-        {
-            ProfScope pg_(h, s, 1);
-            HIP_TRY(launch_cyl3d_geom(G, S, a, s));
-        }
+        if ((st = batch_geometry(h, G, S, a, bt, 1, s))) return st;
         {
             ProfScope pm_(h, s, 0);
             HIP_TRY(launch_cyl3d_mma(kModeCount, G, S, a, s));

@@ -63,14 +63,23 @@ struct Scratch3D {
     double* dense;     // [B_mem][cap_slots][NR * NR]
     int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
-    float* recs;       // [cap_recs][kRecFloats]  tile records (header, W, U, V)
+    float* recs;       // [cap_recs][kRecFloats]  tile records (header, sample blocks of W)
     unsigned int* rec_count;
     int64_t cap_recs;
+    // response rows of every (crystal g, relative ring r) of each class: slot
+    // uvoff[class] + g * (NR + s_max) + (r + s_max) holds P^2 rows of 25
+    float* uvtab;      // [cap_uv][16][25]
+    int* uvmask;       // [cap_uv]  rows whose angle row was clamped (bit per row)
+    int64_t cap_uv;
 };
 
-// tile record: 4 header ints (g1, g2, (r1 + 512) | (r2 + 512) << 10 | class << 20, 0), W[16][16], U[16][25],
-// V[16][25]; rings are relative to the class's reference member
-constexpr int kRecFloats = 4 + 256 + 400 + 400;
+// tile record (ints and floats in one array):
+//   [0] g1  [1] g2  [2] (r1 + 512) | (r2 + 512) << 10 | class << 20  [3] n samples
+//   [4 + k]        pt1 | pt2 << 8 of sample k (the transaxial sub-segments of the bundle)
+//   [20 + 16k + q] W of sample k between axial sub-positions pz1 = q / P and pz2 = q % P
+// rings are relative to the class's reference member
+constexpr int kRecHead = 20;
+constexpr int kRecFloats = kRecHead + 16 * 16;
 
 // Voxels are processed in classes: voxels of one z-column whose z differ by a
 // whole number of ring pitches see the scanner identically up to a shift of
@@ -80,6 +89,7 @@ constexpr int kRecFloats = 4 + 256 + 400 + 400;
 struct Args3D {
     const int4* cls;    // [n_cls]: reference voxel, first member, member count, largest shift
     const int4* mem;    // [n_mem]: voxel, ring shift, class, CSR row
+    const int* uvoff;   // [n_cls]: first response-row slot of the class
     int n_cls;          // classes in this batch
     int n_mem;          // members (voxels) in this batch
     int batch;
@@ -148,6 +158,7 @@ enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad =
 hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st);
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
                                    hipStream_t st);
+hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);

@@ -11,12 +11,15 @@
 //                  line bundles (s1, s2, direction interval), grouped into
 //                  crystal pairs (g1, g2).  For the matrix build it also lists
 //                  the class's transaxial bins (sorted) and maps each to a slot.
+//   K1b rows       the response rows (P^2 x 25 per crystal and relative ring,
+//                  Eq.2-7 with the transaxial two-block remap) of every crystal
+//                  the class can see, into a table.
 //   K2a geometry   one wavefront per (crystal pair, relative ring r1) task.  For
 //                  each ring r2 the lines reach: the P^2 x P^2 weights W3
 //                  between sub-patches (solid angle of the lines, in closed
-//                  form) and the response rows U, V (P^2 x 25, Eq.2-7 with the
-//                  transaxial two-block remap), appended as a tile record.
-//   K2b contract   the tile T = U^T (W V) (Eq.10, 12) on matrix cores, then
+//                  form), appended as a tile record (its non-zero blocks).
+//   K2b contract   the tile T = U^T (W V) (Eq.10, 12) on matrix cores, U and V
+//                  from the table, then
 //                  emission for every member: forward atomics, adjoint
 //                  gathers, or FP64 atomics into the member's dense slot x
 //                  ring-pair accumulator.
@@ -80,7 +83,7 @@ struct W3Geo {
     double c2, s2, D2;  // photon 2's face
 };
 
-__device__ __forceinline__ void cswap(double& a, double& b) {
+__host__ __device__ __forceinline__ void cswap(double& a, double& b) {
     const double lo = fmin(a, b), hi = fmax(a, b);
     a = lo;
     b = hi;
@@ -89,7 +92,7 @@ __device__ __forceinline__ void cswap(double& a, double& b) {
 // one cut of the bundle: where A_i cos(theta - psi_i) = A_j cos(theta - psi_j),
 // i.e. p cos(theta) + q sin(theta) = 0, if that falls strictly inside (ta, tb);
 // otherwise tb (an empty piece)
-__device__ __forceinline__ double w3_cut(double Ai, double Ci, double Si, double Aj, double Cj, double Sj, double ta,
+__host__ __device__ __forceinline__ double w3_cut(double Ai, double Ci, double Si, double Aj, double Cj, double Sj, double ta,
                                          double tb) {
     const double p = Ai * Ci - Aj * Cj, q = Ai * Si - Aj * Sj;
     if (p == 0.0 && q == 0.0) return tb;
@@ -99,12 +102,12 @@ __device__ __forceinline__ double w3_cut(double Ai, double Ci, double Si, double
 }
 
 // asin(A sin(theta - psi) / sqrt(1 + A^2)) at (cos theta, sin theta)
-__device__ __forceinline__ double w3_F(double A, double C, double S, double inv, double ct, double st) {
+__host__ __device__ __forceinline__ double w3_F(double A, double C, double S, double inv, double ct, double st) {
     return asin(A * (st * C - ct * S) * inv);
 }
 
-__device__ double w3_closed(const W3Geo& g, double zv, double z1lo, double z1hi, double z2lo, double z2hi, double ta,
-                            double tb) {
+__host__ __device__ double w3_closed(const W3Geo& g, double zv, double z1lo, double z1hi, double z2lo, double z2hi,
+                                     double ta, double tb) {
     // slope limits T_k(theta) = A_k cos(theta - psi_k): 0 T1lo, 1 T1hi (photon 1, psi = its face normal),
     // 2 T2lo, 3 T2hi (photon 2 travels along theta + pi: psi = its face normal + pi)
     const double A0 = (z1lo - zv) / g.D1, A1 = (z1hi - zv) / g.D1;
@@ -143,6 +146,149 @@ __device__ double w3_closed(const W3Geo& g, double zv, double z1lo, double z1hi,
             a = b;
             ca = cb;
             sa = sb;
+        }
+    }
+    return sum / (2.0 * kPi);
+}
+
+// The same integral without trigonometric calls, from the unit vectors of the
+// bundle's ends.  A point of the bundle (width below a half turn) is the unit
+// vector u; its place along the bundle is the key
+//   key(u) = sin(theta_u - theta_a)       while cos(theta_u - theta_a) >= 0,
+//            2 - sin(theta_u - theta_a)   beyond a quarter turn,
+// which grows with the angle from the start.  A switch of the binding limits
+// (a root of p cos + q sin, Th = Tl or a swap of the binding limit) lies inside
+// when p cos + q sin changes sign strictly between the ends; the root is then
+// +-(q, -p)/|(p, q)|, the sign taken so that it lies ahead of the start.  On
+// each piece the binding limits are read at the (unnormalised) midpoint
+// u_i + u_{i+1}, and each asin difference is taken in one call:
+//   asin x_b - asin x_a = asin(x_b y_a - x_a y_b)   when y_a y_b + x_a x_b >= 0,
+// with x = A sin(theta - psi)/sqrt(1 + A^2) and y = sqrt(1 - x^2) =
+// sqrt(1 + T^2)/sqrt(1 + A^2) (T = A cos(theta - psi), the limit itself).
+
+__host__ __device__ __forceinline__ double w3_key(double ca, double sa, double c, double s) {
+    const double sn = ca * s - sa * c, cs = ca * c + sa * s;
+    return cs >= 0.0 ? sn : 2.0 - sn;
+}
+
+// p, q of switch i: 0 T1hi = T2hi, 1 T1lo = T2lo, 2 T1hi = T2lo, 3 T2hi = T1lo
+struct W3Lim {
+    double A0, A1, A2, A3, C1, S1, C2, S2;
+    __host__ __device__ __forceinline__ void pq(int i, double& p, double& q) const {
+        const double Ai = i == 1 ? A0 : (i == 3 ? A3 : A1);
+        const double Aj = i == 0 ? A3 : (i == 3 ? A0 : A2);
+        const double Ci = i == 3 ? C2 : C1, Si = i == 3 ? S2 : S1;
+        const double Cj = i == 3 ? C1 : C2, Sj = i == 3 ? S1 : S2;
+        p = Ai * Ci - Aj * Cj;
+        q = Ai * Si - Aj * Sj;
+    }
+};
+
+// the root of p cos + q sin inside the bundle when the sign changes strictly
+// between the ends (else key 4: beyond the end)
+__host__ __device__ __forceinline__ double w3_cut_key(double p, double q, double ca, double sa, double cb, double sb) {
+    const double fa = p * ca + q * sa, fb = p * cb + q * sb;
+    if (!((fa < 0.0 && fb > 0.0) || (fa > 0.0 && fb < 0.0))) return 4.0;
+    double uc = q, us = -p;  // unnormalised: the key needs the unit vector
+    const double inv = 1.0 / sqrt(p * p + q * q);
+    uc *= inv;
+    us *= inv;
+    if (ca * us - sa * uc < 0.0) {
+        uc = -uc;
+        us = -us;
+    }
+    return w3_key(ca, sa, uc, us);
+}
+
+__host__ __device__ __forceinline__ void w3_cut_uv(double p, double q, double ca, double sa, double& uc, double& us) {
+    const double inv = 1.0 / sqrt(p * p + q * q);
+    uc = q * inv;
+    us = -p * inv;
+    if (ca * us - sa * uc < 0.0) {
+        uc = -uc;
+        us = -us;
+    }
+}
+
+__host__ __device__ __forceinline__ void kswap(double& ka, int& ia, double& kb, int& ib) {
+    const bool sw = kb < ka;
+    const double k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const int i0 = sw ? ib : ia, i1 = sw ? ia : ib;
+    ka = k0;
+    kb = k1;
+    ia = i0;
+    ib = i1;
+}
+
+// asin(x_b) - asin(x_a) for the limit A cos(theta - psi) between the unit vectors a and b
+__host__ __device__ __forceinline__ double w3_dF(double A, double C, double S, double inv, double ac, double as_,
+                                                 double bc, double bs) {
+    const double xa = A * (as_ * C - ac * S) * inv, xb = A * (bs * C - bc * S) * inv;
+    const double Ta = A * (ac * C + as_ * S), Tb = A * (bc * C + bs * S);
+    const double ya = sqrt(1.0 + Ta * Ta) * inv, yb = sqrt(1.0 + Tb * Tb) * inv;
+    const double sd = xb * ya - xa * yb, cd = ya * yb + xa * xb;
+    const double r = asin(fmin(1.0, fmax(-1.0, sd)));
+    return cd >= 0.0 ? r : (sd >= 0.0 ? kPi - r : -kPi - r);
+}
+
+__host__ __device__ double w3_closed_uv(const W3Geo& g, double zv, double z1lo, double z1hi, double z2lo, double z2hi,
+                                        double ca, double sa, double cb, double sb) {
+    W3Lim L;
+    L.A0 = (z1lo - zv) / g.D1;
+    L.A1 = (z1hi - zv) / g.D1;
+    L.A2 = (zv - z2hi) / g.D2;
+    L.A3 = (zv - z2lo) / g.D2;
+    L.C1 = g.c1;
+    L.S1 = g.s1;
+    L.C2 = -g.c2;
+    L.S2 = -g.s2;
+    double k0, k1, k2, k3;
+    {
+        double p, q;
+        L.pq(0, p, q);
+        k0 = w3_cut_key(p, q, ca, sa, cb, sb);
+        L.pq(1, p, q);
+        k1 = w3_cut_key(p, q, ca, sa, cb, sb);
+        L.pq(2, p, q);
+        k2 = w3_cut_key(p, q, ca, sa, cb, sb);
+        L.pq(3, p, q);
+        k3 = w3_cut_key(p, q, ca, sa, cb, sb);
+    }
+    int j0 = 0, j1 = 1, j2 = 2, j3 = 3;
+    kswap(k0, j0, k1, j1);
+    kswap(k2, j2, k3, j3);
+    kswap(k0, j0, k2, j2);
+    kswap(k1, j1, k3, j3);
+    kswap(k1, j1, k2, j2);
+    const double kend = w3_key(ca, sa, cb, sb);
+    const double i0 = 1.0 / sqrt(1.0 + L.A0 * L.A0), i1 = 1.0 / sqrt(1.0 + L.A1 * L.A1);
+    const double i2 = 1.0 / sqrt(1.0 + L.A2 * L.A2), i3 = 1.0 / sqrt(1.0 + L.A3 * L.A3);
+    double sum = 0.0;
+    double akey = 0.0, ac = ca, as_ = sa;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double bkey = k == 0 ? k0 : (k == 1 ? k1 : (k == 2 ? k2 : (k == 3 ? k3 : kend)));
+        const int bj = k == 0 ? j0 : (k == 1 ? j1 : (k == 2 ? j2 : j3));
+        if (bkey > kend) bkey = kend;
+        if (bkey > akey) {
+            double bc = cb, bs = sb;
+            if (k < 4 && bkey < kend) {
+                double p, q;
+                L.pq(bj, p, q);
+                w3_cut_uv(p, q, ca, sa, bc, bs);
+            }
+            const double cm = ac + bc, sm = as_ + bs;
+            const double T0 = L.A0 * (cm * L.C1 + sm * L.S1), T1 = L.A1 * (cm * L.C1 + sm * L.S1);
+            const double T2 = L.A2 * (cm * L.C2 + sm * L.S2), T3 = L.A3 * (cm * L.C2 + sm * L.S2);
+            const bool h1 = T1 < T3, l0 = T0 > T2;
+            if ((h1 ? T1 : T3) > (l0 ? T0 : T2)) {
+                const double Ah = h1 ? L.A1 : L.A3, Ch = h1 ? L.C1 : L.C2, Sh = h1 ? L.S1 : L.S2, ih = h1 ? i1 : i3;
+                const double Al = l0 ? L.A0 : L.A2, Cl = l0 ? L.C1 : L.C2, Sl = l0 ? L.S1 : L.S2, il = l0 ? i0 : i2;
+                sum += w3_dF(Ah, Ch, Sh, ih, ac, as_, bc, bs) - w3_dF(Al, Cl, Sl, il, ac, as_, bc, bs);
+            }
+            akey = bkey;
+            ac = bc;
+            as_ = bs;
         }
     }
     return sum / (2.0 * kPi);
@@ -454,28 +600,84 @@ hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Arg
 }
 
 // ---------------------------------------------------------------------------
+// K1b: response-row table
+// ---------------------------------------------------------------------------
+// One thread per row (crystal g, relative ring r, sub-patch pt * P + pz) from
+// the class's reference voxel; rows are staged in LDS and stored coalesced.
+// Rows beyond P^2 are zero.  uvmask gets a bit for every row whose angle row
+// had to be clamped.
+
+constexpr int kUvBlock = 256;  // rows per workgroup: 16 (crystal, ring) slots
+
+__global__ void __launch_bounds__(kUvBlock) k_cyl3d_uvtab(Cyl3D G, Scratch3D S, Args3D A, int64_t n_slots) {
+    __shared__ float rows[kUvBlock * 25];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t slot0 = (int64_t)blockIdx.x * (kUvBlock / 16);
+    const int64_t slot = slot0 + tid / 16;
+    const int row = tid & 15;
+    float* out = rows + tid * 25;
+    int rng = 0;
+    if (slot < n_slots) {
+        // the class whose slots hold this one
+        int lo = 0, hi = A.n_cls - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.uvoff[mid] <= slot) lo = mid;
+            else hi = mid - 1;
+        }
+        const int4 cl = A.cls[lo];
+        const int nr1 = G.NR + cl.w;
+        const int64_t rel = slot - A.uvoff[lo];
+        const int g = (int)(rel / nr1), r = (int)(rel - (int64_t)g * nr1) - cl.w;
+        if (row < G.P * G.P) {
+            double vx, vy, vz;
+            voxel_xyz(G, cl.x, vx, vy, vz);
+            rng = uv_row3(G, vx, vy, vz, g, row / G.P, r, row % G.P, out);
+        } else {
+            for (int q = 0; q < 25; ++q) out[q] = 0.0f;
+        }
+    }
+    const unsigned long long b = __ballot(rng != 0);
+    if (row == 0 && slot < n_slots) S.uvmask[slot] = (int)((b >> (lane & 48)) & 0xffffull);
+    __syncthreads();
+    const int64_t left = (n_slots - slot0) * 400;
+    const int nflt = (int)(left < (int64_t)kUvBlock * 25 ? left : (int64_t)kUvBlock * 25);
+    float* dst = S.uvtab + slot0 * 400;
+    for (int e = tid; e < nflt; e += kUvBlock) dst[e] = rows[e];
+}
+
+hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st) {
+    if (a.n_cls <= 0 || n_slots <= 0) return hipSuccess;
+    if (n_slots > S.cap_uv) return hipErrorInvalidValue;
+    const int64_t blocks = (n_slots + kUvBlock / 16 - 1) / (kUvBlock / 16);
+    hipLaunchKernelGGL(k_cyl3d_uvtab, dim3((unsigned)blocks), dim3(kUvBlock), 0, st, G, S, a, n_slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // K2a: tile geometry (FP64) -> tile records
 // ---------------------------------------------------------------------------
 // One wavefront per (crystal pair, ring r1) task, r1 relative to the class's
 // reference voxel and ranging over [-s_max, NR - 1] (s_max the largest member
 // shift), so that every member's rings are covered.  For every ring r2 the
 // lines reach, and that some member sees with both rings inside the scanner,
-// it computes the P^2 x P^2 weights W and, when any is non-zero, the response
-// rows U (g1, r1) and V (g2, r2); the tile is appended to the record buffer
-// for the contraction kernel.  The tasks of a class are dealt round-robin to
-// its workgroups; the batch gets about kGeomWG workgroups in all.
+// it computes the P^2 x P^2 weights W, one P x P block per line bundle
+// (sample), and when any is non-zero appends the record (header and the
+// blocks) for the contraction kernel.  The tasks of a class are dealt
+// round-robin to its workgroups; the batch gets about kGeomWG workgroups.
+// Each wavefront takes record slots kSlotChunk at a time from the shared
+// counter and marks the ones it leaves unused empty (no samples).
 
 constexpr int kWavesT = 4;
 constexpr int kGeomWG = 1024;
+constexpr unsigned int kSlotChunk = 16;
 
 struct WaveLds {
-    float W[kMaxK][kMaxK + 1];
-    float U[kMaxK][25];
-    float V[kMaxK][25];
+    float Wk[kMaxK][16];  // sample k: weights between axial sub-positions pz1 * P + pz2
     double ta[kMaxK], tb[kMaxK];
+    double ca[kMaxK], sa[kMaxK], cb[kMaxK], sb[kMaxK];  // unit vectors of the bundle's ends
     double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
     int pt1[kMaxK], pt2[kMaxK];
-    int urange[2 * kMaxK];
 };
 
 __device__ __forceinline__ float bf16r(float x) {
@@ -500,9 +702,12 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
     const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
     const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
+    const int* umask = S.uvmask + A.uvoff[vb];
     double vx, vy, vz;
     voxel_xyz(G, v, vx, vy, vz);
     int flag = 0;
+    unsigned int slot_next = 0, slot_end = 0;  // this wave's reserved record slots
+    unsigned long long n_tiles = 0;
     const int ntask = np * nr1;
     for (int t = blockIdx.x * kWavesT + wid; t < ntask; t += gridDim.x * kWavesT) {
         const int4 pr = pairs[t / nr1];
@@ -529,6 +734,10 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
         // limits A cos(theta - psi) then lie within A times that range
         if (lane < nsmp) {
             const double ca = cos(L.ta[lane]), sa = sin(L.ta[lane]), cb = cos(L.tb[lane]), sb = sin(L.tb[lane]);
+            L.ca[lane] = ca;
+            L.sa[lane] = sa;
+            L.cb[lane] = cb;
+            L.sb[lane] = sb;
             const double u1a = ca * wg.c1 + sa * wg.s1, u1b = cb * wg.c1 + sb * wg.s1;
             const double u2a = -(ca * wg.c2 + sa * wg.s2), u2b = -(cb * wg.c2 + sb * wg.s2);
             // the maximum 1 is reached inside when the face normal direction lies in the bundle
@@ -545,8 +754,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
         double zmin = 1e300, zmax = -1e300;
         for (int k = 0; k < nsmp; ++k) {
             for (int e = 0; e < 2; ++e) {
-                const double th_ = e ? L.tb[k] : L.ta[k];
-                const double ct = cos(th_), st = sin(th_);
+                const double ct = e ? L.cb[k] : L.ca[k], st = e ? L.sb[k] : L.sa[k];
                 const double ratio = (wg.D2 / wg.D1) * (ct * wg.c1 + st * wg.s1) / -(ct * wg.c2 + st * wg.s2);
                 for (int f = 0; f < 2; ++f) {
                     const double z1 = G.z0 + (r1 + f) * G.lz;
@@ -563,8 +771,8 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
             // members (shifts s) that see both rings inside the scanner
             const int slo = max(0, max(-r1, -r2)), shi = min(smax, min(G.NR - 1 - r1, G.NR - 1 - r2));
             if (slo > shi) continue;
-            // W: P^2 x P^2 weights between sub-patches of (g1, r1) and (g2, r2)
-            for (int e = lane; e < kMaxK * kMaxK; e += 64) L.W[e >> 4][e & 15] = 0.0f;
+            // W: one P x P block per sample
+            for (int e = lane; e < nsmp * 16; e += 64) L.Wk[e >> 4][e & 15] = 0.0f;
             __builtin_amdgcn_wave_barrier();
             int any = 0;
 #pragma unroll 1
@@ -585,58 +793,56 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                     const double t2lo_min = a2lo * (a2lo >= 0.0 ? L.c2lo[k] : L.c2hi[k]);
                     if (t1hi_max <= t2lo_min || t2hi_max <= t1lo_min) continue;
                 }
-                const double w = w3_closed(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ta[k], L.tb[k]);
+                const double w = w3_closed_uv(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ca[k], L.sa[k], L.cb[k], L.sb[k]);
                 if (w > kEpsW3) {
-                    L.W[L.pt1[k] * P + pz1][L.pt2[k] * P + pz2] = (float)w;
+                    L.Wk[k][pz1 * P + pz2] = (float)w;
                     any = 1;
                 }
             }
             if (!__any(any)) continue;
             __builtin_amdgcn_wave_barrier();
-            // response rows: lanes 0..K-1 -> U (g1, r1), lanes 32..32+K-1 -> V (g2, r2)
-            if (lane < K) {
-                L.urange[lane] = uv_row3(G, vx, vy, vz, g1, lane / P, r1, lane % P, L.U[lane]);
-            } else if (lane >= 32 && lane < 32 + K) {
-                const int l = lane - 32;
-                L.urange[kMaxK + l] = uv_row3(G, vx, vy, vz, g2, l / P, r2, l % P, L.V[l]);
-            } else if (lane < kMaxK) {  // rows beyond P^2 take no part in the contraction
-                for (int q = 0; q < 25; ++q) L.U[lane][q] = 0.0f;
-            } else if (lane >= 32 && lane < 32 + kMaxK) {
-                for (int q = 0; q < 25; ++q) L.V[lane - 32][q] = 0.0f;
-            }
-            __builtin_amdgcn_wave_barrier();
-            // range errors count only for rows that carry weight
-            if (lane < K) {
-                float rs = 0.0f, cs_ = 0.0f;
-                for (int q = 0; q < K; ++q) {
-                    rs += L.W[lane][q];
-                    cs_ += L.W[q][lane];
+            // range errors count only for response rows that carry weight
+            if (lane < 2 * K) {
+                const int l = lane < K ? lane : lane - K;
+                const int pt = l / P, pz = l % P;
+                float sum = 0.0f;
+                for (int k = 0; k < nsmp; ++k) {
+                    if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
+                    for (int q = 0; q < P; ++q) sum += lane < K ? L.Wk[k][pz * P + q] : L.Wk[k][q * P + pz];
                 }
-                if ((rs != 0.0f && L.urange[lane]) || (cs_ != 0.0f && L.urange[kMaxK + lane])) flag |= kStatRange;
+                const int m = lane < K ? umask[g1 * nr1 + r1 + smax] : umask[g2 * nr1 + r2 + smax];
+                if (sum != 0.0f && ((m >> l) & 1)) flag |= kStatRange;
             }
-            // append the tile record: header, W (16 x 16), U (16 x 25), V (16 x 25)
-            unsigned int slot = 0;
-            if (lane == 0) slot = atomicAdd(S.rec_count, 1u);
-            slot = __shfl(slot, 0, 64);
+            // append the tile record: header, sample sub-segments, weight blocks
+            if (slot_next == slot_end) {
+                unsigned int base = 0;
+                if (lane == 0) base = atomicAdd(S.rec_count, kSlotChunk);
+                slot_next = __shfl(base, 0, 64);
+                slot_end = slot_next + kSlotChunk;
+            }
+            const unsigned int slot = slot_next++;
             if (slot >= (unsigned int)S.cap_recs) {
                 flag |= kStatScratch;
                 continue;
             }
-            if (lane == 0 && A.tiles) atomicAdd(A.tiles, 1ull);
+            ++n_tiles;
             float* rec = S.recs + (int64_t)slot * kRecFloats;
+            int* h = (int*)rec;
             if (lane == 0) {
-                int* h = (int*)rec;
                 h[0] = g1;
                 h[1] = g2;
                 h[2] = (r1 + 512) | ((r2 + 512) << 10) | (vb << 20);
-                h[3] = 0;
+                h[3] = nsmp;
             }
-            for (int e = lane; e < 256; e += 64) rec[4 + e] = L.W[e >> 4][e & 15];
-            for (int e = lane; e < 400; e += 64) rec[260 + e] = L.U[e / 25][e % 25];
-            for (int e = lane; e < 400; e += 64) rec[660 + e] = L.V[e / 25][e % 25];
+            if (lane < nsmp) h[4 + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
+            for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wk[e >> 4][e & 15];
             __builtin_amdgcn_wave_barrier();
         }
     }
+    // reserved slots left unused hold no samples
+    for (unsigned int sl = slot_next + lane; sl < slot_end && sl < (unsigned int)S.cap_recs; sl += 64)
+        ((int*)(S.recs + (int64_t)sl * kRecFloats))[3] = 0;
+    if (lane == 0 && A.tiles && n_tiles) atomicAdd(A.tiles, n_tiles);
     if (flag) atomicOr(A.status, flag);
 }
 
@@ -666,6 +872,7 @@ template <int MODE>
 __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ MmaLds ml[kWavesM];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int P = G.P;
     MmaLds& L = ml[wid];
     const unsigned int nrec = min(*S.rec_count, (unsigned int)S.cap_recs);
     const unsigned int wave0 = blockIdx.x * kWavesM + wid, nwaves = gridDim.x * kWavesM;
@@ -675,12 +882,25 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
     for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
         const float* rec = S.recs + (int64_t)idx * kRecFloats;
         const int* h = (const int*)rec;
+        const int nsmp = h[3];
+        if (nsmp == 0) continue;  // a reserved slot left unused
         const int g1 = h[0], g2 = h[1], hv = h[2];
         const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
         const int4 cl = A.cls[vb];
-        for (int e = lane; e < 256; e += 64) L.W[e >> 4][e & 15] = rec[4 + e];
-        for (int e = lane; e < 400; e += 64) L.U[e / 25][e % 25] = rec[260 + e];
-        for (int e = lane; e < 400; e += 64) L.V[e / 25][e % 25] = rec[660 + e];
+        const int nr1 = G.NR + cl.w;
+        const float* urow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g1 * nr1 + r1 + cl.w) * 400;
+        const float* vrow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g2 * nr1 + r2 + cl.w) * 400;
+        for (int e = lane; e < 256; e += 64) L.W[e >> 4][e & 15] = 0.0f;
+        for (int e = lane; e < 400; e += 64) L.U[e / 25][e % 25] = urow[e];
+        for (int e = lane; e < 400; e += 64) L.V[e / 25][e % 25] = vrow[e];
+        __builtin_amdgcn_wave_barrier();
+        // scatter the weight blocks: sample k couples (pt1, pz1) with (pt2, pz2)
+        for (int e = lane; e < nsmp * 16; e += 64) {
+            const int k = e >> 4, q = e & 15;
+            if (q >= P * P) continue;
+            const int pts = h[4 + k], pt1 = pts & 0xff, pt2 = pts >> 8;
+            L.W[pt1 * P + q / P][pt2 * P + q % P] = rec[kRecHead + e];
+        }
         __builtin_amdgcn_wave_barrier();
         // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
 #pragma unroll
