@@ -857,13 +857,27 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
 // Lane l holds T[8(j/4) + 4(l/32) + j%4][l%32] in accumulator j: its column
 // b = l%32 fixes the photon-2 crystal, its 16 rows the photon-1 crystals.
 // The transaxial part of each entry's bin is the same for every member of the
-// class; the emission then walks the members, each with its rings shifted.
+// class.  A tile has few non-zero entries (those whose crystals see the
+// bundle), so they are first compacted into a list in LDS (over the operands,
+// which are spent by then); the emission then walks the members, each with its
+// rings shifted, the lanes spread over the list.
 
-struct MmaLds {
+struct MmaOps {
     float W[16][17];
     float U[16][25];
     float V[16][25];
     float X[16][32];
+};
+
+struct MmaList {
+    float t[640];          // entry value
+    int key[640];          // transaxial bin (projections) or the class's slot for it (matrix build)
+    unsigned char m[640];  // (a_z + 2) | (b_z + 2) << 3 | (photon 2 first) << 6
+};
+
+union MmaLds {
+    MmaOps o;
+    MmaList e;
 };
 
 constexpr int kWavesM = 4;
@@ -890,16 +904,16 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
         const int nr1 = G.NR + cl.w;
         const float* urow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g1 * nr1 + r1 + cl.w) * 400;
         const float* vrow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g2 * nr1 + r2 + cl.w) * 400;
-        for (int e = lane; e < 256; e += 64) L.W[e >> 4][e & 15] = 0.0f;
-        for (int e = lane; e < 400; e += 64) L.U[e / 25][e % 25] = urow[e];
-        for (int e = lane; e < 400; e += 64) L.V[e / 25][e % 25] = vrow[e];
+        for (int e = lane; e < 256; e += 64) L.o.W[e >> 4][e & 15] = 0.0f;
+        for (int e = lane; e < 400; e += 64) L.o.U[e / 25][e % 25] = urow[e];
+        for (int e = lane; e < 400; e += 64) L.o.V[e / 25][e % 25] = vrow[e];
         __builtin_amdgcn_wave_barrier();
         // scatter the weight blocks: sample k couples (pt1, pz1) with (pt2, pz2)
         for (int e = lane; e < nsmp * 16; e += 64) {
             const int k = e >> 4, q = e & 15;
             if (q >= P * P) continue;
             const int pts = h[4 + k], pt1 = pts & 0xff, pt2 = pts >> 8;
-            L.W[pt1 * P + q / P][pt2 * P + q % P] = rec[kRecHead + e];
+            L.o.W[pt1 * P + q / P][pt2 * P + q % P] = rec[kRecHead + e];
         }
         __builtin_amdgcn_wave_barrier();
         // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
@@ -910,12 +924,12 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
 #pragma unroll
             for (int kk = 0; kk < 16; kk += 4) {
                 const int k = kk + (lane >> 4);
-                const float a = L.W[lane & 15][k];
-                const float b = col < 25 ? L.V[k][col] : 0.0f;
+                const float a = L.o.W[lane & 15][k];
+                const float b = col < 25 ? L.o.V[k][col] : 0.0f;
                 cx = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cx, 0, 0, 0);
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) L.X[4 * (lane >> 4) + j][col] = cx[j];
+            for (int j = 0; j < 4; ++j) L.o.X[4 * (lane >> 4) + j][col] = cx[j];
         }
         __builtin_amdgcn_wave_barrier();
         v16f ct;
@@ -924,15 +938,15 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
         if (G.precision == PSF_FP32) {
 #pragma unroll
             for (int kk = 0; kk < 16; kk += 2) {
-                const float a = m < 25 ? L.U[kk + hk][m] : 0.0f;
-                ct = __builtin_amdgcn_mfma_f32_32x32x2f32(a, L.X[kk + hk][m], ct, 0, 0, 0);
+                const float a = m < 25 ? L.o.U[kk + hk][m] : 0.0f;
+                ct = __builtin_amdgcn_mfma_f32_32x32x2f32(a, L.o.X[kk + hk][m], ct, 0, 0, 0);
             }
         } else {
             v8bf ah, bh, al, bl;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float u = m < 25 ? L.U[8 * hk + i][m] : 0.0f;
-                const float x = L.X[8 * hk + i][m];
+                const float u = m < 25 ? L.o.U[8 * hk + i][m] : 0.0f;
+                const float x = L.o.X[8 * hk + i][m];
                 const float uh = bf16r(u), xh = bf16r(x);
                 ah[i] = (__bf16)uh;
                 bh[i] = (__bf16)xh;
@@ -946,8 +960,8 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             }
         }
         __builtin_amdgcn_wave_barrier();
-        // transaxial part of each entry: the bin of the crystal pair (or the
-        // class's slot for it) and whether photon 2's crystal comes first
+        // live entries (crystals distinct, inside the 25 x 25 tile, non-zero) and
+        // the transaxial part of their bins
         const int bq = m;
         const int bt = bq / 5 - 2, bz = bq % 5 - 2;
         int gb = g2 + bt;
@@ -976,14 +990,32 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             live |= 1u << j;
             swap |= sw ? 1u << j : 0u;
         }
-        // emission, member by member
+        // compaction: wave prefix sum of the per-lane counts
+        const int nl = __popc(live);
+        int pre = nl;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(pre, off, 64);
+            if (lane >= off) pre += o;
+        }
+        const int total = __shfl(pre, 63, 64);
+        int pos = pre - nl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (!((live >> j) & 1u)) continue;
+            const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
+            L.e.t[pos] = ct[j];
+            L.e.key[pos] = key[j];
+            L.e.m[pos] = (unsigned char)(a % 5 | ((bz + 2) << 3) | (((swap >> j) & 1u) << 6));
+            ++pos;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // emission, member by member (members that see both rings inside the scanner)
         for (int mi = cl.y; mi < cl.y + cl.z; ++mi) {
             const int4 me = A.mem[mi];
             const int R1 = r1 + me.y, R2 = r2 + me.y;
             if (R1 < 0 || R1 >= G.NR || R2 < 0 || R2 >= G.NR) continue;
             const int64_t v = me.x;
-            const int rb = R2 + bz;
-            const bool col_ok = rb >= 0 && rb < G.NR;
             double xv[8], acc[8];
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) {
@@ -992,27 +1024,24 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             }
             double* dense = (MODE == kModeCount || MODE == kModeFill)
                                 ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (!col_ok || !((live >> j) & 1u)) continue;
-                const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
-                const int ra = R1 + a % 5 - 2;
-                if (ra < 0 || ra >= G.NR) continue;
-                const float t = ct[j];
-                const bool sw = (swap >> j) & 1u;
+            for (int e = lane; e < total; e += 64) {
+                const int mm = L.e.m[e];
+                const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
+                if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) continue;
+                const float t = L.e.t[e];
+                const bool sw = (mm >> 6) & 1;
                 const int ri = sw ? rb : ra, rj = sw ? ra : rb;
+                const int64_t idx = ((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj;
                 if (MODE == kModeFwd) {
-                    const int64_t bin = ((int64_t)key[j] * G.NR + ri) * G.NR + rj;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + bin], (float)(xv[bb] * t));
+                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
                 } else if (MODE == kModeAdj) {
-                    const int64_t bin = ((int64_t)key[j] * G.NR + ri) * G.NR + rj;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + bin];
+                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
                 } else {
-                    atomicAdd(&dense[((int64_t)key[j] * G.NR + ri) * G.NR + rj], (double)t);
+                    atomicAdd(&dense[idx], (double)t);
                 }
             }
             if (MODE == kModeAdj) {
@@ -1025,6 +1054,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 }
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
     if (flag) atomicOr(A.status, flag);
 }
