@@ -657,7 +657,7 @@ hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& 
 // ---------------------------------------------------------------------------
 // K2a: tile geometry (FP64) -> tile records
 // ---------------------------------------------------------------------------
-// One wavefront per (crystal pair, ring r1) task, r1 relative to the class's
+// One wavefront per (crystal pair, run of rings r1) unit, r1 relative to the class's
 // reference voxel and ranging over [-s_max, NR - 1] (s_max the largest member
 // shift), so that every member's rings are covered.  For every ring r2 the
 // lines reach, and that some member sees with both rings inside the scanner,
@@ -671,9 +671,15 @@ hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& 
 constexpr int kWavesT = 4;
 constexpr int kGeomWG = 1024;
 constexpr unsigned int kSlotChunk = 16;
+constexpr int kR2Chunk = 8;  // rings r2 handled together
+constexpr int kR1Run = 8;    // consecutive rings r1 of one crystal pair per work unit
+constexpr int kQueue = 128;  // candidate queue (a power of two >= 127)
 
+// Most candidates (r2, sample, pz1, pz2) fail the quick test; the survivors
+// are queued in LDS and the closed form runs on full wavefronts.
 struct WaveLds {
-    float Wk[kMaxK][16];  // sample k: weights between axial sub-positions pz1 * P + pz2
+    float Wr[kR2Chunk][kMaxK][16];  // ring r2c + j, sample k: weights between pz1 * P + pz2
+    int q[kQueue];
     double ta[kMaxK], tb[kMaxK];
     double ca[kMaxK], sa[kMaxK], cb[kMaxK], sb[kMaxK];  // unit vectors of the bundle's ends
     double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
@@ -687,8 +693,10 @@ __device__ __forceinline__ float bf16r(float x) {
 }
 
 // two waves per SIMD: the FP64 geometry needs ~256 registers
+template <int P>
 __global__ void __launch_bounds__(64 * kWavesT) __attribute__((amdgpu_waves_per_eu(2)))
 k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
+    constexpr int K = P * P;
     __shared__ WaveLds wl[kWavesT];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int vb = blockIdx.y;  // class of the batch
@@ -698,7 +706,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     WaveLds& L = wl[wid];
     const int np = S.n_pairs[vb];
     const int nr1 = G.NR + smax;
-    const int P = G.P, K = P * P;
+    const int nrun = (nr1 + kR1Run - 1) / kR1Run;
     const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
     const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
     const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
@@ -708,10 +716,11 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     int flag = 0;
     unsigned int slot_next = 0, slot_end = 0;  // this wave's reserved record slots
     unsigned long long n_tiles = 0;
-    const int ntask = np * nr1;
-    for (int t = blockIdx.x * kWavesT + wid; t < ntask; t += gridDim.x * kWavesT) {
-        const int4 pr = pairs[t / nr1];
-        const int r1 = t % nr1 - smax;
+    const int nunit = np * nrun;
+    for (int u = blockIdx.x * kWavesT + wid; u < nunit; u += gridDim.x * kWavesT) {
+        const int pi = u / nrun;
+        const int r1a = (u - pi * nrun) * kR1Run - smax, r1e = min(r1a + kR1Run, G.NR);
+        const int4 pr = pairs[pi];
         const int g1 = pr.x, g2 = pr.y, nsmp = pr.w;
         if (nsmp > kMaxK) { flag |= kStatScratch; continue; }
         if (lane < nsmp) {
@@ -749,94 +758,151 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
             L.c2lo[lane] = fmin(u2a, u2b);
             L.c2hi[lane] = m2 <= wdt ? 1.0 : fmax(u2a, u2b);
         }
-        __builtin_amdgcn_wave_barrier();
-        // rings r2 reached from ring r1: photon 2 lands at zv - (d2/d1)(z1 - zv)
-        double zmin = 1e300, zmax = -1e300;
-        for (int k = 0; k < nsmp; ++k) {
+        // photon 2 lands at zv - ratio (z1 - zv): the range of the ratio over the
+        // bundles' ends (lanes < nsmp), then over the lanes
+        double rmin = 1e300, rmax = -1e300;
+        if (lane < nsmp) {
             for (int e = 0; e < 2; ++e) {
-                const double ct = e ? L.cb[k] : L.ca[k], st = e ? L.sb[k] : L.sa[k];
+                const double ct = e ? L.cb[lane] : L.ca[lane], st = e ? L.sb[lane] : L.sa[lane];
                 const double ratio = (wg.D2 / wg.D1) * (ct * wg.c1 + st * wg.s1) / -(ct * wg.c2 + st * wg.s2);
-                for (int f = 0; f < 2; ++f) {
-                    const double z1 = G.z0 + (r1 + f) * G.lz;
-                    const double z2 = vz - ratio * (z1 - vz);
-                    zmin = fmin(zmin, z2);
-                    zmax = fmax(zmax, z2);
-                }
+                rmin = fmin(rmin, ratio);
+                rmax = fmax(rmax, ratio);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
+            rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+        }
+        const double invD1 = 1.0 / wg.D1, invD2 = 1.0 / wg.D2;
+        const int smag = (65536 + nsmp - 1) / nsmp;  // c / nsmp == (c * smag) >> 16 for c < 4096
+        __builtin_amdgcn_wave_barrier();
+        for (int r1 = r1a; r1 < r1e; ++r1) {
+        // rings r2 reached from ring r1
+        double zmin = 1e300, zmax = -1e300;
+        for (int f = 0; f < 2; ++f) {
+            const double z1 = G.z0 + (r1 + f) * G.lz;
+            for (int e = 0; e < 2; ++e) {
+                const double z2 = vz - (e ? rmax : rmin) * (z1 - vz);
+                zmin = fmin(zmin, z2);
+                zmax = fmax(zmax, z2);
             }
         }
         int r2a = (int)floor((zmin - G.z0) / G.lz) - 1, r2b = (int)floor((zmax - G.z0) / G.lz) + 1;
         r2a = r2a < -smax ? -smax : r2a;
         r2b = r2b > G.NR - 1 ? G.NR - 1 : r2b;
-        for (int r2 = r2a; r2 <= r2b; ++r2) {
-            // members (shifts s) that see both rings inside the scanner
-            const int slo = max(0, max(-r1, -r2)), shi = min(smax, min(G.NR - 1 - r1, G.NR - 1 - r2));
-            if (slo > shi) continue;
-            // W: one P x P block per sample
-            for (int e = lane; e < nsmp * 16; e += 64) L.Wk[e >> 4][e & 15] = 0.0f;
+        for (int r2c = r2a; r2c <= r2b; r2c += kR2Chunk) {
+            const int nj = min(kR2Chunk, r2b - r2c + 1);
+            // rings of the chunk that some member sees with both rings inside the scanner
+            unsigned int jok = 0u;
+            for (int j = 0; j < nj; ++j) {
+                const int r2 = r2c + j;
+                const int slo = max(0, max(-r1, -r2)), shi = min(smax, min(G.NR - 1 - r1, G.NR - 1 - r2));
+                if (slo <= shi) jok |= 1u << j;
+            }
+            if (!jok) continue;
+            for (int e = lane; e < nj * kMaxK * 16; e += 64) L.Wr[e >> 8][(e >> 4) & 15][e & 15] = 0.0f;
             __builtin_amdgcn_wave_barrier();
-            int any = 0;
+            unsigned int jm = 0u;  // rings whose tile got a weight (this lane's share)
+            int head = 0, tail = 0;
+            const int nk = nsmp * K, ncand = nj * nk;
+            // W3 of queue entry head + lane, when it exists
+            auto eval = [&](int count) {
+                if (lane < count) {
+                    const int item = L.q[(head + lane) & (kQueue - 1)];
+                    const int j = item >> 8, k = (item >> 4) & 15, q = item & 15;
+                    const int pz1 = q / P, pz2 = q - pz1 * P, r2 = r2c + j;
+                    const double z1lo = G.z0 + (r1 + (double)pz1 / P) * G.lz;
+                    const double z1hi = G.z0 + (r1 + (double)(pz1 + 1) / P) * G.lz;
+                    const double z2lo = G.z0 + (r2 + (double)pz2 / P) * G.lz;
+                    const double z2hi = G.z0 + (r2 + (double)(pz2 + 1) / P) * G.lz;
+                    const double w = w3_closed_uv(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ca[k], L.sa[k], L.cb[k], L.sb[k]);
+                    if (w > kEpsW3) {
+                        L.Wr[j][k][q] = (float)w;
+                        jm |= 1u << j;
+                    }
+                }
+                head += count < 64 ? count : 64;
+            };
 #pragma unroll 1
-            for (int e = lane; e < nsmp * K; e += 64) {
-                const int k = e / K, pz1 = (e / P) % P, pz2 = e % P;
-                const double z1lo = G.z0 + (r1 + (double)pz1 / P) * G.lz;
-                const double z1hi = G.z0 + (r1 + (double)(pz1 + 1) / P) * G.lz;
-                const double z2lo = G.z0 + (r2 + (double)pz2 / P) * G.lz;
-                const double z2hi = G.z0 + (r2 + (double)(pz2 + 1) / P) * G.lz;
-                // skip pairs whose slope windows cannot meet anywhere in the bundle
-                // (the closed form is then exactly 0)
-                {
-                    const double a1lo = (z1lo - vz) / wg.D1, a1hi = (z1hi - vz) / wg.D1;
-                    const double a2lo = (vz - z2hi) / wg.D2, a2hi = (vz - z2lo) / wg.D2;
-                    const double t1hi_max = a1hi * (a1hi >= 0.0 ? L.c1hi[k] : L.c1lo[k]);
-                    const double t1lo_min = a1lo * (a1lo >= 0.0 ? L.c1lo[k] : L.c1hi[k]);
-                    const double t2hi_max = a2hi * (a2hi >= 0.0 ? L.c2hi[k] : L.c2lo[k]);
-                    const double t2lo_min = a2lo * (a2lo >= 0.0 ? L.c2lo[k] : L.c2hi[k]);
-                    if (t1hi_max <= t2lo_min || t2hi_max <= t1lo_min) continue;
+            for (int c0 = 0; c0 < ncand; c0 += 64) {
+                const int c = c0 + lane;
+                bool pass = false;
+                int item = 0;
+                if (c < ncand) {
+                    const int ck = c / K, q = c - ck * K;
+                    const int j = (ck * smag) >> 16, k = ck - j * nsmp;
+                    const int pz1 = q / P, pz2 = q - pz1 * P;
+                    if ((jok >> j) & 1u) {
+                        const int r2 = r2c + j;
+                        const double z1lo = G.z0 + (r1 + (double)pz1 / P) * G.lz;
+                        const double z1hi = G.z0 + (r1 + (double)(pz1 + 1) / P) * G.lz;
+                        const double z2lo = G.z0 + (r2 + (double)pz2 / P) * G.lz;
+                        const double z2hi = G.z0 + (r2 + (double)(pz2 + 1) / P) * G.lz;
+                        // pairs whose slope windows cannot meet anywhere in the bundle
+                        // have weight exactly 0
+                        const double a1lo = (z1lo - vz) * invD1, a1hi = (z1hi - vz) * invD1;
+                        const double a2lo = (vz - z2hi) * invD2, a2hi = (vz - z2lo) * invD2;
+                        const double t1hi_max = a1hi * (a1hi >= 0.0 ? L.c1hi[k] : L.c1lo[k]);
+                        const double t1lo_min = a1lo * (a1lo >= 0.0 ? L.c1lo[k] : L.c1hi[k]);
+                        const double t2hi_max = a2hi * (a2hi >= 0.0 ? L.c2hi[k] : L.c2lo[k]);
+                        const double t2lo_min = a2lo * (a2lo >= 0.0 ? L.c2lo[k] : L.c2hi[k]);
+                        pass = !(t1hi_max <= t2lo_min || t2hi_max <= t1lo_min);
+                        item = (j << 8) | (k << 4) | (pz1 * P + pz2);
+                    }
                 }
-                const double w = w3_closed_uv(wg, vz, z1lo, z1hi, z2lo, z2hi, L.ca[k], L.sa[k], L.cb[k], L.sb[k]);
-                if (w > kEpsW3) {
-                    L.Wk[k][pz1 * P + pz2] = (float)w;
-                    any = 1;
-                }
+                const unsigned long long bal = __ballot(pass);
+                if (pass) L.q[(tail + __popcll(bal & ((1ull << lane) - 1ull))) & (kQueue - 1)] = item;
+                tail += __popcll(bal);
+                __builtin_amdgcn_wave_barrier();
+                while (tail - head >= 64) eval(64);
             }
-            if (!__any(any)) continue;
+            if (tail > head) eval(tail - head);
             __builtin_amdgcn_wave_barrier();
-            // range errors count only for response rows that carry weight
-            if (lane < 2 * K) {
-                const int l = lane < K ? lane : lane - K;
-                const int pt = l / P, pz = l % P;
-                float sum = 0.0f;
-                for (int k = 0; k < nsmp; ++k) {
-                    if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
-                    for (int q = 0; q < P; ++q) sum += lane < K ? L.Wk[k][pz * P + q] : L.Wk[k][q * P + pz];
+            // rings with a non-zero tile: OR over the lanes
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) jm |= __shfl_xor(jm, off, 64);
+            for (int j = 0; j < nj; ++j) {
+                if (!((jm >> j) & 1u)) continue;
+                const int r2 = r2c + j;
+                // range errors count only for response rows that carry weight
+                if (lane < 2 * K) {
+                    const int l = lane < K ? lane : lane - K;
+                    const int pt = l / P, pz = l % P;
+                    float sum = 0.0f;
+                    for (int k = 0; k < nsmp; ++k) {
+                        if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
+                        for (int q = 0; q < P; ++q) sum += lane < K ? L.Wr[j][k][pz * P + q] : L.Wr[j][k][q * P + pz];
+                    }
+                    const int m = lane < K ? umask[g1 * nr1 + r1 + smax] : umask[g2 * nr1 + r2 + smax];
+                    if (sum != 0.0f && ((m >> l) & 1)) flag |= kStatRange;
                 }
-                const int m = lane < K ? umask[g1 * nr1 + r1 + smax] : umask[g2 * nr1 + r2 + smax];
-                if (sum != 0.0f && ((m >> l) & 1)) flag |= kStatRange;
+                // append the tile record: header, sample sub-segments, weight blocks
+                if (slot_next == slot_end) {
+                    unsigned int base = 0;
+                    if (lane == 0) base = atomicAdd(S.rec_count, kSlotChunk);
+                    slot_next = __shfl(base, 0, 64);
+                    slot_end = slot_next + kSlotChunk;
+                }
+                const unsigned int slot = slot_next++;
+                if (slot >= (unsigned int)S.cap_recs) {
+                    flag |= kStatScratch;
+                    continue;
+                }
+                ++n_tiles;
+                float* rec = S.recs + (int64_t)slot * kRecFloats;
+                int* h = (int*)rec;
+                if (lane == 0) {
+                    h[0] = g1;
+                    h[1] = g2;
+                    h[2] = (r1 + 512) | ((r2 + 512) << 10) | (vb << 20);
+                    h[3] = nsmp;
+                }
+                if (lane < nsmp) h[4 + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
+                for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wr[j][e >> 4][e & 15];
             }
-            // append the tile record: header, sample sub-segments, weight blocks
-            if (slot_next == slot_end) {
-                unsigned int base = 0;
-                if (lane == 0) base = atomicAdd(S.rec_count, kSlotChunk);
-                slot_next = __shfl(base, 0, 64);
-                slot_end = slot_next + kSlotChunk;
-            }
-            const unsigned int slot = slot_next++;
-            if (slot >= (unsigned int)S.cap_recs) {
-                flag |= kStatScratch;
-                continue;
-            }
-            ++n_tiles;
-            float* rec = S.recs + (int64_t)slot * kRecFloats;
-            int* h = (int*)rec;
-            if (lane == 0) {
-                h[0] = g1;
-                h[1] = g2;
-                h[2] = (r1 + 512) | ((r2 + 512) << 10) | (vb << 20);
-                h[3] = nsmp;
-            }
-            if (lane < nsmp) h[4 + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
-            for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wk[e >> 4][e & 15];
             __builtin_amdgcn_wave_barrier();
+        }
         }
     }
     // reserved slots left unused hold no samples
@@ -1064,7 +1130,13 @@ hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a
     int per_cls = (kGeomWG + a.n_cls - 1) / a.n_cls;
     per_cls = per_cls < 8 ? 8 : (per_cls > 512 ? 512 : per_cls);
     const dim3 grid(per_cls, a.n_cls), block(64 * kWavesT);
-    hipLaunchKernelGGL(k_cyl3d_geom, grid, block, 0, st, G, S, a);
+    switch (G.P) {
+        case 1: hipLaunchKernelGGL(k_cyl3d_geom<1>, grid, block, 0, st, G, S, a); break;
+        case 2: hipLaunchKernelGGL(k_cyl3d_geom<2>, grid, block, 0, st, G, S, a); break;
+        case 3: hipLaunchKernelGGL(k_cyl3d_geom<3>, grid, block, 0, st, G, S, a); break;
+        case 4: hipLaunchKernelGGL(k_cyl3d_geom<4>, grid, block, 0, st, G, S, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
