@@ -68,8 +68,8 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, plan, x64, y32,
-        h64, h32, back, total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, plan, x64,
+        ydiag, y32, h64, h32, back, total;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
@@ -99,7 +99,7 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     L.slot_tbin = off;
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;
-    off += align256(sizeof(double) * (size_t)L.bcsr * L.cap_slots * NR * NR);
+    off += align256(sizeof(float) * (size_t)L.bcsr * L.cap_slots * NR * NR);
     L.chunks = off;
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
     off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
@@ -119,10 +119,14 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(float) * 400 * (size_t)L.cap_uv);
     L.uvmask = off;
     off += align256(sizeof(int) * (size_t)L.cap_uv);
+    L.xrep = off;  // cleared at carving and by every fold
+    off += align256(sizeof(double) * kXRep * 8 * (size_t)(L.bmax > L.bcsr ? L.bmax : L.bcsr));
     L.plan = off;  // classes, members and row-table offsets of every batch: at most 2 int4 + 1 int per voxel
     off += align256((2 * sizeof(int4) + sizeof(int)) * (size_t)h->n_vox);
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
+    L.ydiag = off;  // up to 8 sinograms in the diagonal ring-pair layout
+    off += align256(sizeof(float) * (b < 8 ? b : 8) * (size_t)h->n_bins);
     L.y32 = L.h64 = L.h32 = L.back = off;
     if (n_events > 0) {
         L.y32 = off;
@@ -157,7 +161,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.pairs = at3<int4>(ws, L.pairs);
     S.slotmap = at3<int>(ws, L.slotmap);
     S.slot_tbin = at3<int>(ws, L.slot_tbin);
-    S.dense = at3<double>(ws, L.dense);
+    S.dense = at3<float>(ws, L.dense);
     S.chunk_counts = at3<int>(ws, L.chunks);
     S.max_chunks = L.max_chunks;
     S.recs = at3<float>(ws, L.recs);
@@ -166,6 +170,8 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.uvtab = at3<float>(ws, L.uvtab);
     S.uvmask = at3<int>(ws, L.uvmask);
     S.cap_uv = L.cap_uv;
+    S.xrep = at3<double>(ws, L.xrep);
+    S.cap_mem = L.bmax > L.bcsr ? L.bmax : L.bcsr;
     return S;
 }
 
@@ -287,22 +293,25 @@ int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args
     return PSF_OK;
 }
 
-// y[batch][n_bins] (FP32, accumulated with atomics) += A x over every voxel
+// y[batch][n_bins] = A x (accumulate: +=) over every voxel; the kernels add
+// into a diagonal-layout copy (FP32 atomics), permuted into y at the end
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
-             void* ws, hipStream_t s) {
+             int accumulate, void* ws, hipStream_t s) {
     const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
+    float* yd = at3<float>(ws, L.ydiag);
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
+        HIP_TRY(launch_zero_f32(yd, (int64_t)nb * h->n_bins, s));
         for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
             set_batch(a, bt, pd);
             a.batch = nb;
             a.x = x + (int64_t)b0 * h->n_vox;
-            a.y = y + (int64_t)b0 * h->n_bins;
+            a.y = yd;
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
             if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
@@ -311,6 +320,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
                 HIP_TRY(launch_cyl3d_mma(kModeFwd, G, S, a, s));
             }
         }
+        HIP_TRY(launch_diag_perm(yd, y + (int64_t)b0 * h->n_bins, h->n_bins, G.NR, nb, 1, accumulate, s));
     }
     return PSF_OK;
 }
@@ -322,14 +332,17 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
+    float* yd = at3<float>(ws, L.ydiag);
+    HIP_TRY(launch_zero_f64(S.xrep, (int64_t)kXRep * 8 * S.cap_mem, s));
     for (int b0 = 0; b0 < batch; b0 += 8) {
         const int nb = batch - b0 < 8 ? batch - b0 : 8;
+        if (!ones) HIP_TRY(launch_diag_perm(y + (int64_t)b0 * h->n_bins, yd, h->n_bins, G.NR, nb, 0, 0, s));
         for (const Batch3& bt : pl.batches) {
             Args3D a;
             memset(&a, 0, sizeof(a));
             set_batch(a, bt, pd);
             a.batch = nb;
-            a.yin = ones ? nullptr : y + (int64_t)b0 * h->n_bins;
+            a.yin = ones ? nullptr : yd;
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
@@ -339,6 +352,7 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
                 ProfScope pm_(h, s, 0);
                 HIP_TRY(launch_cyl3d_mma(kModeAdj, G, S, a, s));
             }
+            HIP_TRY(launch_xrep_fold(S, a, h->n_vox, s));
         }
     }
     return PSF_OK;
@@ -375,7 +389,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         }
     }
     // the dense accumulators start clean; the compaction leaves them clean
-    HIP_TRY(launch_zero_f64(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
+    HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
     // the count phase adds each chunk's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
@@ -419,18 +433,15 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
     if ((st = zero_header(ws, s))) return st;
-    const int64_t nout = (int64_t)batch * h->n_bins;
     if (events) {
         float* y32 = at3<float>(ws, L.y32);
-        HIP_TRY(launch_zero_f32(y32, nout, s));
-        if ((st = fwd3_all(h, G, S, L, x, batch, y32, ws, s))) return st;
+        if ((st = fwd3_all(h, G, S, L, x, batch, y32, 0, ws, s))) return st;
         const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
         HIP_TRY(launch_lm_gather(nullptr, y32, h->n_bins, events, n_events, batch, G.Nc, NR, y, o->accumulate,
                                  (int*)ws, s));
         return PSF_OK;
     }
-    if (!o->accumulate) HIP_TRY(launch_zero_f32(y, nout, s));
-    return fwd3_all(h, G, S, L, x, batch, y, ws, s);
+    return fwd3_all(h, G, S, L, x, batch, y, o->accumulate, ws, s);
 }
 
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
@@ -477,8 +488,7 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
     float* back = at3<float>(ws, L.back);
     double* x64 = at3<double>(ws, L.x64);
     // q_e = a_e^T x + r  ->  h[bin] += 1 / q_e  ->  back = A^T h  ->  update
-    HIP_TRY(launch_zero_f32(y32, h->n_bins, s));
-    if ((st = fwd3_all(h, G, S, L, x_in, 1, y32, ws, s))) return st;
+    if ((st = fwd3_all(h, G, S, L, x_in, 1, y32, 0, ws, s))) return st;
     HIP_TRY(launch_zero_f64(h64, h->n_bins, s));
     HIP_TRY(launch_lm_ratio(nullptr, y32, events, n_events, G.Nc, NR, (double)randoms, h64, (int*)ws, s));
     HIP_TRY(launch_finalize(h64, h32, h->n_bins, 0, s));

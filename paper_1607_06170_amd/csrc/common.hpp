@@ -60,7 +60,7 @@ struct Scratch3D {
     int* slotmap;      // [B_cls][ntbins]  transaxial bin -> slot (-1: none)
     int* slot_tbin;    // [B_cls][cap_slots]
     // per member of the batch (index mi)
-    double* dense;     // [B_mem][cap_slots][NR * NR]
+    float* dense;      // [B_mem][cap_slots][NR * NR]  FP32 sums of the FP32 tile entries
     int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
     float* recs;       // [cap_recs][kRecFloats]  tile records (header, sample blocks of W)
@@ -71,7 +71,12 @@ struct Scratch3D {
     float* uvtab;      // [cap_uv][16][25]
     int* uvmask;       // [cap_uv]  rows whose angle row was clamped (bit per row)
     int64_t cap_uv;
+    // adjoint sums of the batch's members, in kXRep copies taken by wavefront
+    // index so that concurrent records do not queue on one address
+    double* xrep;      // [kXRep][B_mem][8]
+    int cap_mem;
 };
+constexpr int kXRep = 64;
 
 // tile record (ints and floats in one array):
 //   [0] g1  [1] g2  [2] (r1 + 512) | (r2 + 512) << 10 | class << 20  [3] n samples
@@ -95,8 +100,8 @@ struct Args3D {
     int batch;
     double threshold;
     const float* x;     // [batch][nvox]  forward input
-    float* y;           // [batch][nbins] forward output (FP32 atomics)
-    const float* yin;   // [batch][nbins] adjoint input
+    float* y;           // [batch][nbins] forward output (FP32 atomics), diagonal ring-pair layout
+    const float* yin;   // [batch][nbins] adjoint input, diagonal ring-pair layout
     double* x64;        // [batch][nvox]  adjoint accumulator
     int64_t* row_ptr;
     int32_t* col;
@@ -163,6 +168,9 @@ hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
+hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,
+                            hipStream_t st);
 int64_t cyl3d_max_chunks(int cap_slots, int NR);
 constexpr int kStatScratch = 16;  // a per-voxel scratch capacity was exceeded
 

@@ -21,7 +21,7 @@
 //   K2b contract   the tile T = U^T (W V) (Eq.10, 12) on matrix cores, U and V
 //                  from the table, then
 //                  emission for every member: forward atomics, adjoint
-//                  gathers, or FP64 atomics into the member's dense slot x
+//                  gathers, or FP32 atomics into the member's dense slot x
 //                  ring-pair accumulator.
 //   K3 compact     ordered compaction of each member's accumulator into CSR rows.
 //
@@ -72,6 +72,41 @@ __device__ __forceinline__ void voxel_xyz(const Cyl3D& G, int64_t v, double& x, 
     x = (ix - 0.5 * (G.nx - 1)) * G.dx + G.cx;
     y = (iy - 0.5 * (G.ny - 1)) * G.dy + G.cy;
     z = (iz - 0.5 * (G.nz - 1)) * G.dz + G.cz;
+}
+
+// Sinograms inside the projections are stored ring pair by diagonal: within a
+// transaxial bin, (r_i, r_j) goes to the diagonal r_j - r_i (ascending), then
+// r_i.  Voxels of a class differ by whole rings, so one tile entry lands on
+// consecutive floats for consecutive members.
+__device__ __forceinline__ int64_t diag_index(int ri, int rj, int NR) {
+    const int d = rj - ri + NR - 1;
+    if (d < NR - 1) return (int64_t)d * (d + 1) / 2 + (ri - (NR - 1 - d));
+    const int k = d - (NR - 1);
+    return (int64_t)NR * (NR - 1) / 2 + (int64_t)k * NR - (int64_t)k * (k - 1) / 2 + ri;
+}
+
+// to_user: user[b] (+)= diag[...]; else diag[...] = user[b]; nb images of nbins
+__global__ void k_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate) {
+    const int64_t nrr = (int64_t)NR * NR;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nbins * nb;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / nbins, u = i - b * nbins;
+        const int64_t tb = u / nrr, rr = u - tb * nrr;
+        const int ri = (int)(rr / NR), rj = (int)(rr - (int64_t)ri * NR);
+        const int64_t di = b * nbins + tb * nrr + diag_index(ri, rj, NR);
+        if (to_user) dst[i] = accumulate ? dst[i] + src[di] : src[di];
+        else dst[di] = src[i];
+    }
+}
+
+hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,
+                            hipStream_t st) {
+    const int64_t n = nbins * nb;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_diag_perm, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, src, dst,
+                       nbins, NR, nb, to_user, accumulate);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -956,6 +991,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
     MmaLds& L = ml[wid];
     const unsigned int nrec = min(*S.rec_count, (unsigned int)S.cap_recs);
     const unsigned int wave0 = blockIdx.x * kWavesM + wid, nwaves = gridDim.x * kWavesM;
+    // consecutive records run side by side: their emissions meet in the caches
     const int nb = A.batch < 8 ? A.batch : 8;
     int flag = 0;
     const int m = lane & 31, hk = lane >> 5;
@@ -1076,7 +1112,65 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
-        // emission, member by member (members that see both rings inside the scanner)
+        // emission.  Projections with at most 64 members: lane = (entry, member),
+        // the member fixed per lane (lane mod the member count rounded up to a
+        // power of two); sinograms in the diagonal layout, so a lane group
+        // touches consecutive floats.  Otherwise member by member.
+        int lg = 0;
+        while ((1 << lg) < cl.z) ++lg;
+        if ((MODE == kModeFwd || MODE == kModeAdj) && lg <= 6) {
+            const int msk = (1 << lg) - 1, sm = lane & msk;
+            int R1 = -1, R2 = -1;
+            int64_t v = 0;
+            double xv[8], acc[8];
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                xv[bb] = 0.0;
+                acc[bb] = 0.0;
+            }
+            bool mok = false;
+            if (sm < cl.z) {
+                const int4 me = A.mem[cl.y + sm];
+                R1 = r1 + me.y;
+                R2 = r2 + me.y;
+                v = me.x;
+                mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
+                if (MODE == kModeFwd && mok) {
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
+                }
+            }
+            if (mok) {
+                for (int e = lane >> lg; e < total; e += 64 >> lg) {
+                    const int mm = L.e.m[e];
+                    const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
+                    if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) continue;
+                    const float t = L.e.t[e];
+                    const bool sw = (mm >> 6) & 1;
+                    const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR + (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
+                    if (MODE == kModeFwd) {
+#pragma unroll
+                        for (int bb = 0; bb < 8; ++bb)
+                            if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
+                    } else {
+#pragma unroll
+                        for (int bb = 0; bb < 8; ++bb)
+                            if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
+                    }
+                }
+            }
+            if (MODE == kModeAdj) {
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb) {
+                    if (bb >= nb) break;
+                    double sacc = acc[bb];
+                    for (int off = 1 << lg; off < 64; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
+                    if (lane == sm && mok && sacc != 0.0)
+                        atomicAdd(&S.xrep[((int64_t)(wave0 % kXRep) * S.cap_mem + cl.y + sm) * 8 + bb], sacc);
+                }
+            }
+        } else {
         for (int mi = cl.y; mi < cl.y + cl.z; ++mi) {
             const int4 me = A.mem[mi];
             const int R1 = r1 + me.y, R2 = r2 + me.y;
@@ -1088,8 +1182,8 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 acc[bb] = 0.0;
                 xv[bb] = (MODE == kModeFwd && bb < nb) ? (double)A.x[(int64_t)bb * G.nvox + v] : 0.0;
             }
-            double* dense = (MODE == kModeCount || MODE == kModeFill)
-                                ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
+            float* dense = (MODE == kModeCount || MODE == kModeFill)
+                               ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
             for (int e = lane; e < total; e += 64) {
                 const int mm = L.e.m[e];
                 const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
@@ -1097,17 +1191,19 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 const float t = L.e.t[e];
                 const bool sw = (mm >> 6) & 1;
                 const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                const int64_t idx = ((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj;
-                if (MODE == kModeFwd) {
+                if (MODE == kModeFwd || MODE == kModeAdj) {
+                    const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR + diag_index(ri, rj, G.NR);
+                    if (MODE == kModeFwd) {
 #pragma unroll
-                    for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
-                } else if (MODE == kModeAdj) {
+                        for (int bb = 0; bb < 8; ++bb)
+                            if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
+                    } else {
 #pragma unroll
-                    for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
+                        for (int bb = 0; bb < 8; ++bb)
+                            if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
+                    }
                 } else {
-                    atomicAdd(&dense[idx], (double)t);
+                    atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
                 }
             }
             if (MODE == kModeAdj) {
@@ -1116,9 +1212,11 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                     if (bb >= nb) break;
                     double sacc = acc[bb];
                     for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
-                    if (lane == 0 && sacc != 0.0) atomicAdd(&A.x64[(int64_t)bb * G.nvox + v], sacc);
+                    if (lane == 0 && sacc != 0.0)
+                        atomicAdd(&S.xrep[((int64_t)(wave0 % kXRep) * S.cap_mem + mi) * 8 + bb], sacc);
                 }
             }
+        }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1160,6 +1258,29 @@ hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const 
     return hipGetLastError();
 }
 
+// adjoint: fold the member sums' copies into x64 (each voxel is one member of
+// the batch) and clear them for the next batch
+__global__ void k_xrep_fold(Scratch3D S, Args3D A, int64_t nvox) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // member * 8 + image
+    if (i >= A.n_mem * 8) return;
+    const int mi = i >> 3, bb = i & 7;
+    double sum = 0.0;
+    for (int c = 0; c < kXRep; ++c) {
+        double* p = &S.xrep[((int64_t)c * S.cap_mem + mi) * 8 + bb];
+        sum += *p;
+        *p = 0.0;
+    }
+    if (bb < A.batch && sum != 0.0) A.x64[(int64_t)bb * nvox + A.mem[mi].x] += sum;
+}
+
+hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st) {
+    if (a.n_mem <= 0) return hipSuccess;
+    if (a.n_mem > S.cap_mem) return hipErrorInvalidValue;
+    const int n = a.n_mem * 8;
+    hipLaunchKernelGGL(k_xrep_fold, dim3((n + 255) / 256), dim3(256), 0, st, S, a, nvox);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // K3: compaction of the dense accumulator into CSR rows (ascending bins)
 // ---------------------------------------------------------------------------
@@ -1190,7 +1311,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int64_t c0 = chunk * kChunk;
     if (c0 >= total) return;
     const int64_t c1 = c0 + kChunk < total ? c0 + kChunk : total;
-    double* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
+    float* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
     const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     int64_t start = 0, cap = 0;
@@ -1210,12 +1331,12 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int64_t run0 = s_run;
     for (int64_t b0 = c0; b0 < c1; b0 += bs) {
         const int64_t i = b0 + tid;
-        double a = 0.0;
+        float a = 0.0f;
         if (i < c1) {
             a = dense[i];
-            if (MODE != kCompactChunks) dense[i] = 0.0;  // leave the accumulator clean
+            if (MODE != kCompactChunks) dense[i] = 0.0f;  // leave the accumulator clean
         }
-        const bool keep = a > 0.0 && a >= A.threshold;
+        const bool keep = a > 0.0f && (double)a >= A.threshold;
         const unsigned long long m = __ballot(keep);
         const int pre = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) wave_tot[wid] = __popcll(m);
