@@ -20,6 +20,7 @@ Workloads (all inputs seeded and synthetic, resident in HBM before timing):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -45,7 +46,38 @@ def parse():
     ap.add_argument("--workload", default="cyl3d_sub16", choices=["cyl3d_sub16", "ring2d_64"])
     ap.add_argument("--precision", type=int, default=0, help="0 FP32 plain, 1 BF16, 2 BF16 hi/lo")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB on the device (a kernel of known traffic, to scale PMC byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    """SHA-256 of the 3D kernel sources: a traffic figure is reported only for the sources it was measured on."""
+    h = hashlib.sha256()
+    for f in ("cyl3d.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1607_06170_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_file):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary (FETCH_SIZE, WRITE_SIZE scaled by a
+    copy kernel of known size), or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def workload(name):
@@ -86,6 +118,13 @@ def main():
     warmup = args.warmup if args.warmup is not None else meta["warmup"]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB read, 1 GiB written per copy
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc = Scanner(cfg, mode3d=meta["mode3d"])
     tab = sc.build_table(cfg["n_rows"], cfg["n_sub"], cfg["step_deg"])
     x_np = phantom(cfg, meta)
@@ -97,28 +136,33 @@ def main():
     torch.cuda.synchronize()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    rec = dict(build=[], fwd=[], adj=[], nnz=0, tiles=0)
+    rec = dict(build=[], fwd=[], adj=[], nnz=0, tiles=0, vtiles=0)
 
     def step(record):
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
         e0.record()
         rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=prec)
         e1.record()
-        t_build = sc.tiles_last_call() if meta["mode3d"] and record else 0
+        # tile counters of each call: copied on the device, in stream order, read after the step
+        h_build = sc.header_counters() if meta["mode3d"] and record else None
         y = sc.project_fwd(tab, x, precision=prec)
         e2.record()
-        t_fwd = sc.tiles_last_call() if meta["mode3d"] and record else 0
+        h_fwd = sc.header_counters() if meta["mode3d"] and record else None
         xb = sc.project_adj(tab, y, precision=prec)
         e3.record()
         if record:
             torch.cuda.synchronize()
-            t_adj = sc.tiles_last_call() if meta["mode3d"] else 0
+            h_adj = sc.header_counters() if meta["mode3d"] else None
+            t_build, v_build = sc.read_counters(h_build)
+            t_fwd, v_fwd = sc.read_counters(h_fwd)
+            t_adj, v_adj = sc.read_counters(h_adj)
             rec["build"].append(e0.elapsed_time(e1))
             rec["fwd"].append(e1.elapsed_time(e2))
             rec["adj"].append(e2.elapsed_time(e3))
             rec["nnz"] += int(col.numel())
-            # the count and fill phases contract the same tiles
+            # the count and fill phases contract the same tiles (the counters hold the fill phase's)
             rec["tiles"] += 2 * t_build + t_fwd + t_adj
+            rec["vtiles"] += 2 * v_build + v_fwd + v_adj
         return xb
 
     def log(msg):
@@ -167,16 +211,23 @@ def main():
     avg_ms = k_ms / max(k_launches, 1)
     if meta["mode3d"]:
         K = cfg["n_sub"] ** 2
-        flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X (unpadded)
+        flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X (unpadded): 32 800 for P = 4
+        # algorithmic units: (voxel, tile) pairs -- the tiles a voxel-by-voxel method contracts; a contracted
+        # tile serves every voxel of its z-column class that sees both its rings
+        vtiles_per_launch = rec["vtiles"] / max(k_launches, 1)
         tiles_per_launch = rec["tiles"] / max(k_launches, 1)
-        achieved = tiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
+        achieved = vtiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
+        executed = tiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
         peak = [FP32_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS][prec]
+        traffic = measured_traffic(f"k_cyl3d_mma.{args.workload}.{['fp32', 'bf16', 'bf16x2'][prec]}.pmc.txt")
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak, "traffic": traffic,
                            "kernel": "k_cyl3d_mma (tile contraction T = U^T (W V) on matrix cores, "
-                                     + ["FP32", "BF16", "BF16 hi/lo"][prec] + ")",
+                                     + ["FP32", "BF16", "BF16 hi/lo"][prec] + ", and its emission; all modes)",
                            "avg_launch_ms": avg_ms, "launches": k_launches,
-                           "tiles_per_launch": tiles_per_launch, "flops_per_tile": flops_tile}
+                           "voxel_tiles_per_launch": vtiles_per_launch, "flops_per_voxel_tile": flops_tile,
+                           "tiles_contracted_per_launch": tiles_per_launch,
+                           "executed_tflops": executed, "executed_frac": executed / peak}
         out["geometry_kernel"] = {"kernel": "k_cyl3d_geom (FP64 homogenization weights and response rows)",
                                   "total_ms_per_step": g_ms / steps, "launches": g_launches,
                                   "contraction_total_ms_per_step": k_ms / steps}

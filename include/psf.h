@@ -187,7 +187,9 @@ int psf_check(psf_handle* h, void* workspace_dev, void* stream);
  * them and writes ms[0], launches[0] (contraction) and ms[1], launches[1]
  * (3D geometry): summed elapsed milliseconds and launch counts.  ms and
  * launches point to two entries each (either may be NULL).  In 3D the
- * workspace holds at byte 64 a uint64 count of the tiles of the last call. */
+ * workspace holds at byte 64 a uint64 count of the tiles contracted by the
+ * last call, and at byte 72 the count of (voxel, tile) pairs they served
+ * (a tile serves every voxel of its z-column class that sees both its rings). */
 int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches);
 
 const char* psf_status_string(int status);

@@ -228,6 +228,23 @@ class Scanner:
         _torch().cuda.synchronize()
         return int(self._ws[64:72].cpu().view(__import__("torch").int64).item()) if self._ws is not None else 0
 
+    def header_counters(self):
+        """Device copy (stream-ordered, no synchronisation) of the last 3D call's tile counters."""
+        return self._ws[64:80].clone() if self._ws is not None else None
+
+    @staticmethod
+    def read_counters(snap):
+        """(tiles, voxel tiles) from a header_counters() snapshot."""
+        if snap is None:
+            return 0, 0
+        t, v = snap.cpu().view(__import__("torch").int64).tolist()
+        return int(t), int(v)
+
+    def voxel_tiles_last_call(self) -> int:
+        """(voxel, tile) pairs the last 3D call's tiles served (from the workspace header)."""
+        _torch().cuda.synchronize()
+        return int(self._ws[72:80].cpu().view(__import__("torch").int64).item()) if self._ws is not None else 0
+
     def check(self):
         """Synchronise and raise if a kernel flagged an error (e.g. angle range)."""
         ws = self._ws

@@ -314,6 +314,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.y = yd;
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+        a.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
             if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
             {
                 ProfScope pm_(h, s, 0);
@@ -347,6 +348,7 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+        a.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
             if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
             {
                 ProfScope pm_(h, s, 0);
@@ -406,6 +408,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         a.val = csr->val;
         a.status = (int*)ws;
         a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+        a.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
         if ((st = batch_geometry(h, G, S, a, bt, 1, s))) return st;
         {
             ProfScope pm_(h, s, 0);

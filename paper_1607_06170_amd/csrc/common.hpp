@@ -20,9 +20,12 @@ constexpr int kStatOverflow = 2;  // fill phase wanted more entries than allotte
 constexpr int kStatGeom = 4;
 constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or the same crystal twice
 
-// Workspace header: status word at byte 0, tile counter (uint64) at byte 64, padding to 256 bytes.
+// Workspace header: status word at byte 0, tile counter (uint64) at byte 64,
+// voxel-tile counter (uint64: tiles times the voxels they serve) at byte 72,
+// padding to 256 bytes.
 constexpr size_t kWsHeader = 256;
 constexpr size_t kWsTileCounter = 64;
+constexpr size_t kWsVoxTileCounter = 72;
 
 // Everything a 2D-ring kernel needs, passed by value.
 struct Ring2D {
@@ -108,7 +111,8 @@ struct Args3D {
     float* val;
     int* status;
     int ones;           // adjoint with y == 1 (sensitivity)
-    unsigned long long* tiles;  // count of tiles contracted (workspace header)
+    unsigned long long* tiles;   // count of tiles contracted (workspace header)
+    unsigned long long* vtiles;  // count of (voxel, tile) pairs emitted (workspace header)
 };
 
 // Device view of the handle (host struct defined in api.cpp).

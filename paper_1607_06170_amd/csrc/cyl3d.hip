@@ -994,6 +994,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
     // consecutive records run side by side: their emissions meet in the caches
     const int nb = A.batch < 8 ? A.batch : 8;
     int flag = 0;
+    unsigned long long n_vt = 0;  // (voxel, tile) pairs
     const int m = lane & 31, hk = lane >> 5;
     for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
         const float* rec = S.recs + (int64_t)idx * kRecFloats;
@@ -1141,6 +1142,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                         if (bb < nb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
                 }
             }
+            n_vt += __popcll(__ballot(mok && lane == sm));
             if (mok) {
                 for (int e = lane >> lg; e < total; e += 64 >> lg) {
                     const int mm = L.e.m[e];
@@ -1175,6 +1177,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             const int4 me = A.mem[mi];
             const int R1 = r1 + me.y, R2 = r2 + me.y;
             if (R1 < 0 || R1 >= G.NR || R2 < 0 || R2 >= G.NR) continue;
+            ++n_vt;
             const int64_t v = me.x;
             double xv[8], acc[8];
 #pragma unroll
@@ -1220,6 +1223,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
         }
         __builtin_amdgcn_wave_barrier();
     }
+    if (lane == 0 && A.vtiles && n_vt) atomicAdd(A.vtiles, n_vt);
     if (flag) atomicOr(A.status, flag);
 }
 
