@@ -100,8 +100,12 @@ typedef struct {
     int64_t vox_begin;      /* voxel range of build_psf_sysmat: [vox_begin, vox_end) */
     int64_t vox_end;        /* vox_end <= 0 means all voxels */
     int32_t accumulate;     /* 1: add into the output instead of overwriting */
-    int32_t pad;
+    int32_t flags;          /* PSF_OPT_* bits */
 } psf_opts;
+
+/* psf_opts.flags: project_adj will be asked for the table gradient (3D: the
+ * workspace then holds its per-batch accumulator). */
+#define PSF_OPT_TABLE_GRAD 1
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
 typedef struct {
@@ -158,7 +162,12 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
 
 /* Back projection x = A^T y (layouts as project_fwd).  If grad_table_dev is
  * not NULL, also accumulates d <y, A xt> / d table into it (FP32, table
- * layout, summed over the batch) with xt = xt_dev [batch][n_voxels]. */
+ * layout, summed over the batch) with xt = xt_dev [batch][n_voxels]: each
+ * response entry U[p][a] (Eq.6-7, with its mirror and two-block remap) is a
+ * table entry, so the gradient collects, over the tiles T = U^T W V (Eq.10,
+ * 12), (W V G^T) for the rows of photon 1 and (W^T U G) for those of photon 2,
+ * G the bins' y times the voxel's xt.  In 3D the workspace must have been
+ * sized with PSF_OPT_TABLE_GRAD in opts->flags (else PSF_ESIZE). */
 int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y_dev, int32_t batch,
                 const int32_t* events_dev, int64_t n_events, float* x_dev, const float* xt_dev,
                 float* grad_table_dev, void* workspace_dev, size_t workspace_bytes, void* stream);

@@ -92,9 +92,9 @@ class Scanner:
             pass
 
     # -- helpers -----------------------------------------------------------
-    def opts(self, precision=PSF_FP32, threshold=0.0, vox_begin=0, vox_end=-1, accumulate=0, homog_k=0):
+    def opts(self, precision=PSF_FP32, threshold=0.0, vox_begin=0, vox_end=-1, accumulate=0, homog_k=0, flags=0):
         return _lib.psf_opts(int(precision), int(homog_k), float(threshold), int(vox_begin), int(vox_end),
-                             int(accumulate), 0)
+                             int(accumulate), int(flags))
 
     def workspace(self, table: Table, batch: int = 1, n_events: int = 0, opts=None):
         torch = _torch()
@@ -180,7 +180,7 @@ class Scanner:
         if want_table_grad:
             xt = _dev_f32(xt, "xt").reshape(batch, self.n_voxels)
             grad = torch.zeros_like(table.data)
-        o = self.opts(precision, accumulate=accumulate)
+        o = self.opts(precision, accumulate=accumulate, flags=_lib.PSF_OPT_TABLE_GRAD if want_table_grad else 0)
         ws = self.workspace(table, batch, ne, o)
         tc = table.c()
         check(self.L.project_adj(self.h, C.byref(tc), C.byref(o), _ptr(y2), batch, _ptr(events), ne, _ptr(x),

@@ -21,6 +21,8 @@ PSF_EHIP = -5
 PSF_EOVERFLOW = -6
 PSF_EUNSUPPORTED = -7
 
+PSF_OPT_TABLE_GRAD = 1
+
 PSF_FP32 = 0
 PSF_BF16 = 1
 PSF_BF16X2 = 2
@@ -45,7 +47,7 @@ class psf_table(C.Structure):
 
 class psf_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("homog_k", C.c_int32), ("threshold", C.c_double),
-                ("vox_begin", C.c_int64), ("vox_end", C.c_int64), ("accumulate", C.c_int32), ("pad", C.c_int32)]
+                ("vox_begin", C.c_int64), ("vox_end", C.c_int64), ("accumulate", C.c_int32), ("flags", C.c_int32)]
 
 
 class psf_csr(C.Structure):

@@ -239,9 +239,9 @@ extern "C" {
 
 int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
                        int64_t n_events, size_t* bytes) {
-    (void)opts;
     if (!h || !table || !bytes || batch < 0 || n_events < 0) return PSF_EINVAL;
-    *bytes = h->mode3d ? ws3_total(h, table, batch, n_events) : ws_layout(h, table, batch, n_events).total;
+    const int grad = opts && (opts->flags & PSF_OPT_TABLE_GRAD);
+    *bytes = h->mode3d ? ws3_total(h, table, batch, n_events, grad) : ws_layout(h, table, batch, n_events).total;
     return PSF_OK;
 }
 
@@ -399,10 +399,9 @@ int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (h->mode3d) {
-        if (grad) return PSF_EUNSUPPORTED;  // the table gradient is built for the 2D ring
-        return project_adj_3d(h, table, opts, y, 0, batch, events, n_events, x, ws, ws_bytes, (hipStream_t)stream);
-    }
+    if (h->mode3d)
+        return project_adj_3d(h, table, opts, y, 0, batch, events, n_events, x, grad ? xt : nullptr, grad, ws,
+                              ws_bytes, (hipStream_t)stream);
     const WsLayout L = ws_layout(h, table, batch, events ? n_events : 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
@@ -432,7 +431,8 @@ int psf_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts,
     if (st) return st;
     if ((st = check_opts(opts))) return st;
     if (h->mode3d)
-        return project_adj_3d(h, table, opts, nullptr, 1, 1, nullptr, 0, s_dev, ws, ws_bytes, (hipStream_t)stream);
+        return project_adj_3d(h, table, opts, nullptr, 1, 1, nullptr, 0, s_dev, nullptr, nullptr, ws, ws_bytes,
+                              (hipStream_t)stream);
     if (ws_bytes < ws_layout(h, table, 1, 0).total) return PSF_ESIZE;
     const hipStream_t s = (hipStream_t)stream;
     if ((st = zero_header(ws, s))) return st;

@@ -68,15 +68,16 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, plan, x64,
-        ydiag, y32, h64, h32, back, total;
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, uvgrad,
+        g64, plan, x64, ydiag, y32, h64, h32, back, total;
+    int64_t table_elems;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
 };
 
-Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
+Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad) {
     Ws3 L;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -121,6 +122,15 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.cap_uv);
     L.xrep = off;  // cleared at carving and by every fold
     off += align256(sizeof(double) * kXRep * 8 * (size_t)(L.bmax > L.bcsr ? L.bmax : L.bcsr));
+    // table gradient: per-slot accumulator (cleared by the fold into the table) and the FP64 table
+    L.table_elems = (int64_t)t->n_rows * t->n_rows * t->n_sub * t->n_sub * 25;
+    L.uvgrad = L.g64 = 0;
+    if (grad) {
+        L.uvgrad = off;
+        off += align256(sizeof(double) * 400 * (size_t)L.cap_uv);
+        L.g64 = off;
+        off += align256(sizeof(double) * (size_t)L.table_elems);
+    }
     L.plan = off;  // classes, members and row-table offsets of every batch: at most 2 int4 + 1 int per voxel
     off += align256((2 * sizeof(int4) + sizeof(int)) * (size_t)h->n_vox);
     L.x64 = off;
@@ -172,6 +182,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.cap_uv = L.cap_uv;
     S.xrep = at3<double>(ws, L.xrep);
     S.cap_mem = L.bmax > L.bcsr ? L.bmax : L.bcsr;
+    S.uvgrad = L.uvgrad ? at3<double>(ws, L.uvgrad) : nullptr;
     return S;
 }
 
@@ -326,9 +337,10 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
     return PSF_OK;
 }
 
-// x64[batch][n_voxels] += A^T y (y FP32 [batch][n_bins], or all ones)
+// x64[batch][n_voxels] += A^T y (y FP32 [batch][n_bins], or all ones); with
+// g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
-             double* x64, void* ws, hipStream_t s) {
+             double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
     const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
@@ -344,6 +356,8 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             set_batch(a, bt, pd);
             a.batch = nb;
             a.yin = ones ? nullptr : yd;
+            a.xt = xt ? xt + (int64_t)b0 * h->n_vox : nullptr;
+            a.g64 = g64;
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;
@@ -352,9 +366,10 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             if ((st = batch_geometry(h, G, S, a, bt, 0, s))) return st;
             {
                 ProfScope pm_(h, s, 0);
-                HIP_TRY(launch_cyl3d_mma(kModeAdj, G, S, a, s));
+                HIP_TRY(launch_cyl3d_mma(g64 ? kModeAdjGrad : kModeAdj, G, S, a, s));
             }
             HIP_TRY(launch_xrep_fold(S, a, h->n_vox, s));
+            if (g64) HIP_TRY(launch_cyl3d_uvgrad(G, S, a, bt.uv_slots, s));
         }
     }
     return PSF_OK;
@@ -362,15 +377,15 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 
 }  // namespace
 
-size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events) {
-    return ws3_layout(h, t, batch, n_events).total;
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad) {
+    return ws3_layout(h, t, batch, n_events, grad).total;
 }
 
 int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
                     hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, 1, 0);
+    const Ws3 L = ws3_layout(h, t, 1, 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
     if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
@@ -431,7 +446,7 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
                    const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0);
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
@@ -448,10 +463,11 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
 }
 
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
-                   const int32_t* events, int64_t n_events, float* x, void* ws, size_t ws_bytes, hipStream_t s) {
+                   const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
+                   size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0);
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, grad != nullptr);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
@@ -469,8 +485,14 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
     }
     double* x64 = at3<double>(ws, L.x64);
     HIP_TRY(launch_zero_f64(x64, (int64_t)batch * h->n_vox, s));
-    if ((st = adj3_all(h, G, S, L, ybins, ones, batch, x64, ws, s))) return st;
+    double* g64 = grad ? at3<double>(ws, L.g64) : nullptr;
+    if (grad) {
+        HIP_TRY(launch_zero_f64(g64, L.table_elems, s));
+        HIP_TRY(launch_zero_f64(S.uvgrad, 400 * L.cap_uv, s));
+    }
+    if ((st = adj3_all(h, G, S, L, ybins, ones, batch, x64, xt, g64, ws, s))) return st;
     HIP_TRY(launch_finalize(x64, x, (int64_t)batch * h->n_vox, ones ? 0 : o->accumulate, s));
+    if (grad) HIP_TRY(launch_finalize(g64, grad, L.table_elems, 1, s));
     return PSF_OK;
 }
 
@@ -479,7 +501,7 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
                size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, 1, n_events);
+    const Ws3 L = ws3_layout(h, t, 1, n_events, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
@@ -496,7 +518,7 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
     HIP_TRY(launch_lm_ratio(nullptr, y32, events, n_events, G.Nc, NR, (double)randoms, h64, (int*)ws, s));
     HIP_TRY(launch_finalize(h64, h32, h->n_bins, 0, s));
     HIP_TRY(launch_zero_f64(x64, h->n_vox, s));
-    if ((st = adj3_all(h, G, S, L, h32, 0, 1, x64, ws, s))) return st;
+    if ((st = adj3_all(h, G, S, L, h32, 0, 1, x64, nullptr, nullptr, ws, s))) return st;
     HIP_TRY(launch_finalize(x64, back, h->n_vox, 0, s));
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
     return PSF_OK;

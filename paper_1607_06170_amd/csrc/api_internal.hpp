@@ -66,13 +66,14 @@ int zero_header(void* ws, hipStream_t st);
 int read_status(void* ws, hipStream_t st);
 
 // 3D entry points (api3d.hip)
-size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events);
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad);
 int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
                     hipStream_t s);
 int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* x, int batch,
                    const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s);
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
-                   const int32_t* events, int64_t n_events, float* x, void* ws, size_t ws_bytes, hipStream_t s);
+                   const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
+                   size_t ws_bytes, hipStream_t s);
 int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
                float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
                size_t ws_bytes, hipStream_t s);

@@ -78,6 +78,9 @@ struct Scratch3D {
     // index so that concurrent records do not queue on one address
     double* xrep;      // [kXRep][B_mem][8]
     int cap_mem;
+    // table gradient: d loss / d response-row entries of the batch's slots
+    // (layout of uvtab), folded into the table entries after each batch
+    double* uvgrad;    // [cap_uv][16][25], or null
 };
 constexpr int kXRep = 64;
 
@@ -111,6 +114,8 @@ struct Args3D {
     float* val;
     int* status;
     int ones;           // adjoint with y == 1 (sensitivity)
+    const float* xt;    // [batch][nvox] image of the table gradient (adjoint with gradient)
+    double* g64;        // table-gradient accumulator [table entries]
     unsigned long long* tiles;   // count of tiles contracted (workspace header)
     unsigned long long* vtiles;  // count of (voxel, tile) pairs emitted (workspace header)
 };
@@ -168,6 +173,7 @@ hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
                                    hipStream_t st);
 hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
+hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);

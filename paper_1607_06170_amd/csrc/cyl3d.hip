@@ -338,11 +338,12 @@ __device__ __forceinline__ int64_t tab3_idx(int nr, int P, int rt, int rz, int p
 }
 
 // out[(a_t+2)*5 + (a_z+2)]: response of the crystal at transaxial offset a_t
-// and ring r + a_z to a photon entering sub-patch (g, pt; r, pz) from (cx, cy, cz).
-// Rings outside the scanner are kept here (r may be a relative ring of a class);
-// the emission drops them.  Returns 1 when an angle row beyond the table had
-// to be clamped.
-__device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, int pt, int r, int pz, float* out) {
+// and ring r + a_z to a photon entering sub-patch (g, pt; r, pz) from (cx, cy, cz)
+// (IDX: the table entry it comes from, -1 for none).  Rings outside the
+// scanner are kept here (r may be a relative ring of a class); the emission
+// drops them.  Returns 1 when an angle row beyond the table had to be clamped.
+template <bool IDX>
+__device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, int pt, int r, int pz, void* out) {
     int range = 0;
     const int b = g / G.nc, c = g - b * G.nc, P = G.P, nr = G.n_rows;
     const double cs = G.frames[2 * b], sn = G.frames[2 * b + 1];
@@ -389,14 +390,16 @@ __device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, i
         const int a_t = mt ? -amt : amt, cc = cm + amt;
         for (int amz = -2; amz <= 2; ++amz) {
             const int a_z = mz ? -amz : amz;
-            float v = 0.0f;
+            int64_t ti = -1;
             if (cc >= 0 && cc < G.nc) {
-                v = G.table[tab3_idx(nr, P, row_t, row_z, ptm, pzm, amt, amz)];
+                ti = tab3_idx(nr, P, row_t, row_z, ptm, pzm, amt, amz);
             } else if (cc >= G.nc && remap) {
                 const int idx = kv + 1 + (cc - G.nc), az1 = amz - dr;
-                if (idx <= 2 && az1 >= -2 && az1 <= 2) v = G.table[tab3_idx(nr, P, row_bt, row_bz, pt1, pz1, idx, az1)];
+                if (idx <= 2 && az1 >= -2 && az1 <= 2) ti = tab3_idx(nr, P, row_bt, row_bz, pt1, pz1, idx, az1);
             }
-            out[(a_t + 2) * kNb + (a_z + 2)] = v;
+            const int pos = (a_t + 2) * kNb + (a_z + 2);
+            if (IDX) ((int*)out)[pos] = (int)ti;
+            else ((float*)out)[pos] = ti >= 0 ? G.table[ti] : 0.0f;
         }
     }
     return range;
@@ -667,7 +670,7 @@ __global__ void __launch_bounds__(kUvBlock) k_cyl3d_uvtab(Cyl3D G, Scratch3D S, 
         if (row < G.P * G.P) {
             double vx, vy, vz;
             voxel_xyz(G, cl.x, vx, vy, vz);
-            rng = uv_row3(G, vx, vy, vz, g, row / G.P, r, row % G.P, out);
+            rng = uv_row3<false>(G, vx, vy, vz, g, row / G.P, r, row % G.P, out);
         } else {
             for (int q = 0; q < 25; ++q) out[q] = 0.0f;
         }
@@ -686,6 +689,47 @@ hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& 
     if (n_slots > S.cap_uv) return hipErrorInvalidValue;
     const int64_t blocks = (n_slots + kUvBlock / 16 - 1) / (kUvBlock / 16);
     hipLaunchKernelGGL(k_cyl3d_uvtab, dim3((unsigned)blocks), dim3(kUvBlock), 0, st, G, S, a, n_slots);
+    return hipGetLastError();
+}
+
+// Table gradient: each (slot, row) recomputes the table entries its 25 values
+// came from and adds the row's accumulated gradient into them (FP64 atomics),
+// then clears the accumulator for the next batch.
+__global__ void __launch_bounds__(kUvBlock) k_cyl3d_uvgrad(Cyl3D G, Scratch3D S, Args3D A, int64_t n_slots) {
+    __shared__ int idx[kUvBlock * 25];
+    const int tid = threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * (kUvBlock / 16) + tid / 16;
+    const int row = tid & 15;
+    int* out = idx + tid * 25;
+    if (slot >= n_slots) return;
+    double* gr = S.uvgrad + (slot * 16 + row) * 25;
+    if (row >= G.P * G.P) return;
+    int lo = 0, hi = A.n_cls - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.uvoff[mid] <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    const int4 cl = A.cls[lo];
+    const int nr1 = G.NR + cl.w;
+    const int64_t rel = slot - A.uvoff[lo];
+    const int g = (int)(rel / nr1), r = (int)(rel - (int64_t)g * nr1) - cl.w;
+    double vx, vy, vz;
+    voxel_xyz(G, cl.x, vx, vy, vz);
+    uv_row3<true>(G, vx, vy, vz, g, row / G.P, r, row % G.P, out);
+    for (int c = 0; c < 25; ++c) {
+        const double v = gr[c];
+        if (v == 0.0) continue;
+        if (out[c] >= 0) atomicAdd(&A.g64[out[c]], v);
+        gr[c] = 0.0;
+    }
+}
+
+hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st) {
+    if (a.n_cls <= 0 || n_slots <= 0) return hipSuccess;
+    if (n_slots > S.cap_uv || !S.uvgrad || !a.g64) return hipErrorInvalidValue;
+    const int64_t blocks = (n_slots + kUvBlock / 16 - 1) / (kUvBlock / 16);
+    hipLaunchKernelGGL(k_cyl3d_uvgrad, dim3((unsigned)blocks), dim3(kUvBlock), 0, st, G, S, a, n_slots);
     return hipGetLastError();
 }
 
@@ -971,9 +1015,10 @@ struct MmaOps {
 };
 
 struct MmaList {
-    float t[640];          // entry value
-    int key[640];          // transaxial bin (projections) or the class's slot for it (matrix build)
-    unsigned char m[640];  // (a_z + 2) | (b_z + 2) << 3 | (photon 2 first) << 6
+    float t[640];           // entry value
+    int key[640];           // transaxial bin (projections) or the class's slot for it (matrix build)
+    unsigned char m[640];   // (a_z + 2) | (b_z + 2) << 3 | (photon 2 first) << 6
+    unsigned short ab[640]; // a | b << 8: the entry's place in the tile
 };
 
 union MmaLds {
@@ -981,14 +1026,35 @@ union MmaLds {
     MmaList e;
 };
 
+// the adjoint with the table gradient keeps the operands past the emission
+struct MmaLdsGrad {
+    MmaOps o;
+    MmaList e;
+    float Gm[32][33];  // d loss / d T
+    float Gl[640];     // the same, by list entry
+};
+
+template <int MODE>
+struct MmaLdsOf {
+    typedef MmaLds type;
+};
+template <>
+struct MmaLdsOf<kModeAdjGrad> {
+    typedef MmaLdsGrad type;
+};
+
 constexpr int kWavesM = 4;
 
 template <int MODE>
-__global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
-    __shared__ MmaLds ml[kWavesM];
+__global__ void __launch_bounds__(64 * kWavesM) __attribute__((amdgpu_waves_per_eu(MODE == kModeAdjGrad ? 2 : 4)))
+k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
+    typedef typename MmaLdsOf<MODE>::type Lds;
+    constexpr bool kAdj = MODE == kModeAdj || MODE == kModeAdjGrad;
+    constexpr bool kGrad = MODE == kModeAdjGrad;
+    __shared__ Lds ml[kWavesM];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int P = G.P;
-    MmaLds& L = ml[wid];
+    Lds& L = ml[wid];
     const unsigned int nrec = min(*S.rec_count, (unsigned int)S.cap_recs);
     const unsigned int wave0 = blockIdx.x * kWavesM + wid, nwaves = gridDim.x * kWavesM;
     // consecutive records run side by side: their emissions meet in the caches
@@ -1110,6 +1176,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
             L.e.t[pos] = ct[j];
             L.e.key[pos] = key[j];
             L.e.m[pos] = (unsigned char)(a % 5 | ((bz + 2) << 3) | (((swap >> j) & 1u) << 6));
+            if constexpr (kGrad) L.e.ab[pos] = (unsigned short)(a | (bq << 8));
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
@@ -1119,7 +1186,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
         // touches consecutive floats.  Otherwise member by member.
         int lg = 0;
         while ((1 << lg) < cl.z) ++lg;
-        if ((MODE == kModeFwd || MODE == kModeAdj) && lg <= 6) {
+        if ((MODE == kModeFwd || kAdj) && lg <= 6) {
             const int msk = (1 << lg) - 1, sm = lane & msk;
             int R1 = -1, R2 = -1;
             int64_t v = 0;
@@ -1136,33 +1203,51 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 R2 = r2 + me.y;
                 v = me.x;
                 mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
-                if (MODE == kModeFwd && mok) {
+                if ((MODE == kModeFwd || kGrad) && mok) {
+                    const float* xs = kGrad ? A.xt : A.x;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb) xv[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
+                        if (bb < nb) xv[bb] = (double)xs[(int64_t)bb * G.nvox + v];
                 }
             }
             n_vt += __popcll(__ballot(mok && lane == sm));
-            if (mok) {
-                for (int e = lane >> lg; e < total; e += 64 >> lg) {
-                    const int mm = L.e.m[e];
-                    const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
-                    if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) continue;
-                    const float t = L.e.t[e];
-                    const bool sw = (mm >> 6) & 1;
-                    const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR + (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
-                    if (MODE == kModeFwd) {
+            // one list entry: forward atomics, or the adjoint (and gradient) products
+            auto emit = [&](int e, double& gv) {
+                const int mm = L.e.m[e];
+                const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
+                if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
+                const float t = L.e.t[e];
+                const bool sw = (mm >> 6) & 1;
+                const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR +
+                                    (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
+                if (MODE == kModeFwd) {
 #pragma unroll
-                        for (int bb = 0; bb < 8; ++bb)
-                            if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
-                    } else {
+                    for (int bb = 0; bb < 8; ++bb)
+                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
+                } else {
 #pragma unroll
-                        for (int bb = 0; bb < 8; ++bb)
-                            if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
+                    for (int bb = 0; bb < 8; ++bb) {
+                        if (bb >= nb) continue;
+                        const double yv = A.ones ? 1.0 : (double)A.yin[(int64_t)bb * G.nbins + idx];
+                        acc[bb] += (double)t * yv;
+                        if constexpr (kGrad) gv += xv[bb] * yv;
                     }
                 }
+            };
+            if constexpr (kGrad) {
+                // every lane runs the same trip count: the entry's gradient sums across its member lanes
+                for (int e0 = 0; e0 < total; e0 += 64 >> lg) {
+                    const int e = e0 + (lane >> lg);
+                    double gv = 0.0;
+                    if (mok && e < total) emit(e, gv);
+                    for (int off = 1; off <= msk; off <<= 1) gv += __shfl_xor(gv, off, 64);
+                    if (sm == 0 && e < total) L.Gl[e] = (float)gv;
+                }
+            } else if (mok) {
+                double gv = 0.0;
+                for (int e = lane >> lg; e < total; e += 64 >> lg) emit(e, gv);
             }
-            if (MODE == kModeAdj) {
+            if (kAdj) {
 #pragma unroll
                 for (int bb = 0; bb < 8; ++bb) {
                     if (bb >= nb) break;
@@ -1173,6 +1258,8 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 }
             }
         } else {
+        if constexpr (kGrad)
+            for (int e = lane; e < total; e += 64) L.Gl[e] = 0.0f;
         for (int mi = cl.y; mi < cl.y + cl.z; ++mi) {
             const int4 me = A.mem[mi];
             const int R1 = r1 + me.y, R2 = r2 + me.y;
@@ -1183,7 +1270,7 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) {
                 acc[bb] = 0.0;
-                xv[bb] = (MODE == kModeFwd && bb < nb) ? (double)A.x[(int64_t)bb * G.nvox + v] : 0.0;
+                xv[bb] = ((MODE == kModeFwd || kGrad) && bb < nb) ? (double)(kGrad ? A.xt : A.x)[(int64_t)bb * G.nvox + v] : 0.0;
             }
             float* dense = (MODE == kModeCount || MODE == kModeFill)
                                ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
@@ -1194,22 +1281,28 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 const float t = L.e.t[e];
                 const bool sw = (mm >> 6) & 1;
                 const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                if (MODE == kModeFwd || MODE == kModeAdj) {
+                if (MODE == kModeFwd || kAdj) {
                     const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR + diag_index(ri, rj, G.NR);
                     if (MODE == kModeFwd) {
 #pragma unroll
                         for (int bb = 0; bb < 8; ++bb)
                             if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
                     } else {
+                        double gv = 0.0;
 #pragma unroll
-                        for (int bb = 0; bb < 8; ++bb)
-                            if (bb < nb) acc[bb] += A.ones ? (double)t : (double)t * (double)A.yin[(int64_t)bb * G.nbins + idx];
+                        for (int bb = 0; bb < 8; ++bb) {
+                            if (bb >= nb) continue;
+                            const double yv = A.ones ? 1.0 : (double)A.yin[(int64_t)bb * G.nbins + idx];
+                            acc[bb] += (double)t * yv;
+                            if constexpr (kGrad) gv += xv[bb] * yv;
+                        }
+                        if constexpr (kGrad) L.Gl[e] += (float)gv;
                     }
                 } else {
                     atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
                 }
             }
-            if (MODE == kModeAdj) {
+            if (kAdj) {
 #pragma unroll
                 for (int bb = 0; bb < 8; ++bb) {
                     if (bb >= nb) break;
@@ -1220,6 +1313,41 @@ __global__ void __launch_bounds__(64 * kWavesM) k_cyl3d_mma(Cyl3D G, Scratch3D S
                 }
             }
         }
+        }
+        if constexpr (kGrad) {
+            // d loss / d T as a 25 x 25 matrix, then dU = X dT^T and dV = W^T (U dT)
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < 32 * 33; e += 64) (&L.Gm[0][0])[e] = 0.0f;
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < total; e += 64) {
+                const int ab = L.e.ab[e];
+                L.Gm[ab & 0xff][ab >> 8] = L.Gl[e];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int K = P * P, nr1 = G.NR + cl.w;
+            const int64_t su = (int64_t)A.uvoff[vb] + (int64_t)g1 * nr1 + r1 + cl.w;
+            const int64_t sv = (int64_t)A.uvoff[vb] + (int64_t)g2 * nr1 + r2 + cl.w;
+            for (int o = lane; o < K * 25; o += 64) {
+                const int p = o / 25, a = o - p * 25;
+                double d = 0.0;
+                for (int b = 0; b < 25; ++b) d += (double)L.o.X[p][b] * (double)L.Gm[a][b];
+                if (d != 0.0) atomicAdd(&S.uvgrad[(su * 16 + p) * 25 + a], d);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // Y = U dT over the spent X
+            for (int o = lane; o < K * 25; o += 64) {
+                const int p = o / 25, b = o - p * 25;
+                double d = 0.0;
+                for (int a = 0; a < 25; ++a) d += (double)L.o.U[p][a] * (double)L.Gm[a][b];
+                L.o.X[p][b] = (float)d;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int o = lane; o < K * 25; o += 64) {
+                const int q = o / 25, b = o - q * 25;
+                double d = 0.0;
+                for (int p = 0; p < K; ++p) d += (double)L.o.W[p][q] * (double)L.o.X[p][b];
+                if (d != 0.0) atomicAdd(&S.uvgrad[(sv * 16 + q) * 25 + b], d);
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1255,6 +1383,10 @@ hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const 
             break;
         case kModeAdj:
             hipLaunchKernelGGL(k_cyl3d_mma<kModeAdj>, grid, block, 0, st, G, S, a);
+            break;
+        case kModeAdjGrad:
+            if (!S.uvgrad || !a.xt) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdjGrad>, grid, block, 0, st, G, S, a);
             break;
         default:
             return hipErrorInvalidValue;

@@ -180,6 +180,46 @@ def test_listmode_small_scanner(torch, oracle, small_ref):
     np.testing.assert_allclose(xg.cpu().numpy(), xo, rtol=2e-5, atol=2e-5 * xo.max())
 
 
+def test_table_gradient_small_scanner(torch, oracle, small_ref):
+    """d <y, A xt> / d table (two images, all bins weighted) against the
+    oracle's, and the autograd wrapper against the direct call."""
+    from paper_1607_06170_amd import PsfProject
+    td, cols, flags = small_ref
+    nr = SMALL["n_rows"]
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, nr, 4, 1.0)
+    n = sc.n_voxels
+    rng = np.random.default_rng(77)
+    xt = np.zeros((2, n))
+    vox = [np.sort(rng.choice(n, 30, replace=False)) for _ in range(2)]
+    for b in range(2):
+        xt[b, vox[b]] = rng.random(30)
+    gy = rng.random((2, sc.n_bins))
+    xf = xt.astype(np.float32).astype(np.float64)
+    gf = gy.astype(np.float32).astype(np.float64)
+    tab_o = oracle.TableRef(td, nr, 4, 1.0)
+    allb = np.arange(sc.n_bins)
+    ref = sum(oracle.table_grad_3d(SMALL, tab_o, vox[b], xf[b, vox[b]], allb, gf[b]) for b in range(2))
+    xd = torch.tensor(xt, dtype=torch.float32, device="cuda")
+    gyd = torch.tensor(gy, dtype=torch.float32, device="cuda")
+    xb, grad = sc.project_adj(t, gyd, xt=xd, want_table_grad=True)
+    sc.check()
+    grad = grad.cpu().numpy().reshape(ref.shape)
+    assert np.count_nonzero(ref) > 1000
+    np.testing.assert_allclose(grad, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+    # the adjoint returned with it is the plain one
+    A_T = _sparse(cols, sc.n_bins)
+    np.testing.assert_allclose(xb.cpu().numpy(), (A_T @ gf.T).T, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xb.cpu().numpy()).max())
+    # autograd: backward of <gy, y(xt, table)>
+    tdat = t.data.clone().requires_grad_(True)
+    xr = xd.clone().requires_grad_(True)
+    y = PsfProject.apply(xr, tdat, sc, (nr, 4, 1.0))
+    (y * gyd).sum().backward()
+    np.testing.assert_allclose(tdat.grad.cpu().numpy().reshape(ref.shape), ref, rtol=1e-5,
+                               atol=1e-6 * np.abs(ref).max())
+    np.testing.assert_allclose(xr.grad.cpu().numpy(), xb.cpu().numpy(), rtol=1e-6)
+
+
 @pytest.mark.parametrize("ijk", [(64, 64, 48), (20, 100, 3)])
 def test_sysmat_full_scanner_sampled(torch, oracle, ijk):
     """The 128 x 128 x 96 configuration: single voxels' rows against the oracle."""
