@@ -11,7 +11,7 @@ using namespace psf;
 
 namespace {
 
-constexpr int kBatchCsr = 48;     // voxels per batch of the matrix build (dense accumulators)
+constexpr int kBatchCsr = 128;    // voxels per batch of the matrix build (dense accumulators, FP32)
 constexpr int kBatchProj = 128;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;

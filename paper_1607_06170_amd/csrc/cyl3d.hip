@@ -1180,13 +1180,13 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
-        // emission.  Projections with at most 64 members: lane = (entry, member),
-        // the member fixed per lane (lane mod the member count rounded up to a
-        // power of two); sinograms in the diagonal layout, so a lane group
+        // emission.  With at most 64 members: lane = (entry, member), the member
+        // fixed per lane (lane mod the member count rounded up to a power of
+        // two); projection sinograms in the diagonal layout, so a lane group
         // touches consecutive floats.  Otherwise member by member.
         int lg = 0;
         while ((1 << lg) < cl.z) ++lg;
-        if ((MODE == kModeFwd || kAdj) && lg <= 6) {
+        if (lg <= 6) {
             const int msk = (1 << lg) - 1, sm = lane & msk;
             int R1 = -1, R2 = -1;
             int64_t v = 0;
@@ -1211,6 +1211,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
             }
             n_vt += __popcll(__ballot(mok && lane == sm));
+            float* dense = (MODE == kModeCount || MODE == kModeFill) && mok
+                               ? S.dense + (int64_t)(cl.y + sm) * S.cap_slots * G.NR * G.NR : nullptr;
             // one list entry: forward atomics, or the adjoint (and gradient) products
             auto emit = [&](int e, double& gv) {
                 const int mm = L.e.m[e];
@@ -1218,6 +1220,11 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
                 const float t = L.e.t[e];
                 const bool sw = (mm >> 6) & 1;
+                if (MODE == kModeCount || MODE == kModeFill) {
+                    const int ri = sw ? rb : ra, rj = sw ? ra : rb;
+                    atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
+                    return;
+                }
                 const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR +
                                     (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
                 if (MODE == kModeFwd) {
