@@ -106,6 +106,12 @@ typedef struct {
 /* psf_opts.flags: project_adj will be asked for the table gradient (3D: the
  * workspace then holds its per-batch accumulator). */
 #define PSF_OPT_TABLE_GRAD 1
+/* psf_opts.flags: build_psf_sysmat's count phase keeps the rows it compacts in
+ * the workspace (psf_workspace_size adds room for them, about 1 MB per voxel
+ * of the range, at most 32 GB), and a fill phase that follows on the same
+ * workspace with the same table and options copies them instead of
+ * recomputing; rows that did not fit are recomputed. */
+#define PSF_OPT_STAGE_CSR 2
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
 typedef struct {

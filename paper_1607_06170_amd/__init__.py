@@ -127,10 +127,11 @@ class Scanner:
         return Table(t, n_rows, n_sub, step_deg)
 
     def build_psf_sysmat(self, table: Table, threshold: float = 0.0, vox_begin: int = 0, vox_end: int = -1,
-                         precision: int = PSF_FP32):
-        """CSR of A^T for voxels [vox_begin, vox_end): (row_ptr int64, col int32, val float32)."""
+                         precision: int = PSF_FP32, stage: bool = True):
+        """CSR of A^T for voxels [vox_begin, vox_end): (row_ptr int64, col int32, val float32).
+        stage: the count phase keeps its rows in the workspace for the fill phase (3D)."""
         torch = _torch()
-        o = self.opts(precision, threshold, vox_begin, vox_end)
+        o = self.opts(precision, threshold, vox_begin, vox_end, flags=_lib.PSF_OPT_STAGE_CSR if stage else 0)
         ve = self.n_voxels if vox_end is None or vox_end < 0 else vox_end
         n = ve - vox_begin
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=self.device)

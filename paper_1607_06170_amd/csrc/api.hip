@@ -240,8 +240,7 @@ extern "C" {
 int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
                        int64_t n_events, size_t* bytes) {
     if (!h || !table || !bytes || batch < 0 || n_events < 0) return PSF_EINVAL;
-    const int grad = opts && (opts->flags & PSF_OPT_TABLE_GRAD);
-    *bytes = h->mode3d ? ws3_total(h, table, batch, n_events, grad) : ws_layout(h, table, batch, n_events).total;
+    *bytes = h->mode3d ? ws3_total(h, table, batch, n_events, opts) : ws_layout(h, table, batch, n_events).total;
     return PSF_OK;
 }
 

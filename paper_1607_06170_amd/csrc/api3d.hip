@@ -1,6 +1,7 @@
 // 3D-scanner halves of the C-ABI entry points: argument checks, workspace
 // carving and the batched launches of the cyl3d.hip kernels.
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <vector>
@@ -19,6 +20,22 @@ constexpr int kCapSlots = 4096;
 constexpr int64_t kRecsPerVoxel = 65536;   // tile records allowed for one voxel
 constexpr int64_t kRecBudget = 1 << 21;    // tile records per batch (1.1 KB each)
 constexpr int kUvRings = 16;               // response-row table: rings per batch beyond the members, in NR
+constexpr int64_t kStagePerVoxel = 131072;  // staged CSR entries allowed per voxel of the range
+constexpr int64_t kStageMax = (int64_t)1 << 32;  // at most 32 GB of staged entries
+
+// the count phase's record of what it staged (workspace header, kWsStage)
+struct StageState {
+    unsigned long long cur;  // device: entries used
+    int full;                // device: a row did not fit
+    int batches;             // device: batches fully staged
+    unsigned long long magic;
+    const void* table;
+    int64_t vb, ve;
+    double threshold;
+    int32_t precision, n_rows, n_sub, n_batches;
+};
+static_assert(kWsStage + sizeof(StageState) <= kWsHeader, "stage state fits the header");
+constexpr unsigned long long kStageMagic = 0x5053465354414745ull;
 
 Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
     Cyl3D G;
@@ -69,15 +86,15 @@ int check3d(const psf_handle* h, const psf_table* t) {
 
 struct Ws3 {
     size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, uvgrad,
-        g64, plan, x64, ydiag, y32, h64, h32, back, total;
-    int64_t table_elems;
+        g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
+    int64_t table_elems, cap_stage;
     int bmax, bcsr, cap_slots;
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
 };
 
-Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad) {
+Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad, int64_t stage_rows) {
     Ws3 L;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -133,6 +150,20 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     }
     L.plan = off;  // classes, members and row-table offsets of every batch: at most 2 int4 + 1 int per voxel
     off += align256((2 * sizeof(int4) + sizeof(int)) * (size_t)h->n_vox);
+    // matrix build staging (count phase -> fill phase)
+    L.cap_stage = stage_rows > 0 ? (stage_rows * kStagePerVoxel < kStageMax ? stage_rows * kStagePerVoxel : kStageMax)
+                                 : 0;
+    L.stage_off = L.stage_tot = L.stage_col = L.stage_val = 0;
+    if (L.cap_stage > 0) {
+        L.stage_off = off;
+        off += align256(sizeof(int64_t) * (size_t)stage_rows);
+        L.stage_tot = off;
+        off += align256(sizeof(int64_t) * (size_t)L.bcsr);
+        L.stage_col = off;
+        off += align256(sizeof(int32_t) * (size_t)L.cap_stage);
+        L.stage_val = off;
+        off += align256(sizeof(float) * (size_t)L.cap_stage);
+    }
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.ydiag = off;  // up to 8 sinograms in the diagonal ring-pair layout
@@ -377,15 +408,22 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 
 }  // namespace
 
-size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad) {
-    return ws3_layout(h, t, batch, n_events, grad).total;
+// rows of the build's range when its count phase stages them, else 0
+static int64_t stage_rows(const psf_handle* h, const psf_opts* o) {
+    if (!o || !(o->flags & PSF_OPT_STAGE_CSR)) return 0;
+    const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
+    return ve > vb && vb >= 0 && ve <= h->n_vox ? ve - vb : 0;
+}
+
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, const psf_opts* o) {
+    return ws3_layout(h, t, batch, n_events, o && (o->flags & PSF_OPT_TABLE_GRAD), stage_rows(h, o)).total;
 }
 
 int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
                     hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, 1, 0, 0);
+    const Ws3 L = ws3_layout(h, t, 1, 0, o->flags & PSF_OPT_TABLE_GRAD, stage_rows(h, o));
     if (ws_bytes < L.total) return PSF_ESIZE;
     const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
     if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
@@ -393,7 +431,20 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
     const int phase_fill = csr->col != nullptr;
+    const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
+    // what a count phase on this workspace staged for us (read before the header is cleared)
+    int staged = 0;
+    StageState ss;
+    if (phase_fill && stage) {
+        HIP_TRY(hipMemcpyAsync(&ss, (char*)ws + kWsStage, sizeof(ss), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ss.magic == kStageMagic && ss.table == (const void*)t->data && ss.vb == vb && ss.ve == ve &&
+            ss.threshold == o->threshold && ss.precision == o->precision && ss.n_rows == t->n_rows &&
+            ss.n_sub == t->n_sub && ss.n_batches == (int32_t)pl.batches.size())
+            staged = ss.batches < (int)pl.batches.size() ? ss.batches : (int)pl.batches.size();
+    }
     if ((st = zero_header(ws, s))) return st;
     if (phase_fill) {
         if (!csr->val) return PSF_EINVAL;
@@ -406,24 +457,46 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         }
     }
     // the dense accumulators start clean; the compaction leaves them clean
-    HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
-    // the count phase adds each chunk's count into row_ptr[row + 1]
+    if (!(phase_fill && staged == (int)pl.batches.size()))
+        HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
+    // the count phase writes each row's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
     PlanDev pd;
     if ((st = upload_plan(pl, ws, L, s, &pd))) return st;
-    for (const Batch3& bt : pl.batches) {
-        Args3D a;
-        memset(&a, 0, sizeof(a));
+    Args3D a0;
+    memset(&a0, 0, sizeof(a0));
+    a0.batch = 1;
+    a0.threshold = o->threshold;
+    a0.row_ptr = csr->row_ptr;
+    a0.col = csr->col;
+    a0.val = csr->val;
+    a0.status = (int*)ws;
+    a0.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
+    a0.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
+    if (stage) {
+        a0.stage_off = at3<int64_t>(ws, L.stage_off);  // indexed by row (voxel - vox_begin)
+        a0.stage_tot = at3<int64_t>(ws, L.stage_tot);
+        a0.stage_col = at3<int32_t>(ws, L.stage_col);
+        a0.stage_val = at3<float>(ws, L.stage_val);
+        a0.cap_stage = L.cap_stage;
+        StageState* dss = (StageState*)((char*)ws + kWsStage);
+        a0.stage_cur = &dss->cur;
+        a0.stage_full = &dss->full;
+        a0.stage_batches = &dss->batches;
+        if (!phase_fill) HIP_TRY(launch_zero_f64((double*)a0.stage_tot, L.bcsr, s));
+    }
+    // fill phase: rows the count phase staged are copied
+    if (staged > 0) {
+        Args3D a = a0;
+        set_batch(a, pl.batches[0], pd);
+        const int n_rows = staged < (int)pl.batches.size() ? pl.batches[staged].mem0 : (int)pl.mem.size();
+        HIP_TRY(launch_stage_copy(a, n_rows, s));
+    }
+    for (int bi = staged; bi < (int)pl.batches.size(); ++bi) {
+        const Batch3& bt = pl.batches[bi];
+        Args3D a = a0;
         set_batch(a, bt, pd);
-        a.batch = 1;
-        a.threshold = o->threshold;
-        a.row_ptr = csr->row_ptr;
-        a.col = csr->col;
-        a.val = csr->val;
-        a.status = (int*)ws;
-        a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
-        a.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
+        a.stage = stage && !phase_fill;
         if ((st = batch_geometry(h, G, S, a, bt, 1, s))) return st;
         {
             ProfScope pm_(h, s, 0);
@@ -435,6 +508,22 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));
         int64_t nnz = 0;
         HIP_TRY(hipMemcpyAsync(&nnz, csr->row_ptr + (ve - vb), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (stage) {  // sign what was staged for the fill phase
+            StageState host;
+            memset(&host, 0, sizeof(host));
+            host.magic = kStageMagic;
+            host.table = (const void*)t->data;
+            host.vb = vb;
+            host.ve = ve;
+            host.threshold = o->threshold;
+            host.precision = o->precision;
+            host.n_rows = t->n_rows;
+            host.n_sub = t->n_sub;
+            host.n_batches = (int32_t)pl.batches.size();
+            const size_t head = offsetof(StageState, magic);
+            HIP_TRY(hipMemcpyAsync((char*)ws + kWsStage + head, (const char*)&host + head, sizeof(host) - head,
+                                   hipMemcpyHostToDevice, s));
+        }
         st = read_status(ws, s);
         csr->nnz = nnz;
         return st;
@@ -446,7 +535,7 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
                    const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, 0);
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
@@ -467,7 +556,7 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
                    size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, grad != nullptr);
+    const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, grad != nullptr, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);
@@ -501,7 +590,7 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
                size_t ws_bytes, hipStream_t s) {
     int st = check3d(h, t);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, 1, n_events, 0);
+    const Ws3 L = ws3_layout(h, t, 1, n_events, 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     const Cyl3D G = make_cyl3d(h, t, o);
     const Scratch3D S = make_scratch(ws, L);

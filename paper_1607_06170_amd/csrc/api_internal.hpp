@@ -66,7 +66,7 @@ int zero_header(void* ws, hipStream_t st);
 int read_status(void* ws, hipStream_t st);
 
 // 3D entry points (api3d.hip)
-size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad);
+size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, const psf_opts* o);
 int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
                     hipStream_t s);
 int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* x, int batch,

@@ -26,6 +26,9 @@ constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or t
 constexpr size_t kWsHeader = 256;
 constexpr size_t kWsTileCounter = 64;
 constexpr size_t kWsVoxTileCounter = 72;
+// Bytes 128..255: the matrix build's staging state (cursor, full flag, staged
+// batches, then the signature of the count phase that filled it).
+constexpr size_t kWsStage = 128;
 
 // Everything a 2D-ring kernel needs, passed by value.
 struct Ring2D {
@@ -116,6 +119,16 @@ struct Args3D {
     int ones;           // adjoint with y == 1 (sensitivity)
     const float* xt;    // [batch][nvox] image of the table gradient (adjoint with gradient)
     double* g64;        // table-gradient accumulator [table entries]
+    // matrix build, count phase with staging: rows compacted into the stage
+    int stage;
+    int64_t* stage_off;         // [rows of the range]  entry offset of a staged row, -1 if not staged
+    int64_t* stage_tot;         // [batch members]  kept entries (chunk sums)
+    int32_t* stage_col;         // [cap_stage]
+    float* stage_val;           // [cap_stage]
+    int64_t cap_stage;
+    unsigned long long* stage_cur;  // workspace header: entries used
+    int* stage_full;                // workspace header: a row did not fit (sticky)
+    int* stage_batches;             // workspace header: batches fully staged
     unsigned long long* tiles;   // count of tiles contracted (workspace header)
     unsigned long long* vtiles;  // count of (voxel, tile) pairs emitted (workspace header)
 };
@@ -177,6 +190,7 @@ hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D&
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
 hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,

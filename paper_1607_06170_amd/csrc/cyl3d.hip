@@ -1432,6 +1432,8 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 // count.  Fill phase: a first pass stores the per-chunk counts, the second
 // writes each chunk at its offset (row start + counts of the chunks before
 // it), in order.  The last pass over a chunk clears it for the next batch.
+// Count phase with staging: the fill passes run, the row going to the stage
+// at an offset the allocator gave it (k_stage_alloc, between the passes).
 
 constexpr int kBlockC = 512;
 constexpr int64_t kChunk = 32768;
@@ -1465,8 +1467,13 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             s_run = off;
         }
         __syncthreads();
-        start = A.row_ptr[row];
-        cap = A.row_ptr[row + 1] - start;
+        if (A.stage) {  // row_ptr[row + 1] holds the row's count until the scan
+            start = A.stage_off[row];
+            cap = start >= 0 ? A.row_ptr[row + 1] : 0;
+        } else {
+            start = A.row_ptr[row];
+            cap = A.row_ptr[row + 1] - start;
+        }
     } else {
         if (tid == 0) s_run = 0;
     }
@@ -1479,7 +1486,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             a = dense[i];
             if (MODE != kCompactChunks) dense[i] = 0.0f;  // leave the accumulator clean
         }
-        const bool keep = a > 0.0f && (double)a >= A.threshold;
+        const bool keep = a > 0.0f && (double)a >= A.threshold && !(MODE == kCompactFill && A.stage && start < 0);
         const unsigned long long m = __ballot(keep);
         const int pre = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) wave_tot[wid] = __popcll(m);
@@ -1494,8 +1501,14 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             const int64_t pos = run + off + pre;
             if (pos < cap) {
                 const int64_t slot = i / nrr, rr = i - slot * nrr;
-                A.col[start + pos] = (int32_t)((int64_t)stb[slot] * nrr + rr);
-                A.val[start + pos] = (float)a;
+                const int32_t b = (int32_t)((int64_t)stb[slot] * nrr + rr);
+                if (A.stage) {
+                    A.stage_col[start + pos] = b;
+                    A.stage_val[start + pos] = a;
+                } else {
+                    A.col[start + pos] = b;
+                    A.val[start + pos] = a;
+                }
             } else {
                 atomicOr(A.status, kStatOverflow);
             }
@@ -1507,8 +1520,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     if (tid == 0) {
         const int64_t n = s_run - run0;
         if (MODE == kCompactCount) atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
-        else if (MODE == kCompactChunks) ccount[chunk] = (int)n;
-        else if (c1 == total && s_run != cap) atomicOr(A.status, kStatOverflow);
+        else if (MODE == kCompactChunks) {
+            ccount[chunk] = (int)n;
+            if (A.stage) atomicAdd((unsigned long long*)&A.stage_tot[mi], (unsigned long long)n);
+        } else if (c1 == total && s_run != cap && !(A.stage && start < 0)) atomicOr(A.status, kStatOverflow);
     }
 }
 
@@ -1516,13 +1531,66 @@ int64_t cyl3d_max_chunks(int cap_slots, int NR) {
     return ((int64_t)cap_slots * NR * NR + kChunk - 1) / kChunk;
 }
 
+// Staging allocator of one batch (one wavefront): members in order take
+// consecutive stage entries while they fit; the first that does not sets the
+// sticky full flag, and no later row is staged.  Sets each row's count in
+// row_ptr[row + 1] and clears the chunk sums.
+__global__ void __launch_bounds__(64) k_stage_alloc(Args3D A) {
+    const int lane = threadIdx.x;
+    unsigned long long cur = *A.stage_cur;
+    int full = *A.stage_full;
+    for (int m0 = 0; m0 < A.n_mem; m0 += 64) {
+        const int mi = m0 + lane;
+        const bool in = mi < A.n_mem;
+        const int64_t tot = in ? A.stage_tot[mi] : 0;
+        const int64_t row = in ? A.mem[mi].w : 0;
+        int64_t pre = tot;  // inclusive prefix over the lanes
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t o = __shfl_up(pre, off, 64);
+            if (lane >= off) pre += o;
+        }
+        const bool fits = !full && cur + (unsigned long long)pre <= (unsigned long long)A.cap_stage;
+        if (in) {
+            A.row_ptr[row + 1] = tot;
+            A.stage_off[row] = fits ? (int64_t)(cur + pre - tot) : -1;
+            A.stage_tot[mi] = 0;
+        }
+        const unsigned long long ok = __ballot(in && fits), all = __ballot(in);
+        if (ok != all) full = 1;
+        cur += (unsigned long long)__shfl(pre, 63, 64) * (full ? 0ull : 1ull);
+    }
+    if (lane == 0) {
+        *A.stage_cur = cur;
+        *A.stage_full = full;
+        if (!full) *A.stage_batches += 1;
+    }
+}
+
+// fill phase: staged rows of the members [0, n) copied to their CSR place
+__global__ void __launch_bounds__(256) k_stage_copy(Args3D A) {
+    const int64_t row = A.mem[blockIdx.x].w;
+    const int64_t src = A.stage_off[row], dst = A.row_ptr[row], n = A.row_ptr[row + 1] - dst;
+    if (src < 0) return;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        A.col[dst + i] = A.stage_col[src + i];
+        A.val[dst + i] = A.stage_val[src + i];
+    }
+}
+
+hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stage_copy, dim3(n_rows), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_mem <= 0) return hipSuccess;
     const dim3 grid((unsigned)S.max_chunks, a.n_mem), block(kBlockC);
-    if (mode == kModeCount) {
+    if (mode == kModeCount && !a.stage) {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactCount>, grid, block, 0, st, G, S, a);
     } else {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactChunks>, grid, block, 0, st, G, S, a);
+        if (a.stage) hipLaunchKernelGGL(k_stage_alloc, dim3(1), dim3(64), 0, st, a);
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactFill>, grid, block, 0, st, G, S, a);
     }
     return hipGetLastError();

@@ -103,6 +103,41 @@ def test_sysmat_small_ranges(torch, oracle, small_ref, vb, ve):
     _check_rows(oracle, rp, col, val, cols, flags, np.arange(vb, ve))
 
 
+def test_sysmat_staging_paths(torch, oracle, small_ref):
+    """The fill phase copies what the count phase staged; without staging, or
+    when another call used the workspace in between, it recomputes: the three
+    give the same matrix."""
+    import ctypes as C
+    from paper_1607_06170_amd import _lib
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    vb, ve = 40, 230
+    ref = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, stage=False)
+    got = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, stage=True)
+    # same pattern; values equal up to the order of the FP32 atomic sums
+    assert torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1])
+    np.testing.assert_allclose(got[2].cpu().numpy(), ref[2].cpu().numpy(), rtol=1e-6)
+    # count phase, then a projection on the same workspace, then the fill phase
+    o = sc.opts(0, 0.0, vb, ve, flags=_lib.PSF_OPT_STAGE_CSR)
+    ws = sc.workspace(t, 1, 0, o)
+    tc = t.c()
+    n = ve - vb
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    csr = _lib.psf_csr(n, 0, row_ptr.data_ptr(), None, None)
+    ptr = lambda x: C.c_void_p(x.data_ptr())
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(sc.L.build_psf_sysmat(sc.h, C.byref(tc), C.byref(o), ptr(ws), ws.numel(), C.byref(csr), stream), "count")
+    sc.project_fwd(t, torch.ones(1, sc.n_voxels, device="cuda"))
+    col = torch.empty(csr.nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(csr.nnz, dtype=torch.float32, device="cuda")
+    csr.col, csr.val = col.data_ptr(), val.data_ptr()
+    _lib.check(sc.L.build_psf_sysmat(sc.h, C.byref(tc), C.byref(o), ptr(ws), ws.numel(), C.byref(csr), stream), "fill")
+    assert torch.equal(row_ptr, ref[0]) and torch.equal(col, ref[1])
+    np.testing.assert_allclose(val.cpu().numpy(), ref[2].cpu().numpy(), rtol=1e-6)
+    _check_rows(oracle, row_ptr, col, val, cols, flags, np.arange(vb, ve))
+
+
 def test_projections_small_scanner(torch, oracle, small_ref):
     td, cols, flags = small_ref
     sc = _scanner(SMALL)
