@@ -85,7 +85,7 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, uvgrad,
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
         g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
     int64_t table_elems, cap_stage;
     int bmax, bcsr, cap_slots;
@@ -139,6 +139,8 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.cap_uv);
     L.xrep = off;  // cleared at carving and by every fold
     off += align256(sizeof(double) * kXRep * 8 * (size_t)(L.bmax > L.bcsr ? L.bmax : L.bcsr));
+    L.xm = off;
+    off += align256(sizeof(float) * 8 * (size_t)(L.bmax > L.bcsr ? L.bmax : L.bcsr));
     // table gradient: per-slot accumulator (cleared by the fold into the table) and the FP64 table
     L.table_elems = (int64_t)t->n_rows * t->n_rows * t->n_sub * t->n_sub * 25;
     L.uvgrad = L.g64 = 0;
@@ -214,6 +216,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.xrep = at3<double>(ws, L.xrep);
     S.cap_mem = L.bmax > L.bcsr ? L.bmax : L.bcsr;
     S.uvgrad = L.uvgrad ? at3<double>(ws, L.uvgrad) : nullptr;
+    S.xm = at3<float>(ws, L.xm);
     return S;
 }
 
@@ -354,6 +357,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.batch = nb;
             a.x = x + (int64_t)b0 * h->n_vox;
             a.y = yd;
+            HIP_TRY(launch_gather_members(S, a, a.x, h->n_vox, s));
             a.status = (int*)ws;
             a.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
         a.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
@@ -389,6 +393,7 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.yin = ones ? nullptr : yd;
             a.xt = xt ? xt + (int64_t)b0 * h->n_vox : nullptr;
             a.g64 = g64;
+            if (a.xt) HIP_TRY(launch_gather_members(S, a, a.xt, h->n_vox, s));
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
             a.status = (int*)ws;

@@ -84,15 +84,19 @@ struct Scratch3D {
     // table gradient: d loss / d response-row entries of the batch's slots
     // (layout of uvtab), folded into the table entries after each batch
     double* uvgrad;    // [cap_uv][16][25], or null
+    float* xm;         // [B_mem][8]  the batch members' image values (forward input, or the gradient's image)
 };
 constexpr int kXRep = 64;
 
 // tile record (ints and floats in one array):
 //   [0] g1  [1] g2  [2] (r1 + 512) | (r2 + 512) << 10 | class << 20  [3] n samples
-//   [4 + k]        pt1 | pt2 << 8 of sample k (the transaxial sub-segments of the bundle)
-//   [20 + 16k + q] W of sample k between axial sub-positions pz1 = q / P and pz2 = q % P
+//   [4] row-table slot of U (g1, r1)  [5] of V (g2, r2)
+//   [6] the class's first member | member count << 16  [7] 0
+//   [8 + k]        pt1 | pt2 << 8 of sample k (the transaxial sub-segments of the bundle)
+//   [24 + 16k + q] W of sample k between axial sub-positions pz1 = q / P and pz2 = q % P
 // rings are relative to the class's reference member
-constexpr int kRecHead = 20;
+constexpr int kRecPts = 8;
+constexpr int kRecHead = 24;
 constexpr int kRecFloats = kRecHead + 16 * 16;
 
 // Voxels are processed in classes: voxels of one z-column whose z differ by a
@@ -193,6 +197,7 @@ hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, co
 hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
+hipError_t launch_gather_members(const Scratch3D& S, const Args3D& a, const float* x, int64_t nvox, hipStream_t st);
 hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,
                             hipStream_t st);
 int64_t cyl3d_max_chunks(int cap_slots, int NR);

@@ -976,8 +976,12 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                     h[1] = g2;
                     h[2] = (r1 + 512) | ((r2 + 512) << 10) | (vb << 20);
                     h[3] = nsmp;
+                    h[4] = A.uvoff[vb] + g1 * nr1 + r1 + smax;
+                    h[5] = A.uvoff[vb] + g2 * nr1 + r2 + smax;
+                    h[6] = cl.y | (cl.z << 16);
+                    h[7] = 0;
                 }
-                if (lane < nsmp) h[4 + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
+                if (lane < nsmp) h[kRecPts + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
                 for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wr[j][e >> 4][e & 15];
             }
             __builtin_amdgcn_wave_barrier();
@@ -1069,10 +1073,11 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         if (nsmp == 0) continue;  // a reserved slot left unused
         const int g1 = h[0], g2 = h[1], hv = h[2];
         const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
-        const int4 cl = A.cls[vb];
-        const int nr1 = G.NR + cl.w;
-        const float* urow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g1 * nr1 + r1 + cl.w) * 400;
-        const float* vrow = S.uvtab + ((int64_t)A.uvoff[vb] + (int64_t)g2 * nr1 + r2 + cl.w) * 400;
+        const int64_t su = h[4], sv = h[5];
+        // the class's members: first (batch index) and count; member s has ring shift s
+        const int4 cl = make_int4(0, h[6] & 0xffff, h[6] >> 16, 0);
+        const float* urow = S.uvtab + su * 400;
+        const float* vrow = S.uvtab + sv * 400;
         for (int e = lane; e < 256; e += 64) L.o.W[e >> 4][e & 15] = 0.0f;
         for (int e = lane; e < 400; e += 64) L.o.U[e / 25][e % 25] = urow[e];
         for (int e = lane; e < 400; e += 64) L.o.V[e / 25][e % 25] = vrow[e];
@@ -1081,7 +1086,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         for (int e = lane; e < nsmp * 16; e += 64) {
             const int k = e >> 4, q = e & 15;
             if (q >= P * P) continue;
-            const int pts = h[4 + k], pt1 = pts & 0xff, pt2 = pts >> 8;
+            const int pts = h[kRecPts + k], pt1 = pts & 0xff, pt2 = pts >> 8;
             L.o.W[pt1 * P + q / P][pt2 * P + q % P] = rec[kRecHead + e];
         }
         __builtin_amdgcn_wave_barrier();
@@ -1189,7 +1194,6 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         if (lg <= 6) {
             const int msk = (1 << lg) - 1, sm = lane & msk;
             int R1 = -1, R2 = -1;
-            int64_t v = 0;
             double xv[8], acc[8];
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) {
@@ -1198,16 +1202,14 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             }
             bool mok = false;
             if (sm < cl.z) {
-                const int4 me = A.mem[cl.y + sm];
-                R1 = r1 + me.y;
-                R2 = r2 + me.y;
-                v = me.x;
+                R1 = r1 + sm;
+                R2 = r2 + sm;
                 mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
                 if ((MODE == kModeFwd || kGrad) && mok) {
-                    const float* xs = kGrad ? A.xt : A.x;
+                    const float* xs = S.xm + (int64_t)(cl.y + sm) * 8;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb) xv[bb] = (double)xs[(int64_t)bb * G.nvox + v];
+                        if (bb < nb) xv[bb] = (double)xs[bb];
                 }
             }
             n_vt += __popcll(__ballot(mok && lane == sm));
@@ -1331,9 +1333,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 L.Gm[ab & 0xff][ab >> 8] = L.Gl[e];
             }
             __builtin_amdgcn_wave_barrier();
-            const int K = P * P, nr1 = G.NR + cl.w;
-            const int64_t su = (int64_t)A.uvoff[vb] + (int64_t)g1 * nr1 + r1 + cl.w;
-            const int64_t sv = (int64_t)A.uvoff[vb] + (int64_t)g2 * nr1 + r2 + cl.w;
+            const int K = P * P;
             for (int o = lane; o < K * 25; o += 64) {
                 const int p = o / 25, a = o - p * 25;
                 double d = 0.0;
@@ -1398,6 +1398,23 @@ hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const 
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// the batch members' image values: xm[member][image] (one gather per batch,
+// so the contraction reads them with the member's index)
+__global__ void k_gather_members(Scratch3D S, Args3D A, const float* x, int64_t nvox) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // member * 8 + image
+    if (i >= A.n_mem * 8) return;
+    const int mi = i >> 3, bb = i & 7;
+    S.xm[i] = bb < A.batch ? x[(int64_t)bb * nvox + A.mem[mi].x] : 0.0f;
+}
+
+hipError_t launch_gather_members(const Scratch3D& S, const Args3D& a, const float* x, int64_t nvox, hipStream_t st) {
+    if (a.n_mem <= 0) return hipSuccess;
+    if (a.n_mem > S.cap_mem) return hipErrorInvalidValue;
+    const int n = a.n_mem * 8;
+    hipLaunchKernelGGL(k_gather_members, dim3((n + 255) / 256), dim3(256), 0, st, S, a, x, nvox);
     return hipGetLastError();
 }
 
