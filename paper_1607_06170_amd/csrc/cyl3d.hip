@@ -1050,7 +1050,7 @@ struct MmaLdsOf<kModeAdjGrad> {
 constexpr int kWavesM = 4;
 
 template <int MODE>
-__global__ void __launch_bounds__(64 * kWavesM) __attribute__((amdgpu_waves_per_eu(MODE == kModeAdjGrad ? 2 : 4)))
+__global__ void __launch_bounds__(64 * kWavesM) __attribute__((amdgpu_waves_per_eu(MODE == kModeAdjGrad ? 2 : 3)))
 k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
     typedef typename MmaLdsOf<MODE>::type Lds;
     constexpr bool kAdj = MODE == kModeAdj || MODE == kModeAdjGrad;
@@ -1066,29 +1066,76 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
     int flag = 0;
     unsigned long long n_vt = 0;  // (voxel, tile) pairs
     const int m = lane & 31, hk = lane >> 5;
-    for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
-        const float* rec = S.recs + (int64_t)idx * kRecFloats;
-        const int* h = (const int*)rec;
-        const int nsmp = h[3];
-        if (nsmp == 0) continue;  // a reserved slot left unused
-        const int g1 = h[0], g2 = h[1], hv = h[2];
-        const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
-        const int64_t su = h[4], sv = h[5];
-        // the class's members: first (batch index) and count; member s has ring shift s
-        const int4 cl = make_int4(0, h[6] & 0xffff, h[6] >> 16, 0);
-        const float* urow = S.uvtab + su * 400;
-        const float* vrow = S.uvtab + sv * 400;
-        for (int e = lane; e < 256; e += 64) L.o.W[e >> 4][e & 15] = 0.0f;
-        for (int e = lane; e < 400; e += 64) L.o.U[e / 25][e % 25] = urow[e];
-        for (int e = lane; e < 400; e += 64) L.o.V[e / 25][e % 25] = vrow[e];
-        __builtin_amdgcn_wave_barrier();
-        // scatter the weight blocks: sample k couples (pt1, pz1) with (pt2, pz2)
-        for (int e = lane; e < nsmp * 16; e += 64) {
-            const int k = e >> 4, q = e & 15;
-            if (q >= P * P) continue;
-            const int pts = h[kRecPts + k], pt1 = pts & 0xff, pt2 = pts >> 8;
-            L.o.W[pt1 * P + q / P][pt2 * P + q % P] = rec[kRecHead + e];
+    // Software pipeline: while a record is processed, the next one's header
+    // (one word per lane 0..23), weight blocks (4 per lane) and response rows
+    // (7 + 7 per lane) are in flight, and the header after it too.
+    int hA = 0, hB = 0;  // headers of the next two records, word = lane
+    float pw[4], pu[7], pv[7];
+    auto load_head = [&](unsigned int j) -> int {
+        return lane < kRecHead ? ((const int*)(S.recs + (int64_t)j * kRecFloats))[lane] : 0;
+    };
+    auto load_data = [&](unsigned int j, int hd) {
+        const float* r = S.recs + (int64_t)j * kRecFloats;
+        const int ns = __shfl(hd, 3, 64);
+        const float* ur = S.uvtab + (int64_t)__shfl(hd, 4, 64) * 400;
+        const float* vr = S.uvtab + (int64_t)__shfl(hd, 5, 64) * 400;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = lane + 64 * i;
+            pw[i] = e < ns * 16 ? r[kRecHead + e] : 0.0f;
         }
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            const int e = lane + 64 * i;
+            pu[i] = e < 400 && ns > 0 ? ur[e] : 0.0f;
+            pv[i] = e < 400 && ns > 0 ? vr[e] : 0.0f;
+        }
+    };
+    if (wave0 < nrec) {
+        hA = load_head(wave0);
+        load_data(wave0, hA);
+        if (wave0 + nwaves < nrec) hB = load_head(wave0 + nwaves);
+    }
+    for (unsigned int idx = wave0; idx < nrec; idx += nwaves) {
+        const int hcur = hA;
+        const int nsmp = __builtin_amdgcn_readfirstlane(__shfl(hcur, 3, 64));
+        if (nsmp > 0) {
+            // the record's operands into LDS
+            for (int e = lane; e < 256; e += 64) L.o.W[e >> 4][e & 15] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                const int e = lane + 64 * i;
+                if (e < 400) {
+                    L.o.U[e / 25][e % 25] = pu[i];
+                    L.o.V[e / 25][e % 25] = pv[i];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // scatter the weight blocks: sample k couples (pt1, pz1) with (pt2, pz2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = lane + 64 * i, k = e >> 4, q = e & 15;
+                const int pts = __shfl(hcur, kRecPts + (k & 15), 64);
+                if (e < nsmp * 16 && q < P * P) {
+                    const int pt1 = pts & 0xff, pt2 = pts >> 8;
+                    L.o.W[pt1 * P + q / P][pt2 * P + q % P] = pw[i];
+                }
+            }
+        }
+        // next record's data, and the header after it
+        hA = hB;
+        if (idx + nwaves < nrec) load_data(idx + nwaves, hA);
+        if (idx + 2 * nwaves < nrec) hB = load_head(idx + 2 * nwaves);
+        if (nsmp == 0) continue;  // a reserved slot left unused
+        const int g1 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 0, 64));
+        const int g2 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 1, 64));
+        const int hv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 2, 64));
+        const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
+        const int64_t su = __builtin_amdgcn_readfirstlane(__shfl(hcur, 4, 64));
+        const int64_t sv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 5, 64));
+        const int h6 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 6, 64));
+        // the class's members: first (batch index) and count; member s has ring shift s
+        const int4 cl = make_int4(0, h6 & 0xffff, h6 >> 16, 0);
         __builtin_amdgcn_wave_barrier();
         // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
 #pragma unroll
