@@ -85,10 +85,10 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, band, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
         g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
     int64_t table_elems, cap_stage;
-    int bmax, bcsr, cap_slots;
+    int bmax, bcsr, cap_slots, band_rows;
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
@@ -118,6 +118,9 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;
     off += align256(sizeof(float) * (size_t)L.bcsr * L.cap_slots * NR * NR);
+    L.band = off;  // a class's s_max is below the batch's member count
+    L.band_rows = (int)NR + (L.bmax > L.bcsr ? L.bmax : L.bcsr) + 3;
+    off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
     L.chunks = off;
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
     off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
@@ -217,6 +220,8 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.cap_mem = L.bmax > L.bcsr ? L.bmax : L.bcsr;
     S.uvgrad = L.uvgrad ? at3<double>(ws, L.uvgrad) : nullptr;
     S.xm = at3<float>(ws, L.xm);
+    S.band = at3<int2>(ws, L.band);
+    S.band_rows = L.band_rows;
     return S;
 }
 
@@ -332,6 +337,7 @@ void set_batch(Args3D& a, const Batch3& b, const PlanDev& d) {
 int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args3D& a, const Batch3& b,
                    int want_slots, hipStream_t s) {
     HIP_TRY(launch_cyl3d_transaxial(G, S, a, want_slots, s));
+    if (want_slots) HIP_TRY(launch_band_init(S, a, s));
     HIP_TRY(launch_cyl3d_uvtab(G, S, a, b.uv_slots, s));
     ProfScope pg_(h, s, 1);
     HIP_TRY(launch_cyl3d_geom(G, S, a, s));

@@ -85,6 +85,10 @@ struct Scratch3D {
     // (layout of uvtab), folded into the table entries after each batch
     double* uvgrad;    // [cap_uv][16][25], or null
     float* xm;         // [B_mem][8]  the batch members' image values (forward input, or the gradient's image)
+    // matrix build: for each class, slot and ring r_i relative to the reference
+    // member (offset s_max + 2), the range of r_j its tiles touched
+    int2* band;        // [B_cls][cap_slots][band_rows]
+    int band_rows;
 };
 constexpr int kXRep = 64;
 
@@ -195,6 +199,7 @@ hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
+hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
 hipError_t launch_gather_members(const Scratch3D& S, const Args3D& a, const float* x, int64_t nvox, hipStream_t st);

@@ -1232,6 +1232,19 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
+        if (MODE == kModeCount || MODE == kModeFill) {
+            // the class's band: the r_j range each (slot, relative r_i) row receives
+            const int brow0 = cl.z + 1;  // s_max + 2
+            int2* band = S.band + (int64_t)vb * S.cap_slots * S.band_rows;
+            for (int e = lane; e < total; e += 64) {
+                const int mm = L.e.m[e];
+                const int ra = r1 + (mm & 7) - 2, rb = r2 + ((mm >> 3) & 7) - 2;
+                const bool sw = (mm >> 6) & 1;
+                int2* b = band + (int64_t)L.e.key[e] * S.band_rows + (sw ? rb : ra) + brow0;
+                atomicMin(&b->x, sw ? ra : rb);
+                atomicMax(&b->y, sw ? ra : rb);
+            }
+        }
         // emission.  With at most 64 members: lane = (entry, member), the member
         // fixed per lane (lane mod the member count rounded up to a power of
         // two); projection sinograms in the diagonal layout, so a lane group
@@ -1491,46 +1504,105 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 // ---------------------------------------------------------------------------
 // K3: compaction of the dense accumulator into CSR rows (ascending bins)
 // ---------------------------------------------------------------------------
-// A member's accumulator is cut into chunks of kChunk entries, one workgroup
-// each.  Count phase: each chunk adds its number of kept entries to the row
-// count.  Fill phase: a first pass stores the per-chunk counts, the second
-// writes each chunk at its offset (row start + counts of the chunks before
-// it), in order.  The last pass over a chunk clears it for the next batch.
-// Count phase with staging: the fill passes run, the row going to the stage
-// at an offset the allocator gave it (k_stage_alloc, between the passes).
+// A member's accumulator rows (slot, r_i) are cut into chunks of kRowsC rows,
+// one workgroup each; of each row only the columns in the class's band (moved
+// by the member's shift) can be non-zero, and only those are read.  Count
+// phase: each chunk adds its number of kept entries to the row count.  Fill
+// phase: a first pass stores the per-chunk counts, the second writes each
+// chunk at its offset (row start + counts of the chunks before it), in order.
+// The last pass over a chunk clears what it read for the next batch.  Count
+// phase with staging: the fill passes run, the row going to the stage at an
+// offset the allocator gave it (k_stage_alloc, between the passes).
 
 constexpr int kBlockC = 512;
-constexpr int64_t kChunk = 32768;
+constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
 
 enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
+
+__global__ void k_band_init(Scratch3D S, Args3D A) {
+    const int cb = blockIdx.y;
+    const int64_t n = (int64_t)S.n_slots[cb] * S.band_rows;
+    int2* band = S.band + (int64_t)cb * S.cap_slots * S.band_rows;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        band[i] = make_int2(0x7fffffff, -0x7fffffff);
+}
+
+hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st) {
+    if (a.n_cls <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_init, dim3(64, a.n_cls), dim3(256), 0, st, S, a);
+    return hipGetLastError();
+}
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ int wave_tot[kBlockC / 64];
     __shared__ int64_t s_run;
+    __shared__ int rlo[kRowsC], rpre[kRowsC + 1];
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
     const int mi = blockIdx.y;  // member of the batch
     const int4 me = A.mem[mi];
-    const int vb = me.z;        // its class
+    const int vb = me.z, sh = me.y;  // its class and ring shift
     const int64_t chunk = blockIdx.x;
     const int64_t row = me.w;
+    const int NR = G.NR;
     const int nsl = S.n_slots[vb];
-    const int64_t nrr = (int64_t)G.NR * G.NR;
-    const int64_t total = (int64_t)nsl * nrr;
-    const int64_t c0 = chunk * kChunk;
-    if (c0 >= total) return;
-    const int64_t c1 = c0 + kChunk < total ? c0 + kChunk : total;
+    const int64_t nrows = (int64_t)nsl * NR;
+    const int64_t q0 = chunk * kRowsC;
+    if (q0 >= nrows) return;
+    const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
+    const int64_t nrr = (int64_t)NR * NR;
     float* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
     const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
+    const int brow0 = A.cls[vb].w + 2 - sh;  // band row of r_i is r_i - shift + s_max + 2
+    const int2* band = S.band + (int64_t)vb * S.cap_slots * S.band_rows;
+    // the chunk's rows: first column and length (band moved by the shift, cut to the scanner)
+    {
+        const int r = tid;  // kRowsC == kBlockC
+        int lo = 0, len = 0;
+        if (r < nq) {
+            const int64_t q = q0 + r;
+            const int slot = (int)(q / NR), ri = (int)(q - (int64_t)slot * NR);
+            const int2 b = band[(int64_t)slot * S.band_rows + ri + brow0];
+            const int l = max(b.x + sh, 0), h = min(b.y + sh, NR - 1);
+            if (b.x <= b.y && l <= h) {
+                lo = l;
+                len = h - l + 1;
+            }
+        }
+        // block exclusive scan of the lengths
+        int inc = len;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) wave_tot[wid] = inc;
+        __syncthreads();
+        int base = 0, all = 0;
+        for (int w = 0; w < nw; ++w) {
+            base += w < wid ? wave_tot[w] : 0;
+            all += wave_tot[w];
+        }
+        rlo[r] = lo;
+        rpre[r] = base + inc - len;
+        if (tid == 0) rpre[kRowsC] = all;
+        __syncthreads();
+    }
+    const int T = rpre[kRowsC];
     int64_t start = 0, cap = 0;
     if (MODE == kCompactFill) {
+        // kept entries of the chunks before this one
+        int64_t part = 0;
+        for (int64_t c = tid; c < chunk; c += bs) part += ccount[c];
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+        __syncthreads();
+        if (lane == 0) wave_tot[wid] = (int)part;
+        __syncthreads();
         if (tid == 0) {
             int64_t off = 0;
-            for (int64_t c = 0; c < chunk; ++c) off += ccount[c];
+            for (int w = 0; w < nw; ++w) off += wave_tot[w];
             s_run = off;
         }
-        __syncthreads();
         if (A.stage) {  // row_ptr[row + 1] holds the row's count until the scan
             start = A.stage_off[row];
             cap = start >= 0 ? A.row_ptr[row + 1] : 0;
@@ -1543,12 +1615,23 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     }
     __syncthreads();
     const int64_t run0 = s_run;
-    for (int64_t b0 = c0; b0 < c1; b0 += bs) {
-        const int64_t i = b0 + tid;
+    for (int f0 = 0; f0 < T; f0 += bs) {
+        const int f = f0 + tid;
         float a = 0.0f;
-        if (i < c1) {
-            a = dense[i];
-            if (MODE != kCompactChunks) dense[i] = 0.0f;  // leave the accumulator clean
+        int64_t di = 0, q = 0;
+        int col = 0;
+        if (f < T) {
+            int lo = 0, hi = nq - 1;  // the row holding flat entry f: last r with rpre[r] <= f
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rpre[mid] <= f) lo = mid;
+                else hi = mid - 1;
+            }
+            col = rlo[lo] + (f - rpre[lo]);
+            q = q0 + lo;
+            di = q * NR + col;
+            a = dense[di];
+            if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
         }
         const bool keep = a > 0.0f && (double)a >= A.threshold && !(MODE == kCompactFill && A.stage && start < 0);
         const unsigned long long m = __ballot(keep);
@@ -1564,7 +1647,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         if (MODE == kCompactFill && keep) {
             const int64_t pos = run + off + pre;
             if (pos < cap) {
-                const int64_t slot = i / nrr, rr = i - slot * nrr;
+                const int64_t slot = q / NR, rr = (q - slot * NR) * NR + col;
                 const int32_t b = (int32_t)((int64_t)stb[slot] * nrr + rr);
                 if (A.stage) {
                     A.stage_col[start + pos] = b;
@@ -1587,12 +1670,12 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         else if (MODE == kCompactChunks) {
             ccount[chunk] = (int)n;
             if (A.stage) atomicAdd((unsigned long long*)&A.stage_tot[mi], (unsigned long long)n);
-        } else if (c1 == total && s_run != cap && !(A.stage && start < 0)) atomicOr(A.status, kStatOverflow);
+        } else if (q0 + nq == nrows && s_run != cap && !(A.stage && start < 0)) atomicOr(A.status, kStatOverflow);
     }
 }
 
 int64_t cyl3d_max_chunks(int cap_slots, int NR) {
-    return ((int64_t)cap_slots * NR * NR + kChunk - 1) / kChunk;
+    return ((int64_t)cap_slots * NR + kRowsC - 1) / kRowsC;
 }
 
 // Staging allocator of one batch (one wavefront): members in order take
