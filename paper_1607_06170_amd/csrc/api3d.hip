@@ -13,7 +13,7 @@ using namespace psf;
 namespace {
 
 constexpr int kBatchCsr = 128;    // voxels per batch of the matrix build (dense accumulators, FP32)
-constexpr int kBatchProj = 128;   // voxels per batch of the projections
+constexpr int kBatchProj = 512;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
@@ -153,8 +153,8 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
         L.g64 = off;
         off += align256(sizeof(double) * (size_t)L.table_elems);
     }
-    L.plan = off;  // classes, members and row-table offsets of every batch: at most 2 int4 + 1 int per voxel
-    off += align256((2 * sizeof(int4) + sizeof(int)) * (size_t)h->n_vox);
+    L.plan = off;  // classes, members, row-table offsets and images of every batch: at most 2 int4 + 2 int per voxel
+    off += align256((2 * sizeof(int4) + 2 * sizeof(int)) * (size_t)h->n_vox);
     // matrix build staging (count phase -> fill phase)
     L.cap_stage = stage_rows > 0 ? (stage_rows * kStagePerVoxel < kStageMax ? stage_rows * kStagePerVoxel : kStageMax)
                                  : 0;
@@ -243,14 +243,37 @@ struct Batch3 {
 struct Plan3 {
     std::vector<int4> cls, mem;  // cls: reference voxel, first member (batch-relative), count, largest shift
     std::vector<int> uvoff;      // mem: voxel, shift, class (batch-relative), CSR row
-    std::vector<Batch3> batches; // uvoff: first response-row slot of the class (batch-relative)
+    std::vector<int> sym;        // uvoff: first response-row slot of the class (batch-relative)
+    std::vector<Batch3> batches; // sym: voxels per column | image codes << 8 (3 bits per column)
 };
 
 int64_t class_recs(const Ws3& L, int64_t NR, int n) {
     return (L.per_vox * (NR + n - 1) + NR - 1) / NR;
 }
 
-Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax) {
+// The image is symmetric under the scanner's quarter turns and its mirror
+// y -> -y when it is square, centred on the axis and the block layout starts on
+// the x axis: image `code` (bit 2: mirror first; bits 0-1: quarter turns
+// counter-clockwise) of column (ix, iy).
+static bool square_symmetry(const psf_handle* h) {
+    return h->im.nx == h->im.ny && h->im.dx == h->im.dy && h->im.cx == 0.0 && h->im.cy == 0.0 &&
+           h->g.n_blocks % 4 == 0 && h->g.phi0 == 0.0;
+}
+
+static int64_t column_image(int code, int64_t n, int64_t ixy) {
+    int64_t ix = ixy % n, iy = ixy / n;
+    if (code & 4) iy = n - 1 - iy;
+    for (int k = 0; k < (code & 3); ++k) {
+        const int64_t t = ix;
+        ix = n - 1 - iy;
+        iy = t;
+    }
+    return iy * n + ix;
+}
+
+// sym: classes may join the images of a column under the square's symmetry
+// (projections); the matrix build keeps one column per class.
+Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym) {
     Plan3 pl;
     const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -258,46 +281,94 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax)
     const double q = nearbyint(h->g.pitch_z / h->im.dz);
     if (q >= 1.0 && q < 1e6 && fabs(q * h->im.dz - h->g.pitch_z) <= 1e-12 * h->g.pitch_z) m = (int64_t)q;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
+    sym = sym && square_symmetry(h);
     int cmax = bmax;
     while (cmax > 1 && (class_recs(L, NR, cmax) > L.cap_recs || NR + cmax - 1 > L.cap_uv_rings)) --cmax;
     Batch3 cur = {0, 0, 0, 0, 0};
     int64_t cur_recs = 0;
-    auto add_class = [&](int64_t v0, int64_t step, int n) {
-        const int64_t need = class_recs(L, NR, n), uv = Nc * (NR + n - 1);
+    // a class: reference voxel v0, nz voxels step `step` apart in z, in the
+    // columns images[0..ni) (image 0 the reference's own column)
+    auto add_class = [&](int64_t v0, int64_t step, int nzc, const int64_t* cols, const int* codes, int ni) {
+        const int n = nzc * ni;
+        const int64_t need = class_recs(L, NR, nzc), uv = Nc * (NR + nzc - 1);
         if (cur.nmem > 0 &&
             (cur.nmem + n > bmax || cur_recs + need > L.cap_recs || cur.uv_slots + uv > L.cap_uv)) {
             pl.batches.push_back(cur);
             cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0, 0};
             cur_recs = 0;
         }
-        pl.cls.push_back(make_int4((int)v0, cur.nmem, n, n - 1));
+        pl.cls.push_back(make_int4((int)v0, cur.nmem, n, nzc - 1));
         pl.uvoff.push_back((int)cur.uv_slots);
+        int sc = nzc;
+        for (int i = 0; i < ni; ++i) sc |= codes[i] << (8 + 3 * i);
+        pl.sym.push_back(sc);
         cur.uv_slots += uv;
-        for (int k = 0; k < n; ++k) {
-            const int64_t v = v0 + k * step;
-            pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
-        }
+        const int64_t z0 = v0 / nxy;
+        for (int i = 0; i < ni; ++i)
+            for (int k = 0; k < nzc; ++k) {
+                const int64_t v = cols[i] + (z0 * nxy + k * step);
+                pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
+            }
         cur.ncls += 1;
         cur.nmem += n;
         cur_recs += need;
     };
-    for (int64_t ixy = 0; ixy < nxy; ++ixy) {
-        // z range of this column inside [vb, ve)
-        int64_t zlo = vb - ixy <= 0 ? 0 : (vb - ixy + nxy - 1) / nxy;
-        int64_t zhi = ve - 1 - ixy < 0 ? -1 : (ve - 1 - ixy) / nxy;
-        if (zhi > nz - 1) zhi = nz - 1;
-        if (zlo > zhi) continue;
+    auto zrange = [&](int64_t ixy, int64_t* zlo, int64_t* zhi) {
+        *zlo = vb - ixy <= 0 ? 0 : (vb - ixy + nxy - 1) / nxy;
+        *zhi = ve - 1 - ixy < 0 ? -1 : (ve - 1 - ixy) / nxy;
+        if (*zhi > nz - 1) *zhi = nz - 1;
+    };
+    // the columns of one class group, all with the z range [zlo, zhi]
+    auto add_columns = [&](const int64_t* cols, const int* codes, int ni, int64_t zlo, int64_t zhi) {
+        if (zlo > zhi) return;
         if (m == 0) {
-            for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(ixy + iz * nxy, 0, 1);
-            continue;
+            for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(cols[0] + iz * nxy, 0, 1, cols, codes, ni);
+            return;
         }
+        int run = cmax;  // the contraction gives each of a class's members a lane: at most 64 with images
+        if (ni > 1 && run * ni > 64) run = 64 / ni;
         for (int64_t c = 0; c < m && zlo + c <= zhi; ++c) {
             const int64_t n_all = (zhi - (zlo + c)) / m + 1;
-            for (int64_t k0 = 0; k0 < n_all; k0 += cmax) {
-                const int n = (int)(n_all - k0 < cmax ? n_all - k0 : cmax);
-                add_class(ixy + (zlo + c + k0 * m) * nxy, m * nxy, n);
+            for (int64_t k0 = 0; k0 < n_all; k0 += run) {
+                const int n = (int)(n_all - k0 < run ? n_all - k0 : run);
+                add_class(cols[0] + (zlo + c + k0 * m) * nxy, m * nxy, n, cols, codes, ni);
             }
         }
+    };
+    for (int64_t ixy = 0; ixy < nxy; ++ixy) {
+        int64_t zlo, zhi;
+        zrange(ixy, &zlo, &zhi);
+        if (!sym) {
+            const int code0 = 0;
+            add_columns(&ixy, &code0, 1, zlo, zhi);
+            continue;
+        }
+        // only the orbit's first column (smallest index) builds its classes
+        int64_t img[8];
+        bool first = true;
+        for (int c = 0; c < 8; ++c) {
+            img[c] = column_image(c, nx, ixy);
+            if (img[c] < ixy) first = false;
+        }
+        if (!first) continue;
+        // images with the reference's z range join its classes; others stand alone
+        int64_t cols[8];
+        int codes[8], ni = 0;
+        for (int c = 0; c < 8; ++c) {
+            bool seen = false;
+            for (int i = 0; i < c; ++i) seen = seen || img[i] == img[c];
+            if (seen) continue;
+            int64_t zl, zh;
+            zrange(img[c], &zl, &zh);
+            if (zl == zlo && zh == zhi) {
+                cols[ni] = img[c];
+                codes[ni++] = c;
+            } else {
+                const int code0 = 0;
+                add_columns(&img[c], &code0, 1, zl, zh);
+            }
+        }
+        add_columns(cols, codes, ni, zlo, zhi);
     }
     if (cur.nmem > 0) pl.batches.push_back(cur);
     return pl;
@@ -305,7 +376,7 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax)
 
 struct PlanDev {
     const int4 *cls, *mem;
-    const int* uvoff;
+    const int *uvoff, *sym;
 };
 
 // copies the plan into the workspace; returns the device arrays
@@ -313,15 +384,18 @@ int upload_plan(const Plan3& pl, void* ws, const Ws3& L, hipStream_t s, PlanDev*
     int4* c = at3<int4>(ws, L.plan);
     int4* mm = c + pl.cls.size();
     int* uo = (int*)(mm + pl.mem.size());
+    int* sy = uo + pl.uvoff.size();
     if (!pl.cls.empty()) {
         HIP_TRY(hipMemcpyAsync(c, pl.cls.data(), sizeof(int4) * pl.cls.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(mm, pl.mem.data(), sizeof(int4) * pl.mem.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(uo, pl.uvoff.data(), sizeof(int) * pl.uvoff.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(sy, pl.sym.data(), sizeof(int) * pl.sym.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope after the call
     }
     d->cls = c;
     d->mem = mm;
     d->uvoff = uo;
+    d->sym = sy;
     return PSF_OK;
 }
 
@@ -329,6 +403,7 @@ void set_batch(Args3D& a, const Batch3& b, const PlanDev& d) {
     a.cls = d.cls + b.cls0;
     a.mem = d.mem + b.mem0;
     a.uvoff = d.uvoff + b.cls0;
+    a.sym = d.sym + b.cls0;
     a.n_cls = b.ncls;
     a.n_mem = b.nmem;
 }
@@ -348,7 +423,7 @@ int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args
 // into a diagonal-layout copy (FP32 atomics), permuted into y at the end
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              int accumulate, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -382,7 +457,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -444,7 +519,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int phase_fill = csr->col != nullptr;
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr);
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, false);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;

@@ -95,7 +95,8 @@ constexpr int kXRep = 64;
 // tile record (ints and floats in one array):
 //   [0] g1  [1] g2  [2] (r1 + 512) | (r2 + 512) << 10 | class << 20  [3] n samples
 //   [4] row-table slot of U (g1, r1)  [5] of V (g2, r2)
-//   [6] the class's first member | member count << 16  [7] 0
+//   [6] the class's first member | member count << 16
+//   [7] the class's voxels per column | image codes << 8 (3 bits per column)
 //   [8 + k]        pt1 | pt2 << 8 of sample k (the transaxial sub-segments of the bundle)
 //   [24 + 16k + q] W of sample k between axial sub-positions pz1 = q / P and pz2 = q % P
 // rings are relative to the class's reference member
@@ -112,6 +113,7 @@ struct Args3D {
     const int4* cls;    // [n_cls]: reference voxel, first member, member count, largest shift
     const int4* mem;    // [n_mem]: voxel, ring shift, class, CSR row
     const int* uvoff;   // [n_cls]: first response-row slot of the class
+    const int* sym;     // [n_cls]: voxels per column | image codes << 8 (3 bits per column of the class)
     int n_cls;          // classes in this batch
     int n_mem;          // members (voxels) in this batch
     int batch;

@@ -67,6 +67,18 @@ __device__ __forceinline__ int64_t tbin_of(int64_t gi, int64_t gj, int64_t Nc) {
     return gi * Nc - gi * (gi + 1) / 2 + (gj - gi - 1);
 }
 
+// crystal g of a column seen from its image `code` under the square's symmetry
+// (bit 2: the mirror y -> -y, c -> nc - 1 - c; bits 0-1: quarter turns, a
+// quarter of the ring's crystals each)
+__device__ __forceinline__ int image_crystal(int code, int g, int Nc, int nc) {
+    if (code & 4) {
+        g = nc - 1 - g;
+        if (g < 0) g += Nc;
+    }
+    g += (code & 3) * (Nc >> 2);
+    return g >= Nc ? g - Nc : g;
+}
+
 __device__ __forceinline__ void voxel_xyz(const Cyl3D& G, int64_t v, double& x, double& y, double& z) {
     const int64_t ix = v % G.nx, iy = (v / G.nx) % G.ny, iz = v / ((int64_t)G.nx * G.ny);
     x = (ix - 0.5 * (G.nx - 1)) * G.dx + G.cx;
@@ -979,7 +991,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                     h[4] = A.uvoff[vb] + g1 * nr1 + r1 + smax;
                     h[5] = A.uvoff[vb] + g2 * nr1 + r2 + smax;
                     h[6] = cl.y | (cl.z << 16);
-                    h[7] = 0;
+                    h[7] = A.sym[vb];
                 }
                 if (lane < nsmp) h[kRecPts + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
                 for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wr[j][e >> 4][e & 15];
@@ -1134,8 +1146,13 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         const int64_t su = __builtin_amdgcn_readfirstlane(__shfl(hcur, 4, 64));
         const int64_t sv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 5, 64));
         const int h6 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 6, 64));
-        // the class's members: first (batch index) and count; member s has ring shift s
+        const int h7 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 7, 64));
+        // the class's members: first (batch index) and count, column-major: member
+        // i * nzc + s is voxel s (ring shift s) of column i, the image of the
+        // reference column under `codes` (3 bits per column; column 0 is the reference)
         const int4 cl = make_int4(0, h6 & 0xffff, h6 >> 16, 0);
+        const int nzc = h7 & 0xff, codes = h7 >> 8;
+        const bool imgs = codes != 0;
         __builtin_amdgcn_wave_barrier();
         // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
 #pragma unroll
@@ -1198,8 +1215,14 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
             if (bq >= 25 || a >= 25 || ct[j] == 0.0f || ga == gb) continue;
             const bool sw = ga > gb;
-            const int tb_ = (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
-            if (MODE == kModeCount || MODE == kModeFill) {
+            const int tb_ = imgs ? (ga | (gb << 16)) : (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
+            if ((MODE == kModeCount || MODE == kModeFill) && imgs) {
+                flag |= kStatGeom;  // the matrix build keeps one column per class
+                continue;
+            }
+            if (imgs) {
+                key[j] = tb_;
+            } else if (MODE == kModeCount || MODE == kModeFill) {
                 key[j] = smap[tb_];
                 if (key[j] < 0) {
                     flag |= kStatScratch;
@@ -1261,9 +1284,16 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 acc[bb] = 0.0;
             }
             bool mok = false;
+            int code = 0;
             if (sm < cl.z) {
-                R1 = r1 + sm;
-                R2 = r2 + sm;
+                int ci = 0, s = sm;  // column and ring shift of the lane's member
+                while (s >= nzc) {
+                    s -= nzc;
+                    ++ci;
+                }
+                code = (codes >> (3 * ci)) & 7;
+                R1 = r1 + s;
+                R2 = r2 + s;
                 mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
                 if ((MODE == kModeFwd || kGrad) && mok) {
                     const float* xs = S.xm + (int64_t)(cl.y + sm) * 8;
@@ -1281,14 +1311,20 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
                 if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
                 const float t = L.e.t[e];
-                const bool sw = (mm >> 6) & 1;
+                bool sw = (mm >> 6) & 1;
                 if (MODE == kModeCount || MODE == kModeFill) {
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
                     atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
                     return;
                 }
-                const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR +
-                                    (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
+                int64_t tb = L.e.key[e];
+                if (imgs) {  // the entry's crystals seen from the member's column
+                    const int ga = image_crystal(code, tb & 0xffff, G.Nc, G.nc);
+                    const int gb = image_crystal(code, (int)(tb >> 16), G.Nc, G.nc);
+                    sw = ga > gb;
+                    tb = tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
+                }
+                const int64_t idx = tb * G.NR * G.NR + (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
                 if (MODE == kModeFwd) {
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
@@ -1326,6 +1362,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         atomicAdd(&S.xrep[((int64_t)(wave0 % kXRep) * S.cap_mem + cl.y + sm) * 8 + bb], sacc);
                 }
             }
+        } else if (imgs) {
+            flag |= kStatGeom;  // classes with images have at most 64 members
         } else {
         if constexpr (kGrad)
             for (int e = lane; e < total; e += 64) L.Gl[e] = 0.0f;
