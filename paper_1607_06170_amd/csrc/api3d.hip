@@ -118,8 +118,8 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;
     off += align256(sizeof(float) * (size_t)L.bcsr * L.cap_slots * NR * NR);
-    L.band = off;  // a class's s_max is below the batch's member count
-    L.band_rows = (int)NR + (L.bmax > L.bcsr ? L.bmax : L.bcsr) + 3;
+    L.band = off;  // a class's s_max is below the build batch's member count
+    L.band_rows = (int)NR + L.bcsr + 3;
     off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
     L.chunks = off;
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
@@ -271,8 +271,9 @@ static int64_t column_image(int code, int64_t n, int64_t ixy) {
     return iy * n + ix;
 }
 
-// sym: classes may join the images of a column under the square's symmetry
-// (projections); the matrix build keeps one column per class.
+// sym: classes may join the images of a column under the square's symmetry.  The
+// matrix build keeps one column per class: its rows are written per member, and
+// joining images there costs more in slot lookups than it saves in tiles.
 Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym) {
     Plan3 pl;
     const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;

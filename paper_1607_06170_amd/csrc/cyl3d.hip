@@ -423,6 +423,14 @@ __device__ int uv_row3(const Cyl3D& G, double cx, double cy, double cz, int g, i
 
 constexpr int kBlockT = 512;
 
+// a class that gives up: none of its columns has slots
+__device__ void clear_slot_counts(const Scratch3D& S, const Args3D& A, int cb) {
+    if (!S.n_slots) return;
+    const int4 c = A.cls[cb];
+    const int nzc = A.sym[cb] & 0xff;
+    for (int i = 0; i < c.z; i += nzc) S.n_slots[c.y + i] = 0;
+}
+
 __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D S, Args3D A, int want_slots) {
     extern __shared__ __align__(16) unsigned char smem3[];
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -507,7 +515,7 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     const int ns = s_total;
     if (ns > S.cap_samples) {
         if (tid == 0) atomicOr(A.status, kStatScratch);
-        if (tid == 0) { S.n_samples[vb] = 0; S.n_pairs[vb] = 0; if (S.n_slots) S.n_slots[vb] = 0; }
+        if (tid == 0) { S.n_samples[vb] = 0; S.n_pairs[vb] = 0; clear_slot_counts(S, A, vb); }
         return;
     }
     // group each g1's bundles by g2 (insertion sort of <= P * few entries)
@@ -559,7 +567,7 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     __syncthreads();
     const int np = s_np;
     if (np > S.cap_pairs) {
-        if (tid == 0) { atomicOr(A.status, kStatScratch); S.n_samples[vb] = 0; S.n_pairs[vb] = 0; if (S.n_slots) S.n_slots[vb] = 0; }
+        if (tid == 0) { atomicOr(A.status, kStatScratch); S.n_samples[vb] = 0; S.n_pairs[vb] = 0; clear_slot_counts(S, A, vb); }
         return;
     }
     for (int g1 = tid; g1 < G.Nc; g1 += bs) {
@@ -579,60 +587,69 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
         S.n_pairs[vb] = np;
     }
     if (!want_slots) return;
-    __syncthreads();
-    // transaxial bins of this class: mark, then scan in bin order into slots
-    int* smap = S.slotmap + (int64_t)vb * G.ntbins;
-    for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
-    __syncthreads();
-    for (int p = tid; p < np; p += bs) {
-        const int4 pr = pairs[p];
-        for (int at = -2; at <= 2; ++at)
-            for (int bt = -2; bt <= 2; ++bt) {
-                int gi = pr.x + at, gj = pr.y + bt;
-                gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
-                gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
-                if (gi == gj) continue;
-                const int lo_ = gi < gj ? gi : gj, hi_ = gi < gj ? gj : gi;
-                smap[tbin_of(lo_, hi_, G.Nc)] = 1;
-            }
-    }
-    __syncthreads();
-    // block scan over the marks (chunks of bs), writing slot indices
-    int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
+    // transaxial bins of each column of the class (its crystals mapped by the
+    // column's image code): mark, then scan in bin order into slots.  Column i's
+    // maps live at group cl.y + i * nzc (the member index of its first voxel).
+    const int4 clv = A.cls[vb];
+    const int sy = A.sym[vb], nzc = sy & 0xff, codes = sy >> 8, ni = clv.z / nzc;
     __shared__ int s_run;
-    if (tid == 0) s_run = 0;
-    __syncthreads();
     const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
-    for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
-        const int64_t i = b0 + tid;
-        const int mk = i < G.ntbins ? smap[i] : 0;
-        const unsigned long long m = __ballot(mk != 0);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) red[wid] = __popcll(m);
+    for (int ci = 0; ci < ni; ++ci) {
+        const int code = (codes >> (3 * ci)) & 7, grp = clv.y + ci * nzc;
         __syncthreads();
-        int off = 0, tot = 0;
-        for (int w = 0; w < nw; ++w) {
-            off += w < wid ? red[w] : 0;
-            tot += red[w];
+        int* smap = S.slotmap + (int64_t)grp * G.ntbins;
+        for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
+        __syncthreads();
+        for (int p = tid; p < np; p += bs) {
+            const int4 pr = pairs[p];
+            for (int at = -2; at <= 2; ++at)
+                for (int bt = -2; bt <= 2; ++bt) {
+                    int gi = pr.x + at, gj = pr.y + bt;
+                    gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
+                    gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
+                    if (gi == gj) continue;
+                    gi = image_crystal(code, gi, G.Nc, G.nc);
+                    gj = image_crystal(code, gj, G.Nc, G.nc);
+                    const int lo_ = gi < gj ? gi : gj, hi_ = gi < gj ? gj : gi;
+                    smap[tbin_of(lo_, hi_, G.Nc)] = 1;
+                }
         }
-        const int run = s_run;
-        if (i < G.ntbins) {
-            if (mk) {
-                const int slot = run + off + pre;
-                smap[i] = slot < S.cap_slots ? slot : -1;
-                if (slot < S.cap_slots) stb[slot] = (int)i;
-            } else {
-                smap[i] = -1;
+        __syncthreads();
+        // block scan over the marks (chunks of bs), writing slot indices
+        int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+        if (tid == 0) s_run = 0;
+        __syncthreads();
+        for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
+            const int64_t i = b0 + tid;
+            const int mk = i < G.ntbins ? smap[i] : 0;
+            const unsigned long long m = __ballot(mk != 0);
+            const int pre = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) red[wid] = __popcll(m);
+            __syncthreads();
+            int off = 0, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                off += w < wid ? red[w] : 0;
+                tot += red[w];
             }
+            const int run = s_run;
+            if (i < G.ntbins) {
+                if (mk) {
+                    const int slot = run + off + pre;
+                    smap[i] = slot < S.cap_slots ? slot : -1;
+                    if (slot < S.cap_slots) stb[slot] = (int)i;
+                } else {
+                    smap[i] = -1;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) s_run = run + tot;
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid == 0) s_run = run + tot;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const int nsl = s_run;
-        if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
-        S.n_slots[vb] = nsl < S.cap_slots ? nsl : S.cap_slots;
+        if (tid == 0) {
+            const int nsl = s_run;
+            if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
+            S.n_slots[grp] = nsl < S.cap_slots ? nsl : S.cap_slots;
+        }
     }
 }
 
@@ -1204,7 +1221,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         const int bt = bq / 5 - 2, bz = bq % 5 - 2;
         int gb = g2 + bt;
         gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-        const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)vb * G.ntbins : nullptr;
+        // the reference column's slot map (group cl.y); columns with images map their crystals first
+        const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)cl.y * G.ntbins : nullptr;
         int key[16];
         unsigned int live = 0u, swap = 0u;
 #pragma unroll
@@ -1216,10 +1234,6 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             if (bq >= 25 || a >= 25 || ct[j] == 0.0f || ga == gb) continue;
             const bool sw = ga > gb;
             const int tb_ = imgs ? (ga | (gb << 16)) : (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
-            if ((MODE == kModeCount || MODE == kModeFill) && imgs) {
-                flag |= kStatGeom;  // the matrix build keeps one column per class
-                continue;
-            }
             if (imgs) {
                 key[j] = tb_;
             } else if (MODE == kModeCount || MODE == kModeFill) {
@@ -1256,14 +1270,32 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         }
         __builtin_amdgcn_wave_barrier();
         if (MODE == kModeCount || MODE == kModeFill) {
-            // the class's band: the r_j range each (slot, relative r_i) row receives
-            const int brow0 = cl.z + 1;  // s_max + 2
-            int2* band = S.band + (int64_t)vb * S.cap_slots * S.band_rows;
-            for (int e = lane; e < total; e += 64) {
+            // each column's band: the r_j range each (slot, relative r_i) row receives
+            const int brow0 = nzc + 1;  // s_max + 2
+            const int ni = cl.z / nzc;
+            for (int it = lane; it < total * ni; it += 64) {
+                int e = it, ci = 0;
+                while (e >= total) {
+                    e -= total;
+                    ++ci;
+                }
                 const int mm = L.e.m[e];
                 const int ra = r1 + (mm & 7) - 2, rb = r2 + ((mm >> 3) & 7) - 2;
-                const bool sw = (mm >> 6) & 1;
-                int2* b = band + (int64_t)L.e.key[e] * S.band_rows + (sw ? rb : ra) + brow0;
+                bool sw = (mm >> 6) & 1;
+                int slot = L.e.key[e];
+                const int grp = cl.y + ci * nzc;
+                if (imgs) {
+                    const int code = (codes >> (3 * ci)) & 7;
+                    const int ga = image_crystal(code, slot & 0xffff, G.Nc, G.nc);
+                    const int gb = image_crystal(code, slot >> 16, G.Nc, G.nc);
+                    sw = ga > gb;
+                    slot = S.slotmap[(int64_t)grp * G.ntbins + tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc)];
+                    if (slot < 0) {
+                        flag |= kStatScratch;
+                        continue;
+                    }
+                }
+                int2* b = S.band + ((int64_t)grp * S.cap_slots + slot) * S.band_rows + (sw ? rb : ra) + brow0;
                 atomicMin(&b->x, sw ? ra : rb);
                 atomicMax(&b->y, sw ? ra : rb);
             }
@@ -1284,9 +1316,9 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 acc[bb] = 0.0;
             }
             bool mok = false;
-            int code = 0;
+            int code = 0, ci = 0;
             if (sm < cl.z) {
-                int ci = 0, s = sm;  // column and ring shift of the lane's member
+                int s = sm;  // column and ring shift of the lane's member
                 while (s >= nzc) {
                     s -= nzc;
                     ++ci;
@@ -1313,8 +1345,16 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 const float t = L.e.t[e];
                 bool sw = (mm >> 6) & 1;
                 if (MODE == kModeCount || MODE == kModeFill) {
+                    int slot = L.e.key[e];
+                    if (imgs) {  // the entry's crystals seen from the member's column, in its slot map
+                        const int ga = image_crystal(code, slot & 0xffff, G.Nc, G.nc);
+                        const int gb = image_crystal(code, slot >> 16, G.Nc, G.nc);
+                        sw = ga > gb;
+                        slot = S.slotmap[(int64_t)(cl.y + ci * nzc) * G.ntbins + tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc)];
+                        if (slot < 0) return;
+                    }
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                    atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
+                    atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], t);
                     return;
                 }
                 int64_t tb = L.e.key[e];
@@ -1363,7 +1403,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
             }
         } else if (imgs) {
-            flag |= kStatGeom;  // classes with images have at most 64 members
+            flag |= kStatGeom;  // classes with images have at most 64 members (the plan keeps them so)
         } else {
         if constexpr (kGrad)
             for (int e = lane; e < total; e += 64) L.Gl[e] = 0.0f;
@@ -1558,16 +1598,17 @@ constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
 enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
 
 __global__ void k_band_init(Scratch3D S, Args3D A) {
-    const int cb = blockIdx.y;
-    const int64_t n = (int64_t)S.n_slots[cb] * S.band_rows;
-    int2* band = S.band + (int64_t)cb * S.cap_slots * S.band_rows;
+    const int grp = blockIdx.y;  // a member; the first voxel of each column holds the column's band
+    if (A.mem[grp].y != 0) return;
+    const int64_t n = (int64_t)S.n_slots[grp] * S.band_rows;
+    int2* band = S.band + (int64_t)grp * S.cap_slots * S.band_rows;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         band[i] = make_int2(0x7fffffff, -0x7fffffff);
 }
 
 hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st) {
-    if (a.n_cls <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_band_init, dim3(64, a.n_cls), dim3(256), 0, st, S, a);
+    if (a.n_mem <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_init, dim3(64, a.n_mem), dim3(256), 0, st, S, a);
     return hipGetLastError();
 }
 
@@ -1580,20 +1621,21 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int mi = blockIdx.y;  // member of the batch
     const int4 me = A.mem[mi];
     const int vb = me.z, sh = me.y;  // its class and ring shift
+    const int grp = mi - sh;         // its column's group (the member index of the column's first voxel)
     const int64_t chunk = blockIdx.x;
     const int64_t row = me.w;
     const int NR = G.NR;
-    const int nsl = S.n_slots[vb];
+    const int nsl = S.n_slots[grp];
     const int64_t nrows = (int64_t)nsl * NR;
     const int64_t q0 = chunk * kRowsC;
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
     float* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
-    const int* stb = S.slot_tbin + (int64_t)vb * S.cap_slots;
+    const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     const int brow0 = A.cls[vb].w + 2 - sh;  // band row of r_i is r_i - shift + s_max + 2
-    const int2* band = S.band + (int64_t)vb * S.cap_slots * S.band_rows;
+    const int2* band = S.band + (int64_t)grp * S.cap_slots * S.band_rows;
     // the chunk's rows: first column and length (band moved by the shift, cut to the scanner)
     {
         const int r = tid;  // kRowsC == kBlockC
