@@ -141,10 +141,11 @@ def main():
     def step(record):
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
         e0.record()
-        rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=prec)
+        # tile counters of each call (each build phase): copied on the device, in stream order, read after
+        # the step; a fill phase that copies the rows its count phase staged contracts nothing
+        h_build = [] if meta["mode3d"] and record else None
+        rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=prec, counters=h_build)
         e1.record()
-        # tile counters of each call: copied on the device, in stream order, read after the step
-        h_build = sc.header_counters() if meta["mode3d"] and record else None
         y = sc.project_fwd(tab, x, precision=prec)
         e2.record()
         h_fwd = sc.header_counters() if meta["mode3d"] and record else None
@@ -153,16 +154,16 @@ def main():
         if record:
             torch.cuda.synchronize()
             h_adj = sc.header_counters() if meta["mode3d"] else None
-            t_build, v_build = sc.read_counters(h_build)
+            t_build, v_build = (sum(c) for c in zip(*[sc.read_counters(h) for h in h_build])) if h_build \
+                else (0, 0)
             t_fwd, v_fwd = sc.read_counters(h_fwd)
             t_adj, v_adj = sc.read_counters(h_adj)
             rec["build"].append(e0.elapsed_time(e1))
             rec["fwd"].append(e1.elapsed_time(e2))
             rec["adj"].append(e2.elapsed_time(e3))
             rec["nnz"] += int(col.numel())
-            # the count and fill phases contract the same tiles (the counters hold the fill phase's)
-            rec["tiles"] += 2 * t_build + t_fwd + t_adj
-            rec["vtiles"] += 2 * v_build + v_fwd + v_adj
+            rec["tiles"] += t_build + t_fwd + t_adj
+            rec["vtiles"] += v_build + v_fwd + v_adj
         return xb
 
     def log(msg):

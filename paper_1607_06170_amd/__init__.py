@@ -127,9 +127,10 @@ class Scanner:
         return Table(t, n_rows, n_sub, step_deg)
 
     def build_psf_sysmat(self, table: Table, threshold: float = 0.0, vox_begin: int = 0, vox_end: int = -1,
-                         precision: int = PSF_FP32, stage: bool = True):
+                         precision: int = PSF_FP32, stage: bool = True, counters: list | None = None):
         """CSR of A^T for voxels [vox_begin, vox_end): (row_ptr int64, col int32, val float32).
-        stage: the count phase keeps its rows in the workspace for the fill phase (3D)."""
+        stage: the count phase keeps its rows in the workspace for the fill phase (3D).
+        counters: if a list, each phase appends its header_counters() snapshot (3D)."""
         torch = _torch()
         o = self.opts(precision, threshold, vox_begin, vox_end, flags=_lib.PSF_OPT_STAGE_CSR if stage else 0)
         ve = self.n_voxels if vox_end is None or vox_end < 0 else vox_end
@@ -140,12 +141,16 @@ class Scanner:
         csr = _lib.psf_csr(n, 0, row_ptr.data_ptr(), None, None)
         check(self.L.build_psf_sysmat(self.h, C.byref(tc), C.byref(o), _ptr(ws), ws.numel(), C.byref(csr),
                                       _stream()), "build_psf_sysmat (count)")
+        if counters is not None:
+            counters.append(self.header_counters())
         nnz = csr.nnz
         col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
         val = torch.empty(max(nnz, 1), dtype=torch.float32, device=self.device)
         csr.col, csr.val = col.data_ptr(), val.data_ptr()
         check(self.L.build_psf_sysmat(self.h, C.byref(tc), C.byref(o), _ptr(ws), ws.numel(), C.byref(csr),
                                       _stream()), "build_psf_sysmat (fill)")
+        if counters is not None:
+            counters.append(self.header_counters())
         return row_ptr, col[:nnz], val[:nnz]
 
     def project_fwd(self, table: Table, x, events=None, precision: int = PSF_FP32, y=None, accumulate: int = 0):
