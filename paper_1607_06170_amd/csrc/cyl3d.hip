@@ -1067,6 +1067,18 @@ struct MmaLdsGrad {
     float Gl[640];     // the same, by list entry
 };
 
+// the matrix build also gathers each tile's band contribution: for every
+// transaxial neighbour pair (a_t, b_t) and row of the tile, the r_j range of its
+// live entries, and the pair's slot (with the photon order in bit 30)
+struct MmaLdsBuild {
+    union {
+        MmaOps o;
+        MmaList e;
+    };
+    int2 bnd[125];
+    int bslot[25];
+};
+
 template <int MODE>
 struct MmaLdsOf {
     typedef MmaLds type;
@@ -1074,6 +1086,10 @@ struct MmaLdsOf {
 template <>
 struct MmaLdsOf<kModeAdjGrad> {
     typedef MmaLdsGrad type;
+};
+template <>
+struct MmaLdsOf<kModeCount> {
+    typedef MmaLdsBuild type;
 };
 
 constexpr int kWavesM = 4;
@@ -1265,15 +1281,43 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             L.e.t[pos] = ct[j];
             L.e.key[pos] = key[j];
             L.e.m[pos] = (unsigned char)(a % 5 | ((bz + 2) << 3) | (((swap >> j) & 1u) << 6));
-            if constexpr (kGrad) L.e.ab[pos] = (unsigned short)(a | (bq << 8));
+            if constexpr (kGrad || MODE == kModeCount) L.e.ab[pos] = (unsigned short)(a | (bq << 8));
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
-        if (MODE == kModeCount || MODE == kModeFill) {
+        if constexpr (MODE == kModeCount) {
             // each column's band: the r_j range each (slot, relative r_i) row receives
             const int brow0 = nzc + 1;  // s_max + 2
             const int ni = cl.z / nzc;
-            for (int it = lane; it < total * ni; it += 64) {
+            if (!imgs) {
+                // one column: the tile's rows first meet in LDS, cell (a_t, b_t, row), where
+                // the row is a_z (b_z when photon 2 is first: the pair's slot is ordered so)
+                for (int c = lane; c < 125; c += 64) L.bnd[c] = make_int2(0x7fffffff, -0x7fffffff);
+                __builtin_amdgcn_wave_barrier();
+                for (int e = lane; e < total; e += 64) {
+                    const int mm = L.e.m[e], ab = L.e.ab[e];
+                    const int az = mm & 7, bze = (mm >> 3) & 7;
+                    const bool sw = (mm >> 6) & 1;
+                    const int p = ((ab & 0xff) / 5) * 5 + (ab >> 8) / 5;
+                    const int c = p * 5 + (sw ? bze : az);
+                    const int bj = sw ? r1 + az - 2 : r2 + bze - 2;
+                    atomicMin(&L.bnd[c].x, bj);
+                    atomicMax(&L.bnd[c].y, bj);
+                    L.bslot[p] = L.e.key[e] | (sw ? 0x40000000 : 0);
+                }
+                __builtin_amdgcn_wave_barrier();
+                int2* bg = S.band + (int64_t)cl.y * S.cap_slots * S.band_rows;
+                for (int c = lane; c < 125; c += 64) {
+                    const int2 v = L.bnd[c];
+                    if (v.x > v.y) continue;
+                    const int p = c / 5, ks = L.bslot[p];
+                    const int ai = ((ks & 0x40000000) ? r2 : r1) + (c - 5 * p) - 2;
+                    int2* b = bg + (int64_t)(ks & 0x3fffffff) * S.band_rows + ai + brow0;
+                    atomicMin(&b->x, v.x);
+                    atomicMax(&b->y, v.y);
+                }
+            }
+            for (int it = lane; imgs && it < total * ni; it += 64) {
                 int e = it, ci = 0;
                 while (e >= total) {
                     e -= total;
