@@ -13,6 +13,7 @@ using namespace psf;
 namespace {
 
 constexpr int kBatchCsr = 128;    // voxels per batch of the matrix build (dense accumulators, FP32)
+constexpr int kShareCsr = 16;     // voxels per class in the matrix build (its accumulators interleave them)
 constexpr int kBatchProj = 512;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
@@ -89,6 +90,7 @@ struct Ws3 {
         g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
     int64_t table_elems, cap_stage;
     int bmax, bcsr, cap_slots, band_rows;
+    int64_t dense_slab;  // floats of one member's share of the build accumulators
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
@@ -116,8 +118,9 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * ntbins);
     L.slot_tbin = off;
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
-    L.dense = off;
-    off += align256(sizeof(float) * (size_t)L.bcsr * L.cap_slots * NR * NR);
+    L.dense = off;  // a class of n members takes n slabs: [slot][NR + n - 1][NR + n - 1][n]
+    L.dense_slab = (int64_t)L.cap_slots * (NR + kShareCsr - 1) * (NR + kShareCsr - 1);
+    off += align256(sizeof(float) * (size_t)L.bcsr * L.dense_slab);
     L.band = off;  // a class's s_max is below the build batch's member count
     L.band_rows = (int)NR + L.bcsr + 3;
     off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
@@ -208,6 +211,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.slotmap = at3<int>(ws, L.slotmap);
     S.slot_tbin = at3<int>(ws, L.slot_tbin);
     S.dense = at3<float>(ws, L.dense);
+    S.dense_slab = L.dense_slab;
     S.chunk_counts = at3<int>(ws, L.chunks);
     S.max_chunks = L.max_chunks;
     S.recs = at3<float>(ws, L.recs);
@@ -274,7 +278,8 @@ static int64_t column_image(int code, int64_t n, int64_t ixy) {
 // sym: classes may join the images of a column under the square's symmetry.  The
 // matrix build keeps one column per class: its rows are written per member, and
 // joining images there costs more in slot lookups than it saves in tiles.
-Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym) {
+// share: most voxels of one column in a class.
+Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share) {
     Plan3 pl;
     const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -283,7 +288,7 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
     if (q >= 1.0 && q < 1e6 && fabs(q * h->im.dz - h->g.pitch_z) <= 1e-12 * h->g.pitch_z) m = (int64_t)q;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     sym = sym && square_symmetry(h);
-    int cmax = bmax;
+    int cmax = bmax < share ? bmax : share;
     while (cmax > 1 && (class_recs(L, NR, cmax) > L.cap_recs || NR + cmax - 1 > L.cap_uv_rings)) --cmax;
     Batch3 cur = {0, 0, 0, 0, 0};
     int64_t cur_recs = 0;
@@ -424,7 +429,7 @@ int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args
 // into a diagonal-layout copy (FP32 atomics), permuted into y at the end
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              int accumulate, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -458,7 +463,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -520,7 +525,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int phase_fill = csr->col != nullptr;
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, false);
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, false, kShareCsr);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;
@@ -545,7 +550,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     }
     // the dense accumulators start clean; the compaction leaves them clean
     if (!(phase_fill && staged == (int)pl.batches.size()))
-        HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.cap_slots * G.NR * G.NR, s));
+        HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.dense_slab, s));
     // the count phase writes each row's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     PlanDev pd;

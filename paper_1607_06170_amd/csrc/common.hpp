@@ -65,8 +65,12 @@ struct Scratch3D {
     int4* pairs;       // [B_cls][cap_pairs]  g1, g2, first sample, sample count
     int* slotmap;      // [B_cls][ntbins]  transaxial bin -> slot (-1: none)
     int* slot_tbin;    // [B_cls][cap_slots]
-    // per member of the batch (index mi)
-    float* dense;      // [B_mem][cap_slots][NR * NR]  FP32 sums of the FP32 tile entries
+    // matrix build: FP32 sums of the FP32 tile entries.  A column of n members
+    // (s_max = n - 1) from batch member mi0 on holds [slot][i][j][s] from slab
+    // mi0: member s's ring pair (r_i, r_j) at i = r_i - s + s_max, j = r_j - s +
+    // s_max (both < NR + s_max), so an entry's members lie side by side
+    float* dense;      // [B_mem][dense_slab]
+    int64_t dense_slab;
     int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
     float* recs;       // [cap_recs][kRecFloats]  tile records (header, sample blocks of W)

@@ -21,8 +21,8 @@
 //   K2b contract   the tile T = U^T (W V) (Eq.10, 12) on matrix cores, U and V
 //                  from the table, then
 //                  emission for every member: forward atomics, adjoint
-//                  gathers, or FP32 atomics into the member's dense slot x
-//                  ring-pair accumulator.
+//                  gathers, or FP32 atomics into the build's slot x ring-pair
+//                  accumulators (a class's members interleaved).
 //   K3 compact     ordered compaction of each member's accumulator into CSR rows.
 //
 // Bins: bin = tbin(g_i, g_j) * NR^2 + r_i * NR + r_j with g_i < g_j (r_i the
@@ -1379,8 +1379,10 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
             }
             n_vt += __popcll(__ballot(mok && lane == sm));
+            // build: the lane's column's accumulators, [slot][i][j][s] (members interleaved)
             float* dense = (MODE == kModeCount || MODE == kModeFill) && mok
-                               ? S.dense + (int64_t)(cl.y + sm) * S.cap_slots * G.NR * G.NR : nullptr;
+                               ? S.dense + (int64_t)(cl.y + ci * nzc) * S.dense_slab : nullptr;
+            const int s_of = R1 - r1, NRr = G.NR + nzc - 1;  // the member's ring shift
             // one list entry: forward atomics, or the adjoint (and gradient) products
             auto emit = [&](int e, double& gv) {
                 const int mm = L.e.m[e];
@@ -1398,7 +1400,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if (slot < 0) return;
                     }
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                    atomicAdd(&dense[((int64_t)slot * G.NR + ri) * G.NR + rj], t);
+                    atomicAdd(&dense[(((int64_t)slot * NRr + ri - s_of + nzc - 1) * NRr + rj - s_of + nzc - 1) * nzc + s_of],
+                              t);
                     return;
                 }
                 int64_t tb = L.e.key[e];
@@ -1463,8 +1466,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 acc[bb] = 0.0;
                 xv[bb] = ((MODE == kModeFwd || kGrad) && bb < nb) ? (double)(kGrad ? A.xt : A.x)[(int64_t)bb * G.nvox + v] : 0.0;
             }
-            float* dense = (MODE == kModeCount || MODE == kModeFill)
-                               ? S.dense + (int64_t)mi * S.cap_slots * G.NR * G.NR : nullptr;
+            float* dense = (MODE == kModeCount || MODE == kModeFill) ? S.dense + (int64_t)cl.y * S.dense_slab : nullptr;
+            const int NRr = G.NR + nzc - 1;
             for (int e = lane; e < total; e += 64) {
                 const int mm = L.e.m[e];
                 const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
@@ -1490,7 +1493,9 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if constexpr (kGrad) L.Gl[e] += (float)gv;
                     }
                 } else {
-                    atomicAdd(&dense[((int64_t)L.e.key[e] * G.NR + ri) * G.NR + rj], t);
+                    atomicAdd(&dense[(((int64_t)L.e.key[e] * NRr + ri - me.y + nzc - 1) * NRr + rj - me.y + nzc - 1) * nzc +
+                                     me.y],
+                              t);
                 }
             }
             if (kAdj) {
@@ -1675,7 +1680,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
-    float* dense = S.dense + (int64_t)mi * S.cap_slots * nrr;
+    const int nzc = A.cls[vb].w + 1, NRr = NR + nzc - 1;  // the column's members, interleaved
+    float* dense = S.dense + (int64_t)grp * S.dense_slab;
     const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     const int brow0 = A.cls[vb].w + 2 - sh;  // band row of r_i is r_i - shift + s_max + 2
@@ -1753,7 +1759,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             }
             col = rlo[lo] + (f - rpre[lo]);
             q = q0 + lo;
-            di = q * NR + col;
+            const int64_t slot = q / NR;
+            di = ((slot * NRr + (q - slot * NR) - sh + nzc - 1) * NRr + col - sh + nzc - 1) * nzc + sh;
             a = dense[di];
             if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
         }
