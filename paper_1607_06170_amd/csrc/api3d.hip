@@ -12,8 +12,8 @@ using namespace psf;
 
 namespace {
 
-constexpr int kBatchCsr = 128;    // voxels per batch of the matrix build (dense accumulators, FP32)
-constexpr int kShareCsr = 16;     // voxels per class in the matrix build (its accumulators interleave them)
+constexpr int kBatchCsr = 512;    // voxels per batch of the matrix build (dense accumulators, FP32)
+constexpr int kShareCsr = 8;      // voxels of one column in a class of the matrix build (interleaved accumulators)
 constexpr int kBatchProj = 512;   // voxels per batch of the projections
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
@@ -86,7 +86,7 @@ int check3d(const psf_handle* h, const psf_table* t) {
 }
 
 struct Ws3 {
-    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, dense, band, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
+    size_t counts, sidx, sth, pairs, slotmap, slot_tbin, slot_order, dense, band, bandc, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
         g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
     int64_t table_elems, cap_stage;
     int bmax, bcsr, cap_slots, band_rows;
@@ -118,11 +118,15 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * ntbins);
     L.slot_tbin = off;
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
+    L.slot_order = off;
+    off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;  // a class of n members takes n slabs: [slot][NR + n - 1][NR + n - 1][n]
     L.dense_slab = (int64_t)L.cap_slots * (NR + kShareCsr - 1) * (NR + kShareCsr - 1);
     off += align256(sizeof(float) * (size_t)L.bcsr * L.dense_slab);
-    L.band = off;  // a class's s_max is below the build batch's member count
-    L.band_rows = (int)NR + L.bcsr + 3;
+    L.band = off;  // a build class's s_max is below kShareCsr
+    L.band_rows = (int)NR + kShareCsr + 3;
+    off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
+    L.bandc = off;
     off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
     L.chunks = off;
     L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
@@ -210,6 +214,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.pairs = at3<int4>(ws, L.pairs);
     S.slotmap = at3<int>(ws, L.slotmap);
     S.slot_tbin = at3<int>(ws, L.slot_tbin);
+    S.slot_order = at3<int>(ws, L.slot_order);
     S.dense = at3<float>(ws, L.dense);
     S.dense_slab = L.dense_slab;
     S.chunk_counts = at3<int>(ws, L.chunks);
@@ -225,6 +230,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.uvgrad = L.uvgrad ? at3<double>(ws, L.uvgrad) : nullptr;
     S.xm = at3<float>(ws, L.xm);
     S.band = at3<int2>(ws, L.band);
+    S.bandc = at3<int2>(ws, L.bandc);
     S.band_rows = L.band_rows;
     return S;
 }
@@ -275,9 +281,7 @@ static int64_t column_image(int code, int64_t n, int64_t ixy) {
     return iy * n + ix;
 }
 
-// sym: classes may join the images of a column under the square's symmetry.  The
-// matrix build keeps one column per class: its rows are written per member, and
-// joining images there costs more in slot lookups than it saves in tiles.
+// sym: classes may join the images of a column under the square's symmetry.
 // share: most voxels of one column in a class.
 Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share) {
     Plan3 pl;
@@ -418,7 +422,10 @@ void set_batch(Args3D& a, const Batch3& b, const PlanDev& d) {
 int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args3D& a, const Batch3& b,
                    int want_slots, hipStream_t s) {
     HIP_TRY(launch_cyl3d_transaxial(G, S, a, want_slots, s));
-    if (want_slots) HIP_TRY(launch_band_init(S, a, s));
+    if (want_slots) {
+        HIP_TRY(launch_image_slots(G, S, a, s));
+        HIP_TRY(launch_band_init(S, a, s));
+    }
     HIP_TRY(launch_cyl3d_uvtab(G, S, a, b.uv_slots, s));
     ProfScope pg_(h, s, 1);
     HIP_TRY(launch_cyl3d_geom(G, S, a, s));
@@ -525,7 +532,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int phase_fill = csr->col != nullptr;
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, false, kShareCsr);
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, true, kShareCsr);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;

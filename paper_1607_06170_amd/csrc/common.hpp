@@ -63,8 +63,10 @@ struct Scratch3D {
     int* sidx;         // [B_cls][cap_samples]  s1 << 16 | s2
     double* sth;       // [B_cls][cap_samples][2]  direction interval of the sample
     int4* pairs;       // [B_cls][cap_pairs]  g1, g2, first sample, sample count
-    int* slotmap;      // [B_cls][ntbins]  transaxial bin -> slot (-1: none)
-    int* slot_tbin;    // [B_cls][cap_slots]
+    // matrix build, per column (index: the member index of its first voxel)
+    int* slotmap;      // [B_mem][ntbins]  transaxial bin -> slot (-1: none), reference columns
+    int* slot_tbin;    // [B_mem][cap_slots]  the column's bins in ascending order
+    int* slot_order;   // [B_mem][cap_slots]  their reference slots (bit 30: photons swapped)
     // matrix build: FP32 sums of the FP32 tile entries.  A column of n members
     // (s_max = n - 1) from batch member mi0 on holds [slot][i][j][s] from slab
     // mi0: member s's ring pair (r_i, r_j) at i = r_i - s + s_max, j = r_j - s +
@@ -89,9 +91,11 @@ struct Scratch3D {
     // (layout of uvtab), folded into the table entries after each batch
     double* uvgrad;    // [cap_uv][16][25], or null
     float* xm;         // [B_mem][8]  the batch members' image values (forward input, or the gradient's image)
-    // matrix build: for each class, slot and ring r_i relative to the reference
-    // member (offset s_max + 2), the range of r_j its tiles touched
-    int2* band;        // [B_cls][cap_slots][band_rows]
+    // matrix build: for each class (at its first member), reference slot and ring
+    // r_i relative to the reference voxel (offset s_max + 2), the range of r_j
+    // its tiles touched; bandc the same by column: for each r_j, the r_i range
+    int2* band;        // [B_mem][cap_slots][band_rows]
+    int2* bandc;       // [B_mem][cap_slots][band_rows]
     int band_rows;
 };
 constexpr int kXRep = 64;
@@ -206,6 +210,7 @@ hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const 
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
 hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st);
+hipError_t launch_image_slots(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
 hipError_t launch_gather_members(const Scratch3D& S, const Args3D& a, const float* x, int64_t nvox, hipStream_t st);

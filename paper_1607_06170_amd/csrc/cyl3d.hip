@@ -587,70 +587,134 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
         S.n_pairs[vb] = np;
     }
     if (!want_slots) return;
-    // transaxial bins of each column of the class (its crystals mapped by the
-    // column's image code): mark, then scan in bin order into slots.  Column i's
-    // maps live at group cl.y + i * nzc (the member index of its first voxel).
-    const int4 clv = A.cls[vb];
-    const int sy = A.sym[vb], nzc = sy & 0xff, codes = sy >> 8, ni = clv.z / nzc;
+    // the reference column's transaxial bins: mark, then scan in bin order into
+    // slots (group cl.y, the member index of its first voxel).  The class's other
+    // columns take their bins from these (k_image_slots).
+    const int grp = A.cls[vb].y;
     __shared__ int s_run;
     const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
-    for (int ci = 0; ci < ni; ++ci) {
-        const int code = (codes >> (3 * ci)) & 7, grp = clv.y + ci * nzc;
-        __syncthreads();
-        int* smap = S.slotmap + (int64_t)grp * G.ntbins;
-        for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
-        __syncthreads();
-        for (int p = tid; p < np; p += bs) {
-            const int4 pr = pairs[p];
-            for (int at = -2; at <= 2; ++at)
-                for (int bt = -2; bt <= 2; ++bt) {
-                    int gi = pr.x + at, gj = pr.y + bt;
-                    gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
-                    gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
-                    if (gi == gj) continue;
-                    gi = image_crystal(code, gi, G.Nc, G.nc);
-                    gj = image_crystal(code, gj, G.Nc, G.nc);
-                    const int lo_ = gi < gj ? gi : gj, hi_ = gi < gj ? gj : gi;
-                    smap[tbin_of(lo_, hi_, G.Nc)] = 1;
-                }
-        }
-        __syncthreads();
-        // block scan over the marks (chunks of bs), writing slot indices
-        int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
-        if (tid == 0) s_run = 0;
-        __syncthreads();
-        for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
-            const int64_t i = b0 + tid;
-            const int mk = i < G.ntbins ? smap[i] : 0;
-            const unsigned long long m = __ballot(mk != 0);
-            const int pre = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) red[wid] = __popcll(m);
-            __syncthreads();
-            int off = 0, tot = 0;
-            for (int w = 0; w < nw; ++w) {
-                off += w < wid ? red[w] : 0;
-                tot += red[w];
+    int* smap = S.slotmap + (int64_t)grp * G.ntbins;
+    for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
+    __syncthreads();
+    for (int p = tid; p < np; p += bs) {
+        const int4 pr = pairs[p];
+        for (int at = -2; at <= 2; ++at)
+            for (int bt = -2; bt <= 2; ++bt) {
+                int gi = pr.x + at, gj = pr.y + bt;
+                gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
+                gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
+                if (gi == gj) continue;
+                const int lo_ = gi < gj ? gi : gj, hi_ = gi < gj ? gj : gi;
+                smap[tbin_of(lo_, hi_, G.Nc)] = 1;
             }
-            const int run = s_run;
-            if (i < G.ntbins) {
-                if (mk) {
-                    const int slot = run + off + pre;
-                    smap[i] = slot < S.cap_slots ? slot : -1;
-                    if (slot < S.cap_slots) stb[slot] = (int)i;
-                } else {
-                    smap[i] = -1;
-                }
-            }
-            __syncthreads();
-            if (tid == 0) s_run = run + tot;
-            __syncthreads();
-        }
-        if (tid == 0) {
-            const int nsl = s_run;
-            if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
-            S.n_slots[grp] = nsl < S.cap_slots ? nsl : S.cap_slots;
-        }
     }
+    __syncthreads();
+    // block scan over the marks (chunks of bs), writing slot indices
+    int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
+        const int64_t i = b0 + tid;
+        const int mk = i < G.ntbins ? smap[i] : 0;
+        const unsigned long long m = __ballot(mk != 0);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) red[wid] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            off += w < wid ? red[w] : 0;
+            tot += red[w];
+        }
+        const int run = s_run;
+        if (i < G.ntbins) {
+            if (mk) {
+                const int slot = run + off + pre;
+                smap[i] = slot < S.cap_slots ? slot : -1;
+                if (slot < S.cap_slots) stb[slot] = (int)i;
+            } else {
+                smap[i] = -1;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_run = run + tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int nsl = s_run;
+        if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
+        S.n_slots[grp] = nsl < S.cap_slots ? nsl : S.cap_slots;
+    }
+}
+
+// The build's slots of each column of a class: the reference column's bins
+// (in K1's order) seen through the column's image code, sorted.  slot_order of
+// the column lists, in bin order, the reference slot of each bin, with bit 30
+// set when the image swaps the photon order (then its ring pair is the
+// reference's transposed); slot_tbin the bins.  One workgroup per column
+// (member blocks of shift 0); the reference column gets the identity.
+constexpr int kSortSlots = 4096;  // the build's slot capacity at most
+__global__ void __launch_bounds__(512) k_image_slots(Cyl3D G, Scratch3D S, Args3D A) {
+    __shared__ unsigned long long kv[kSortSlots];
+    const int grp = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
+    const int4 me = A.mem[grp];
+    if (me.y != 0) return;
+    const int4 cl = A.cls[me.z];
+    const int nzc = A.sym[me.z] & 0xff, codes = A.sym[me.z] >> 8;
+    const int ci = (grp - cl.y) / nzc, code = (codes >> (3 * ci)) & 7;
+    const int n = S.n_slots[cl.y];
+    int* order = S.slot_order + (int64_t)grp * S.cap_slots;
+    if (ci == 0) {
+        for (int k = tid; k < n; k += bs) order[k] = k;
+        return;
+    }
+    const int* rtb = S.slot_tbin + (int64_t)cl.y * S.cap_slots;
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int k = tid; k < np2; k += bs) {
+        unsigned long long v = ~0ull;
+        if (k < n) {
+            // the crystals of bin t: g_i = the last row start <= t, g_j from the offset
+            const int64_t t = rtb[k], N2 = 2 * (int64_t)G.Nc - 1;
+            int64_t gi = (int64_t)floor(0.5 * ((double)N2 - sqrt((double)(N2 * N2 - 8 * t))));
+            gi = gi < 0 ? 0 : (gi > G.Nc - 2 ? G.Nc - 2 : gi);
+            while (gi > 0 && tbin_of(gi, gi + 1, G.Nc) > t) --gi;
+            while (gi < G.Nc - 2 && tbin_of(gi + 1, gi + 2, G.Nc) <= t) ++gi;
+            const int gj = (int)(t - tbin_of(gi, gi + 1, G.Nc)) + (int)gi + 1;
+            const int a = image_crystal(code, (int)gi, G.Nc, G.nc), b = image_crystal(code, gj, G.Nc, G.nc);
+            const int64_t t2 = a < b ? tbin_of(a, b, G.Nc) : tbin_of(b, a, G.Nc);
+            v = ((unsigned long long)t2 << 32) | (unsigned)(k | (a > b ? 0x40000000 : 0));
+        }
+        kv[k] = v;
+    }
+    __syncthreads();
+    // bitonic sort, ascending
+    for (int k2 = 2; k2 <= np2; k2 <<= 1)
+        for (int j = k2 >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < np2; i += bs) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = kv[i], y = kv[l];
+                    if ((x > y) == ((i & k2) == 0)) {
+                        kv[i] = y;
+                        kv[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+    for (int k = tid; k < n; k += bs) {
+        order[k] = (int)(kv[k] & 0xffffffffu);
+        stb[k] = (int)(kv[k] >> 32);
+    }
+    if (tid == 0) S.n_slots[grp] = n;
+}
+
+hipError_t launch_image_slots(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
+    if (a.n_mem <= 0) return hipSuccess;
+    if (S.cap_slots > kSortSlots) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_image_slots, dim3(a.n_mem), dim3(512), 0, st, G, S, a);
+    return hipGetLastError();
 }
 
 size_t cyl3d_transaxial_smem(const Cyl3D& G) {
@@ -1069,13 +1133,15 @@ struct MmaLdsGrad {
 
 // the matrix build also gathers each tile's band contribution: for every
 // transaxial neighbour pair (a_t, b_t) and row of the tile, the r_j range of its
-// live entries, and the pair's slot (with the photon order in bit 30)
+// live entries (and for every column the r_i range), and the pair's slot (with
+// the photon order in bit 30)
 struct MmaLdsBuild {
     union {
         MmaOps o;
         MmaList e;
     };
-    int2 bnd[125];
+    int2 bnd[125];   // by row: the r_j range
+    int2 bndc[125];  // by column: the r_i range (classes with images)
     int bslot[25];
 };
 
@@ -1237,7 +1303,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         const int bt = bq / 5 - 2, bz = bq % 5 - 2;
         int gb = g2 + bt;
         gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-        // the reference column's slot map (group cl.y); columns with images map their crystals first
+        // the build keys entries by the reference column's slot (group cl.y); the
+        // projections by transaxial bin, or by crystals in classes with images
         const int* smap = (MODE == kModeCount || MODE == kModeFill) ? S.slotmap + (int64_t)cl.y * G.ntbins : nullptr;
         int key[16];
         unsigned int live = 0u, swap = 0u;
@@ -1249,17 +1316,15 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
             if (bq >= 25 || a >= 25 || ct[j] == 0.0f || ga == gb) continue;
             const bool sw = ga > gb;
-            const int tb_ = imgs ? (ga | (gb << 16)) : (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
-            if (imgs) {
-                key[j] = tb_;
-            } else if (MODE == kModeCount || MODE == kModeFill) {
+            const int tb_ = (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
+            if (MODE == kModeCount || MODE == kModeFill) {
                 key[j] = smap[tb_];
                 if (key[j] < 0) {
                     flag |= kStatScratch;
                     continue;
                 }
             } else {
-                key[j] = tb_;
+                key[j] = imgs ? (ga | (gb << 16)) : tb_;
             }
             live |= 1u << j;
             swap |= sw ? 1u << j : 0u;
@@ -1286,62 +1351,51 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         }
         __builtin_amdgcn_wave_barrier();
         if constexpr (MODE == kModeCount) {
-            // each column's band: the r_j range each (slot, relative r_i) row receives
+            // the reference column's band, in the reference's photon order: the
+            // r_j range each (slot, relative r_i) row receives, and with images
+            // also the r_i range of each (slot, relative r_j) column (a column
+            // whose image swaps the photons reads its rows there).  The tile's
+            // entries first meet in LDS, cell (a_t, b_t, row or column), where
+            // the row is a_z (b_z when photon 2 is first: the slot is ordered so).
             const int brow0 = nzc + 1;  // s_max + 2
-            const int ni = cl.z / nzc;
-            if (!imgs) {
-                // one column: the tile's rows first meet in LDS, cell (a_t, b_t, row), where
-                // the row is a_z (b_z when photon 2 is first: the pair's slot is ordered so)
-                for (int c = lane; c < 125; c += 64) L.bnd[c] = make_int2(0x7fffffff, -0x7fffffff);
-                __builtin_amdgcn_wave_barrier();
-                for (int e = lane; e < total; e += 64) {
-                    const int mm = L.e.m[e], ab = L.e.ab[e];
-                    const int az = mm & 7, bze = (mm >> 3) & 7;
-                    const bool sw = (mm >> 6) & 1;
-                    const int p = ((ab & 0xff) / 5) * 5 + (ab >> 8) / 5;
-                    const int c = p * 5 + (sw ? bze : az);
-                    const int bj = sw ? r1 + az - 2 : r2 + bze - 2;
-                    atomicMin(&L.bnd[c].x, bj);
-                    atomicMax(&L.bnd[c].y, bj);
-                    L.bslot[p] = L.e.key[e] | (sw ? 0x40000000 : 0);
+            for (int c = lane; c < 125; c += 64) {
+                L.bnd[c] = make_int2(0x7fffffff, -0x7fffffff);
+                L.bndc[c] = make_int2(0x7fffffff, -0x7fffffff);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < total; e += 64) {
+                const int mm = L.e.m[e], ab = L.e.ab[e];
+                const int az = mm & 7, bze = (mm >> 3) & 7;
+                const bool sw = (mm >> 6) & 1;
+                const int p = ((ab & 0xff) / 5) * 5 + (ab >> 8) / 5;
+                const int cr = p * 5 + (sw ? bze : az), cc = p * 5 + (sw ? az : bze);
+                const int ai = sw ? r2 + bze - 2 : r1 + az - 2, bj = sw ? r1 + az - 2 : r2 + bze - 2;
+                atomicMin(&L.bnd[cr].x, bj);
+                atomicMax(&L.bnd[cr].y, bj);
+                if (imgs) {
+                    atomicMin(&L.bndc[cc].x, ai);
+                    atomicMax(&L.bndc[cc].y, ai);
                 }
-                __builtin_amdgcn_wave_barrier();
-                int2* bg = S.band + (int64_t)cl.y * S.cap_slots * S.band_rows;
-                for (int c = lane; c < 125; c += 64) {
-                    const int2 v = L.bnd[c];
-                    if (v.x > v.y) continue;
-                    const int p = c / 5, ks = L.bslot[p];
-                    const int ai = ((ks & 0x40000000) ? r2 : r1) + (c - 5 * p) - 2;
-                    int2* b = bg + (int64_t)(ks & 0x3fffffff) * S.band_rows + ai + brow0;
+                L.bslot[p] = L.e.key[e] | (sw ? 0x40000000 : 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int64_t bbase = (int64_t)cl.y * S.cap_slots * S.band_rows;
+            for (int c = lane; c < 125; c += 64) {
+                const int p = c / 5, ks = L.bslot[p];
+                const bool sw = ks & 0x40000000;
+                const int64_t brow = bbase + (int64_t)(ks & 0x3fffffff) * S.band_rows + c - 5 * p - 2 + brow0;
+                const int2 v = L.bnd[c];
+                if (v.x <= v.y) {
+                    int2* b = S.band + brow + (sw ? r2 : r1);
                     atomicMin(&b->x, v.x);
                     atomicMax(&b->y, v.y);
                 }
-            }
-            for (int it = lane; imgs && it < total * ni; it += 64) {
-                int e = it, ci = 0;
-                while (e >= total) {
-                    e -= total;
-                    ++ci;
+                const int2 w = L.bndc[c];
+                if (imgs && w.x <= w.y) {
+                    int2* b = S.bandc + brow + (sw ? r1 : r2);
+                    atomicMin(&b->x, w.x);
+                    atomicMax(&b->y, w.y);
                 }
-                const int mm = L.e.m[e];
-                const int ra = r1 + (mm & 7) - 2, rb = r2 + ((mm >> 3) & 7) - 2;
-                bool sw = (mm >> 6) & 1;
-                int slot = L.e.key[e];
-                const int grp = cl.y + ci * nzc;
-                if (imgs) {
-                    const int code = (codes >> (3 * ci)) & 7;
-                    const int ga = image_crystal(code, slot & 0xffff, G.Nc, G.nc);
-                    const int gb = image_crystal(code, slot >> 16, G.Nc, G.nc);
-                    sw = ga > gb;
-                    slot = S.slotmap[(int64_t)grp * G.ntbins + tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc)];
-                    if (slot < 0) {
-                        flag |= kStatScratch;
-                        continue;
-                    }
-                }
-                int2* b = S.band + ((int64_t)grp * S.cap_slots + slot) * S.band_rows + (sw ? rb : ra) + brow0;
-                atomicMin(&b->x, sw ? ra : rb);
-                atomicMax(&b->y, sw ? ra : rb);
             }
         }
         // emission.  With at most 64 members: lane = (entry, member), the member
@@ -1391,13 +1445,13 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 const float t = L.e.t[e];
                 bool sw = (mm >> 6) & 1;
                 if (MODE == kModeCount || MODE == kModeFill) {
-                    int slot = L.e.key[e];
-                    if (imgs) {  // the entry's crystals seen from the member's column, in its slot map
-                        const int ga = image_crystal(code, slot & 0xffff, G.Nc, G.nc);
-                        const int gb = image_crystal(code, slot >> 16, G.Nc, G.nc);
-                        sw = ga > gb;
-                        slot = S.slotmap[(int64_t)(cl.y + ci * nzc) * G.ntbins + tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc)];
-                        if (slot < 0) return;
+                    const int slot = L.e.key[e];  // the reference column's slot
+                    if (imgs) {  // the photon order of the entry's crystals seen from the member's column
+                        const int ab = L.e.ab[e];
+                        int ga = g1 + (ab & 0xff) / 5 - 2, gb = g2 + (ab >> 8) / 5 - 2;
+                        ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                        gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                        sw = image_crystal(code, ga, G.Nc, G.nc) > image_crystal(code, gb, G.Nc, G.nc);
                     }
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
                     atomicAdd(&dense[(((int64_t)slot * NRr + ri - s_of + nzc - 1) * NRr + rj - s_of + nzc - 1) * nzc + s_of],
@@ -1647,12 +1701,15 @@ constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
 enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
 
 __global__ void k_band_init(Scratch3D S, Args3D A) {
-    const int grp = blockIdx.y;  // a member; the first voxel of each column holds the column's band
-    if (A.mem[grp].y != 0) return;
+    const int grp = blockIdx.y;  // a member; the first voxel of each class holds the class's bands
+    if (A.cls[A.mem[grp].z].y != grp) return;
     const int64_t n = (int64_t)S.n_slots[grp] * S.band_rows;
     int2* band = S.band + (int64_t)grp * S.cap_slots * S.band_rows;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    int2* bandc = S.bandc + (int64_t)grp * S.cap_slots * S.band_rows;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         band[i] = make_int2(0x7fffffff, -0x7fffffff);
+        bandc[i] = make_int2(0x7fffffff, -0x7fffffff);
+    }
 }
 
 hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st) {
@@ -1683,9 +1740,12 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int nzc = A.cls[vb].w + 1, NRr = NR + nzc - 1;  // the column's members, interleaved
     float* dense = S.dense + (int64_t)grp * S.dense_slab;
     const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+    // the column's slots in its bin order: the reference slot, and whether the
+    // image swaps the photons (the ring pair then reads the reference transposed)
+    const int* order = S.slot_order + (int64_t)grp * S.cap_slots;
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     const int brow0 = A.cls[vb].w + 2 - sh;  // band row of r_i is r_i - shift + s_max + 2
-    const int2* band = S.band + (int64_t)grp * S.cap_slots * S.band_rows;
+    const int64_t bref = (int64_t)A.cls[vb].y * S.cap_slots * S.band_rows;  // the class's bands
     // the chunk's rows: first column and length (band moved by the shift, cut to the scanner)
     {
         const int r = tid;  // kRowsC == kBlockC
@@ -1693,7 +1753,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         if (r < nq) {
             const int64_t q = q0 + r;
             const int slot = (int)(q / NR), ri = (int)(q - (int64_t)slot * NR);
-            const int2 b = band[(int64_t)slot * S.band_rows + ri + brow0];
+            const int ov = order[slot];
+            const int2 b = ((ov & 0x40000000) ? S.bandc : S.band)[bref + (int64_t)(ov & 0x3fffffff) * S.band_rows + ri + brow0];
             const int l = max(b.x + sh, 0), h = min(b.y + sh, NR - 1);
             if (b.x <= b.y && l <= h) {
                 lo = l;
@@ -1759,8 +1820,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             }
             col = rlo[lo] + (f - rpre[lo]);
             q = q0 + lo;
-            const int64_t slot = q / NR;
-            di = ((slot * NRr + (q - slot * NR) - sh + nzc - 1) * NRr + col - sh + nzc - 1) * nzc + sh;
+            const int64_t slot = q / NR, k = order[slot] & 0x3fffffff;
+            di = ((k * NRr + (q - slot * NR) - sh + nzc - 1) * NRr + col - sh + nzc - 1) * nzc + sh;
             a = dense[di];
             if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
         }
