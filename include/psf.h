@@ -112,6 +112,14 @@ typedef struct {
  * workspace with the same table and options copies them instead of
  * recomputing; rows that did not fit are recomputed. */
 #define PSF_OPT_STAGE_CSR 2
+/* psf_opts.flags (3D build_psf_sysmat): the caller asserts that since a build
+ * on this handle last completed on this workspace, the workspace was passed
+ * only to calls on this handle and not otherwise written.  The build then
+ * skips clearing its accumulators (every build leaves them clear; the last
+ * 32 bytes of the workspace header record the handle and layout that did, and
+ * the clear is skipped only when they match).  A wrong assertion gives wrong
+ * matrices; without the flag every build clears them (about 25 GB). */
+#define PSF_OPT_WS_CLEAN 4
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
 typedef struct {

@@ -82,6 +82,7 @@ class Scanner:
         check(self.L.psf_sizes(self.h, C.byref(nc), C.byref(nb), C.byref(nv)), "psf_sizes")
         self.n_crystals, self.n_bins, self.n_voxels = nc.value, nb.value, nv.value
         self._ws = None
+        self._ws_clean = False  # a 3D build completed on self._ws since it was allocated
 
     def __del__(self):
         try:
@@ -105,6 +106,7 @@ class Scanner:
               "psf_workspace_size")
         if self._ws is None or self._ws.numel() < n.value:
             self._ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+            self._ws_clean = False
         return self._ws
 
     # -- entry points --------------------------------------------------------
@@ -137,6 +139,9 @@ class Scanner:
         n = ve - vox_begin
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=self.device)
         ws = self.workspace(table, 1, 0, o)
+        if self._ws_clean:  # only this object's calls used the workspace since a build completed on it
+            o.flags |= _lib.PSF_OPT_WS_CLEAN
+        self._ws_clean = False
         tc = table.c()
         csr = _lib.psf_csr(n, 0, row_ptr.data_ptr(), None, None)
         check(self.L.build_psf_sysmat(self.h, C.byref(tc), C.byref(o), _ptr(ws), ws.numel(), C.byref(csr),
@@ -149,6 +154,7 @@ class Scanner:
         csr.col, csr.val = col.data_ptr(), val.data_ptr()
         check(self.L.build_psf_sysmat(self.h, C.byref(tc), C.byref(o), _ptr(ws), ws.numel(), C.byref(csr),
                                       _stream()), "build_psf_sysmat (fill)")
+        self._ws_clean = True
         if counters is not None:
             counters.append(self.header_counters())
         return row_ptr, col[:nnz], val[:nnz]

@@ -23,6 +23,7 @@ PSF_EUNSUPPORTED = -7
 
 PSF_OPT_TABLE_GRAD = 1
 PSF_OPT_STAGE_CSR = 2
+PSF_OPT_WS_CLEAN = 4
 
 PSF_FP32 = 0
 PSF_BF16 = 1

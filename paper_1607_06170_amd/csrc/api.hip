@@ -178,7 +178,7 @@ int check_opts(const psf_opts* o) {
 
 // status word: zero at the start of a call, read back by psf_check
 __global__ void k_zero_header(int* p) {
-    if (threadIdx.x < kWsHeader / sizeof(int)) p[threadIdx.x] = 0;
+    if (threadIdx.x < kWsDense / sizeof(int)) p[threadIdx.x] = 0;
 }
 
 int zero_header(void* ws, hipStream_t st) {

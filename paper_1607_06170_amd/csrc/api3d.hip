@@ -35,7 +35,7 @@ struct StageState {
     double threshold;
     int32_t precision, n_rows, n_sub, n_batches;
 };
-static_assert(kWsStage + sizeof(StageState) <= kWsHeader, "stage state fits the header");
+static_assert(kWsStage + sizeof(StageState) <= kWsDense, "stage state fits the header");
 constexpr unsigned long long kStageMagic = 0x5053465354414745ull;
 
 Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
@@ -555,9 +555,14 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
             return PSF_ESIZE;
         }
     }
-    // the dense accumulators start clean; the compaction leaves them clean
-    if (!(phase_fill && staged == (int)pl.batches.size()))
-        HIP_TRY(launch_zero_f32(S.dense, (int64_t)L.bcsr * L.dense_slab, s));
+    // the accumulators start clean (cleared, or known clean from the last build
+    // on this workspace); the compaction leaves them clean
+    const bool use_dense = !(phase_fill && staged == (int)pl.batches.size());
+    const unsigned long long dsig[3] = {(unsigned long long)(uintptr_t)h, (unsigned long long)L.dense,
+                                        (unsigned long long)(L.bcsr * L.dense_slab)};
+    unsigned long long* dstate = (unsigned long long*)((char*)ws + kWsDense);
+    if (use_dense)
+        HIP_TRY(launch_dense_clear(S.dense, L.bcsr * L.dense_slab, dstate, dsig, (o->flags & PSF_OPT_WS_CLEAN) != 0, s));
     // the count phase writes each row's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     PlanDev pd;
@@ -603,6 +608,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         }
         HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, S, a, s));
     }
+    if (use_dense) HIP_TRY(launch_dense_mark(dstate, dsig, 1, s));  // every batch compacted: clear again
     if (!phase_fill) {
         HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));
         int64_t nnz = 0;

@@ -26,9 +26,13 @@ constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or t
 constexpr size_t kWsHeader = 256;
 constexpr size_t kWsTileCounter = 64;
 constexpr size_t kWsVoxTileCounter = 72;
-// Bytes 128..255: the matrix build's staging state (cursor, full flag, staged
+// Bytes 128..223: the matrix build's staging state (cursor, full flag, staged
 // batches, then the signature of the count phase that filled it).
 constexpr size_t kWsStage = 128;
+// Bytes 224..255 survive the header clear of every call: the handle and the
+// accumulator layout of the last build that completed (left its accumulators
+// clear), or zeros.
+constexpr size_t kWsDense = 224;
 
 // Everything a 2D-ring kernel needs, passed by value.
 struct Ring2D {
@@ -212,6 +216,12 @@ hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
 hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_image_slots(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+// the build's accumulators: cleared unless `trust` and the header words at
+// `state` (magic, handle, offset, size) match `sig`; then marked in use
+hipError_t launch_dense_clear(float* p, int64_t n, unsigned long long* state, const unsigned long long* sig, bool trust,
+                              hipStream_t st);
+// marks the accumulators clean (`clean`, with the signature) or in use
+hipError_t launch_dense_mark(unsigned long long* state, const unsigned long long* sig, int clean, hipStream_t st);
 hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, hipStream_t st);
 hipError_t launch_gather_members(const Scratch3D& S, const Args3D& a, const float* x, int64_t nvox, hipStream_t st);
 hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,

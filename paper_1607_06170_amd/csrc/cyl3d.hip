@@ -1940,6 +1940,40 @@ __global__ void k_zero_f32(float* p, int64_t n) {
         p[i] = 0.0f;
 }
 
+constexpr unsigned long long kDenseMagic = 0x50534644454e5345ull;
+
+__global__ void k_dense_clear(float* p, int64_t n, const unsigned long long* state, unsigned long long s0,
+                              unsigned long long s1, unsigned long long s2, int trust) {
+    if (trust && state[0] == kDenseMagic && state[1] == s0 && state[2] == s1 && state[3] == s2) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void k_dense_mark(unsigned long long* state, unsigned long long s0, unsigned long long s1,
+                             unsigned long long s2, int clean) {
+    if (threadIdx.x == 0) {
+        state[0] = clean ? kDenseMagic : 0ull;
+        state[1] = s0;
+        state[2] = s1;
+        state[3] = s2;
+    }
+}
+
+hipError_t launch_dense_clear(float* p, int64_t n, unsigned long long* state, const unsigned long long* sig, bool trust,
+                              hipStream_t st) {
+    if (n > 0) {
+        const int64_t blocks = (n + 255) / 256;
+        hipLaunchKernelGGL(k_dense_clear, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, p, n,
+                           state, sig[0], sig[1], sig[2], trust ? 1 : 0);
+    }
+    return launch_dense_mark(state, sig, 0, st);
+}
+
+hipError_t launch_dense_mark(unsigned long long* state, const unsigned long long* sig, int clean, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_mark, dim3(1), dim3(64), 0, st, state, sig[0], sig[1], sig[2], clean);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;

@@ -138,6 +138,47 @@ def test_sysmat_staging_paths(torch, oracle, small_ref):
     _check_rows(oracle, row_ptr, col, val, cols, flags, np.arange(vb, ve))
 
 
+def test_sysmat_clean_workspace_flag(torch, oracle, small_ref):
+    """PSF_OPT_WS_CLEAN skips clearing the build's accumulators only when the
+    workspace header records a completed build of this handle and layout: on a
+    workspace of arbitrary bytes the build still clears them, and a build after
+    a projection on the same workspace (the Scanner sets the flag) gives the
+    same matrix."""
+    import ctypes as C
+    from paper_1607_06170_amd import _lib
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    vb, ve = 0, 200
+    ref = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, stage=False)
+    # a foreign workspace full of ones, with the flag: the header does not match, so the build clears
+    o = sc.opts(0, 0.0, vb, ve, flags=_lib.PSF_OPT_WS_CLEAN)
+    n_ws = C.c_size_t()
+    tc = t.c()
+    _lib.check(sc.L.psf_workspace_size(sc.h, C.byref(tc), C.byref(o), 1, 0, C.byref(n_ws)), "size")
+    ws = torch.ones(n_ws.value, dtype=torch.uint8, device="cuda")
+    n = ve - vb
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    csr = _lib.psf_csr(n, 0, row_ptr.data_ptr(), None, None)
+    ptr = lambda x: C.c_void_p(x.data_ptr())
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(sc.L.build_psf_sysmat(sc.h, C.byref(tc), C.byref(o), ptr(ws), ws.numel(), C.byref(csr), stream), "count")
+    col = torch.empty(csr.nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(csr.nnz, dtype=torch.float32, device="cuda")
+    csr.col, csr.val = col.data_ptr(), val.data_ptr()
+    _lib.check(sc.L.build_psf_sysmat(sc.h, C.byref(tc), C.byref(o), ptr(ws), ws.numel(), C.byref(csr), stream), "fill")
+    assert torch.equal(row_ptr, ref[0]) and torch.equal(col, ref[1])
+    np.testing.assert_allclose(val.cpu().numpy(), ref[2].cpu().numpy(), rtol=1e-6)
+    del ws
+    # the Scanner's own workspace: a projection, then a build that trusts the accumulators
+    sc.project_fwd(t, torch.ones(1, sc.n_voxels, device="cuda"))
+    assert sc._ws_clean
+    got = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, stage=False)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    np.testing.assert_allclose(got[2].cpu().numpy(), ref[2].cpu().numpy(), rtol=1e-6)
+    _check_rows(oracle, got[0], got[1], got[2], cols, flags, np.arange(vb, ve))
+
+
 def test_projections_small_scanner(torch, oracle, small_ref):
     td, cols, flags = small_ref
     sc = _scanner(SMALL)
