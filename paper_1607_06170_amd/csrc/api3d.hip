@@ -21,12 +21,11 @@ constexpr int kCapSlots = 4096;
 constexpr int64_t kRecsPerVoxel = 65536;   // tile records allowed for one voxel
 constexpr int64_t kRecBudget = 1 << 21;    // tile records per batch (1.1 KB each)
 constexpr int kUvRings = 16;               // response-row table: rings per batch beyond the members, in NR
-constexpr int64_t kStagePerVoxel = 131072;  // staged CSR entries allowed per voxel of the range
+constexpr int64_t kStagePerVoxel = 262144;  // staged cells (8 B; non-zeros and the band's zeros) per voxel of the range
 constexpr int64_t kStageMax = (int64_t)1 << 32;  // at most 32 GB of staged entries
 
 // the count phase's record of what it staged (workspace header, kWsStage)
 struct StageState {
-    unsigned long long cur;  // device: entries used
     int full;                // device: a row did not fit
     int batches;             // device: batches fully staged
     unsigned long long magic;
@@ -87,8 +86,8 @@ int check3d(const psf_handle* h, const psf_table* t) {
 
 struct Ws3 {
     size_t counts, sidx, sth, pairs, slotmap, slot_tbin, slot_order, dense, band, bandc, chunks, recs, reccount, uvtab, uvmask, xrep, xm, uvgrad,
-        g64, plan, stage_off, stage_tot, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
-    int64_t table_elems, cap_stage;
+        g64, plan, stage_cb, stage_cn, stage_nch, stage_cnt, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
+    int64_t table_elems, cap_stage, stage_rows;  // stage: entries; rows with a region of kStagePerVoxel
     int bmax, bcsr, cap_slots, band_rows;
     int64_t dense_slab;  // floats of one member's share of the build accumulators
     int64_t max_chunks;
@@ -165,12 +164,17 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     // matrix build staging (count phase -> fill phase)
     L.cap_stage = stage_rows > 0 ? (stage_rows * kStagePerVoxel < kStageMax ? stage_rows * kStagePerVoxel : kStageMax)
                                  : 0;
-    L.stage_off = L.stage_tot = L.stage_col = L.stage_val = 0;
+    L.stage_rows = L.cap_stage / kStagePerVoxel;
+    L.stage_cb = L.stage_cn = L.stage_nch = L.stage_cnt = L.stage_col = L.stage_val = 0;
     if (L.cap_stage > 0) {
-        L.stage_off = off;
-        off += align256(sizeof(int64_t) * (size_t)stage_rows);
-        L.stage_tot = off;
-        off += align256(sizeof(int64_t) * (size_t)L.bcsr);
+        L.stage_cb = off;
+        off += align256(sizeof(int64_t) * (size_t)stage_rows * L.max_chunks);
+        L.stage_cn = off;
+        off += align256(sizeof(int) * (size_t)stage_rows * L.max_chunks);
+        L.stage_nch = off;
+        off += align256(sizeof(int) * (size_t)stage_rows);
+        L.stage_cnt = off;
+        off += align256(sizeof(int) * (size_t)stage_rows);
         L.stage_col = off;
         off += align256(sizeof(int32_t) * (size_t)L.cap_stage);
         L.stage_val = off;
@@ -578,23 +582,25 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     a0.tiles = (unsigned long long*)((char*)ws + kWsTileCounter);
     a0.vtiles = (unsigned long long*)((char*)ws + kWsVoxTileCounter);
     if (stage) {
-        a0.stage_off = at3<int64_t>(ws, L.stage_off);  // indexed by row (voxel - vox_begin)
-        a0.stage_tot = at3<int64_t>(ws, L.stage_tot);
+        a0.stage_cb = at3<int64_t>(ws, L.stage_cb);  // indexed by row (voxel - vox_begin) and chunk
+        a0.stage_cn = at3<int>(ws, L.stage_cn);
+        a0.stage_nch = at3<int>(ws, L.stage_nch);
         a0.stage_col = at3<int32_t>(ws, L.stage_col);
         a0.stage_val = at3<float>(ws, L.stage_val);
-        a0.cap_stage = L.cap_stage;
+        a0.stage_cnt = at3<int>(ws, L.stage_cnt);
+        a0.stage_rows = L.stage_rows;
+        a0.stage_per_row = kStagePerVoxel;
+        if (!phase_fill) HIP_TRY(launch_zero_f32((float*)a0.stage_cnt, stage_rows(h, o), s));
         StageState* dss = (StageState*)((char*)ws + kWsStage);
-        a0.stage_cur = &dss->cur;
         a0.stage_full = &dss->full;
         a0.stage_batches = &dss->batches;
-        if (!phase_fill) HIP_TRY(launch_zero_f64((double*)a0.stage_tot, L.bcsr, s));
     }
     // fill phase: rows the count phase staged are copied
     if (staged > 0) {
         Args3D a = a0;
         set_batch(a, pl.batches[0], pd);
         const int n_rows = staged < (int)pl.batches.size() ? pl.batches[staged].mem0 : (int)pl.mem.size();
-        HIP_TRY(launch_stage_copy(a, n_rows, s));
+        HIP_TRY(launch_stage_copy(a, n_rows, L.max_chunks, s));
     }
     for (int bi = staged; bi < (int)pl.batches.size(); ++bi) {
         const Batch3& bt = pl.batches[bi];

@@ -26,8 +26,8 @@ constexpr int kStatEventBad = 8;  // an event names a crystal out of range, or t
 constexpr size_t kWsHeader = 256;
 constexpr size_t kWsTileCounter = 64;
 constexpr size_t kWsVoxTileCounter = 72;
-// Bytes 128..223: the matrix build's staging state (cursor, full flag, staged
-// batches, then the signature of the count phase that filled it).
+// Bytes 128..223: the matrix build's staging state (full flag, staged batches,
+// then the signature of the count phase that filled it).
 constexpr size_t kWsStage = 128;
 // Bytes 224..255 survive the header clear of every call: the handle and the
 // accumulator layout of the last build that completed (left its accumulators
@@ -141,14 +141,17 @@ struct Args3D {
     int ones;           // adjoint with y == 1 (sensitivity)
     const float* xt;    // [batch][nvox] image of the table gradient (adjoint with gradient)
     double* g64;        // table-gradient accumulator [table entries]
-    // matrix build, count phase with staging: rows compacted into the stage
+    // matrix build, count phase with staging: rows compacted into the stage, in
+    // pieces of one compaction chunk each
     int stage;
-    int64_t* stage_off;         // [rows of the range]  entry offset of a staged row, -1 if not staged
-    int64_t* stage_tot;         // [batch members]  kept entries (chunk sums)
+    int64_t* stage_cb;          // [rows of the range][max_chunks]  stage offset of a chunk's entries, -1 if none
+    int* stage_cn;              // [rows of the range][max_chunks]  its kept entries
+    int* stage_nch;             // [rows of the range]  the row's chunks
     int32_t* stage_col;         // [cap_stage]
     float* stage_val;           // [cap_stage]
-    int64_t cap_stage;
-    unsigned long long* stage_cur;  // workspace header: entries used
+    int64_t stage_rows;             // rows of the range with a stage region (the first ones)
+    int64_t stage_per_row;          // entries of a row's region
+    int* stage_cnt;                 // [stage_rows]  entries a row's chunks reserved
     int* stage_full;                // workspace header: a row did not fit (sticky)
     int* stage_batches;             // workspace header: batches fully staged
     unsigned long long* tiles;   // count of tiles contracted (workspace header)
@@ -212,7 +215,7 @@ hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D&
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
-hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st);
+hipError_t launch_stage_copy(const Args3D& a, int n_rows, int64_t max_chunks, hipStream_t st);
 hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_image_slots(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);

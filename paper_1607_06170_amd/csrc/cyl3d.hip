@@ -1692,13 +1692,17 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 // phase: a first pass stores the per-chunk counts, the second writes each
 // chunk at its offset (row start + counts of the chunks before it), in order.
 // The last pass over a chunk clears what it read for the next batch.  Count
-// phase with staging: the fill passes run, the row going to the stage at an
-// offset the allocator gave it (k_stage_alloc, between the passes).
+// phase with staging: one pass (kCompactStage below); the fill phase copies
+// each row's chunks in order (k_stage_copy).
 
 constexpr int kBlockC = 512;
 constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
 
-enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
+// kCompactStage (count phase with staging): one pass; each chunk reserves
+// room for all the cells it reads in its row's stage region (a per-row
+// counter), writes its kept entries there in order, and records (stage
+// offset, count) for the fill phase's copy.
+enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2, kCompactStage = 3 };
 
 __global__ void k_band_init(Scratch3D S, Args3D A) {
     const int grp = blockIdx.y;  // a member; the first voxel of each class holds the class's bands
@@ -1721,7 +1725,7 @@ hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st)
 template <int MODE>
 __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ int wave_tot[kBlockC / 64];
-    __shared__ int64_t s_run;
+    __shared__ int64_t s_run, s_base;
     __shared__ int rlo[kRowsC], rpre[kRowsC + 1];
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
     const int mi = blockIdx.y;  // member of the batch
@@ -1734,6 +1738,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int nsl = S.n_slots[grp];
     const int64_t nrows = (int64_t)nsl * NR;
     const int64_t q0 = chunk * kRowsC;
+    if (MODE == kCompactStage && chunk == 0 && threadIdx.x == 0) A.stage_nch[row] = (int)((nrows + kRowsC - 1) / kRowsC);
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
@@ -1781,7 +1786,22 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     }
     const int T = rpre[kRowsC];
     int64_t start = 0, cap = 0;
-    if (MODE == kCompactFill) {
+    if (MODE == kCompactStage) {
+        if (tid == 0) {
+            int64_t b = -1;
+            if (T > 0) {
+                if (row < A.stage_rows) {
+                    const int c = atomicAdd(&A.stage_cnt[row], T);
+                    if ((int64_t)c + T <= A.stage_per_row) b = row * A.stage_per_row + c;
+                }
+                if (b < 0) atomicOr(A.stage_full, 1);
+            }
+            s_base = b;
+            s_run = 0;
+        }
+        __syncthreads();
+        start = s_base;
+    } else if (MODE == kCompactFill) {
         // kept entries of the chunks before this one
         int64_t part = 0;
         for (int64_t c = tid; c < chunk; c += bs) part += ccount[c];
@@ -1794,13 +1814,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             for (int w = 0; w < nw; ++w) off += wave_tot[w];
             s_run = off;
         }
-        if (A.stage) {  // row_ptr[row + 1] holds the row's count until the scan
-            start = A.stage_off[row];
-            cap = start >= 0 ? A.row_ptr[row + 1] : 0;
-        } else {
-            start = A.row_ptr[row];
-            cap = A.row_ptr[row + 1] - start;
-        }
+        start = A.row_ptr[row];
+        cap = A.row_ptr[row + 1] - start;
     } else {
         if (tid == 0) s_run = 0;
     }
@@ -1825,7 +1840,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             a = dense[di];
             if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
         }
-        const bool keep = a > 0.0f && (double)a >= A.threshold && !(MODE == kCompactFill && A.stage && start < 0);
+        const bool keep = a > 0.0f && (double)a >= A.threshold;
         const unsigned long long m = __ballot(keep);
         const int pre = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) wave_tot[wid] = __popcll(m);
@@ -1836,18 +1851,16 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             tot += wave_tot[w];
         }
         const int64_t run = s_run;
-        if (MODE == kCompactFill && keep) {
+        if ((MODE == kCompactFill || (MODE == kCompactStage && start >= 0)) && keep) {
             const int64_t pos = run + off + pre;
-            if (pos < cap) {
-                const int64_t slot = q / NR, rr = (q - slot * NR) * NR + col;
-                const int32_t b = (int32_t)((int64_t)stb[slot] * nrr + rr);
-                if (A.stage) {
-                    A.stage_col[start + pos] = b;
-                    A.stage_val[start + pos] = a;
-                } else {
-                    A.col[start + pos] = b;
-                    A.val[start + pos] = a;
-                }
+            const int64_t slot = q / NR, rr = (q - slot * NR) * NR + col;
+            const int32_t b = (int32_t)((int64_t)stb[slot] * nrr + rr);
+            if (MODE == kCompactStage) {  // pos < T: the chunk's reservation
+                A.stage_col[start + pos] = b;
+                A.stage_val[start + pos] = a;
+            } else if (pos < cap) {
+                A.col[start + pos] = b;
+                A.val[start + pos] = a;
             } else {
                 atomicOr(A.status, kStatOverflow);
             }
@@ -1858,11 +1871,16 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     }
     if (tid == 0) {
         const int64_t n = s_run - run0;
-        if (MODE == kCompactCount) atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
-        else if (MODE == kCompactChunks) {
+        if (MODE == kCompactCount || MODE == kCompactStage)
+            atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
+        if (MODE == kCompactStage) {
+            A.stage_cb[row * S.max_chunks + chunk] = start;
+            A.stage_cn[row * S.max_chunks + chunk] = (int)n;
+        } else if (MODE == kCompactChunks) {
             ccount[chunk] = (int)n;
-            if (A.stage) atomicAdd((unsigned long long*)&A.stage_tot[mi], (unsigned long long)n);
-        } else if (q0 + nq == nrows && s_run != cap && !(A.stage && start < 0)) atomicOr(A.status, kStatOverflow);
+        } else if (MODE == kCompactFill && q0 + nq == nrows && s_run != cap) {
+            atomicOr(A.status, kStatOverflow);
+        }
     }
 }
 
@@ -1870,66 +1888,46 @@ int64_t cyl3d_max_chunks(int cap_slots, int NR) {
     return ((int64_t)cap_slots * NR + kRowsC - 1) / kRowsC;
 }
 
-// Staging allocator of one batch (one wavefront): members in order take
-// consecutive stage entries while they fit; the first that does not sets the
-// sticky full flag, and no later row is staged.  Sets each row's count in
-// row_ptr[row + 1] and clears the chunk sums.
-__global__ void __launch_bounds__(64) k_stage_alloc(Args3D A) {
-    const int lane = threadIdx.x;
-    unsigned long long cur = *A.stage_cur;
-    int full = *A.stage_full;
-    for (int m0 = 0; m0 < A.n_mem; m0 += 64) {
-        const int mi = m0 + lane;
-        const bool in = mi < A.n_mem;
-        const int64_t tot = in ? A.stage_tot[mi] : 0;
-        const int64_t row = in ? A.mem[mi].w : 0;
-        int64_t pre = tot;  // inclusive prefix over the lanes
-        for (int off = 1; off < 64; off <<= 1) {
-            const int64_t o = __shfl_up(pre, off, 64);
-            if (lane >= off) pre += o;
-        }
-        const bool fits = !full && cur + (unsigned long long)pre <= (unsigned long long)A.cap_stage;
-        if (in) {
-            A.row_ptr[row + 1] = tot;
-            A.stage_off[row] = fits ? (int64_t)(cur + pre - tot) : -1;
-            A.stage_tot[mi] = 0;
-        }
-        const unsigned long long ok = __ballot(in && fits), all = __ballot(in);
-        if (ok != all) full = 1;
-        cur += (unsigned long long)__shfl(pre, 63, 64) * (full ? 0ull : 1ull);
-    }
-    if (lane == 0) {
-        *A.stage_cur = cur;
-        *A.stage_full = full;
-        if (!full) *A.stage_batches += 1;
-    }
+// after a batch's staged compaction: the batch counts as staged if no chunk
+// so far lacked room
+__global__ void k_stage_batch(Args3D A) {
+    if (threadIdx.x == 0 && !*A.stage_full) *A.stage_batches += 1;
 }
 
-// fill phase: staged rows of the members [0, n) copied to their CSR place
-__global__ void __launch_bounds__(256) k_stage_copy(Args3D A) {
+// fill phase: staged rows of the members [0, n) copied to their CSR place,
+// chunk by chunk
+__global__ void __launch_bounds__(256) k_stage_copy(Args3D A, int64_t max_chunks) {
     const int64_t row = A.mem[blockIdx.x].w;
-    const int64_t src = A.stage_off[row], dst = A.row_ptr[row], n = A.row_ptr[row + 1] - dst;
-    if (src < 0) return;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        A.col[dst + i] = A.stage_col[src + i];
-        A.val[dst + i] = A.stage_val[src + i];
+    int64_t dst = A.row_ptr[row];
+    const int nch = A.stage_nch[row];
+    for (int c = 0; c < nch; ++c) {
+        const int64_t src = A.stage_cb[row * max_chunks + c];
+        const int n = A.stage_cn[row * max_chunks + c];
+        if (src >= 0)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                A.col[dst + i] = A.stage_col[src + i];
+                A.val[dst + i] = A.stage_val[src + i];
+            }
+        dst += n;
     }
 }
 
-hipError_t launch_stage_copy(const Args3D& a, int n_rows, hipStream_t st) {
+hipError_t launch_stage_copy(const Args3D& a, int n_rows, int64_t max_chunks, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stage_copy, dim3(n_rows), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_stage_copy, dim3(n_rows), dim3(256), 0, st, a, max_chunks);
     return hipGetLastError();
 }
 
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_mem <= 0) return hipSuccess;
     const dim3 grid((unsigned)S.max_chunks, a.n_mem), block(kBlockC);
-    if (mode == kModeCount && !a.stage) {
+    if (mode == kModeCount && a.stage) {
+        hipLaunchKernelGGL(k_cyl3d_compact<kCompactStage>, grid, block, 0, st, G, S, a);
+        hipLaunchKernelGGL(k_stage_batch, dim3(1), dim3(64), 0, st, a);
+    } else if (mode == kModeCount) {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactCount>, grid, block, 0, st, G, S, a);
     } else {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactChunks>, grid, block, 0, st, G, S, a);
-        if (a.stage) hipLaunchKernelGGL(k_stage_alloc, dim3(1), dim3(64), 0, st, a);
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactFill>, grid, block, 0, st, G, S, a);
     }
     return hipGetLastError();
