@@ -258,7 +258,8 @@ struct Plan3 {
     std::vector<int4> cls, mem;  // cls: reference voxel, first member (batch-relative), count, largest shift
     std::vector<int> uvoff;      // mem: voxel, shift, class (batch-relative), CSR row
     std::vector<int> sym;        // uvoff: first response-row slot of the class (batch-relative)
-    std::vector<Batch3> batches; // sym: voxels per column | image codes << 8 (3 bits per column)
+    std::vector<Batch3> batches; // sym: voxels per column | axial mirror << 8 | image codes of columns 1..7
+                                 //      << 9 (3 bits each)
 };
 
 int64_t class_recs(const Ws3& L, int64_t NR, int n) {
@@ -286,8 +287,10 @@ static int64_t column_image(int code, int64_t n, int64_t ixy) {
 }
 
 // sym: classes may join the images of a column under the square's symmetry.
+// zmir: a class may also take the axial mirror image of its z-run (z -> -z
+// about the scanner's centre), when the image grid is centred axially.
 // share: most voxels of one column in a class.
-Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share) {
+Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share, bool zmir) {
     Plan3 pl;
     const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -296,14 +299,16 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
     if (q >= 1.0 && q < 1e6 && fabs(q * h->im.dz - h->g.pitch_z) <= 1e-12 * h->g.pitch_z) m = (int64_t)q;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     sym = sym && square_symmetry(h);
+    zmir = zmir && h->im.cz == 0.0;
     int cmax = bmax < share ? bmax : share;
     while (cmax > 1 && (class_recs(L, NR, cmax) > L.cap_recs || NR + cmax - 1 > L.cap_uv_rings)) --cmax;
     Batch3 cur = {0, 0, 0, 0, 0};
     int64_t cur_recs = 0;
     // a class: reference voxel v0, nz voxels step `step` apart in z, in the
-    // columns images[0..ni) (image 0 the reference's own column)
-    auto add_class = [&](int64_t v0, int64_t step, int nzc, const int64_t* cols, const int* codes, int ni) {
-        const int n = nzc * ni;
+    // columns images[0..ni) (image 0 the reference's own column), and with
+    // `mir` also the axial mirror images of those voxels (listed in z order)
+    auto add_class = [&](int64_t v0, int64_t step, int nzc, const int64_t* cols, const int* codes, int ni, int mir) {
+        const int n = nzc * ni * (mir ? 2 : 1);
         const int64_t need = class_recs(L, NR, nzc), uv = Nc * (NR + nzc - 1);
         if (cur.nmem > 0 &&
             (cur.nmem + n > bmax || cur_recs + need > L.cap_recs || cur.uv_slots + uv > L.cap_uv)) {
@@ -313,16 +318,17 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
         }
         pl.cls.push_back(make_int4((int)v0, cur.nmem, n, nzc - 1));
         pl.uvoff.push_back((int)cur.uv_slots);
-        int sc = nzc;
-        for (int i = 0; i < ni; ++i) sc |= codes[i] << (8 + 3 * i);
+        int sc = nzc | (mir ? 1 << 8 : 0);
+        for (int i = 1; i < ni; ++i) sc |= codes[i] << (3 * i + 6);
         pl.sym.push_back(sc);
         cur.uv_slots += uv;
-        const int64_t z0 = v0 / nxy;
+        const int64_t z0 = v0 / nxy, zm = nz - 1 - (z0 + (int64_t)(nzc - 1) * (step / nxy));
         for (int i = 0; i < ni; ++i)
-            for (int k = 0; k < nzc; ++k) {
-                const int64_t v = cols[i] + (z0 * nxy + k * step);
-                pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
-            }
+            for (int h2 = 0; h2 < (mir ? 2 : 1); ++h2)
+                for (int k = 0; k < nzc; ++k) {
+                    const int64_t v = cols[i] + ((h2 ? zm : z0) * nxy + k * step);
+                    pl.mem.push_back(make_int4((int)v, k, cur.ncls, (int)(v - vb)));
+                }
         cur.ncls += 1;
         cur.nmem += n;
         cur_recs += need;
@@ -336,17 +342,36 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
     auto add_columns = [&](const int64_t* cols, const int* codes, int ni, int64_t zlo, int64_t zhi) {
         if (zlo > zhi) return;
         if (m == 0) {
-            for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(cols[0] + iz * nxy, 0, 1, cols, codes, ni);
+            for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(cols[0] + iz * nxy, 0, 1, cols, codes, ni, 0);
             return;
         }
-        int run = cmax;  // the contraction gives each of a class's members a lane: at most 64 with images
+        // the contraction gives each member of a class a lane in one of two passes
+        // of 64: at most 64 members with images, 128 with the mirror half too
+        int run = cmax;
         if (ni > 1 && run * ni > 64) run = 64 / ni;
+        std::vector<int64_t> rs, rn;  // runs: first z, voxels
         for (int64_t c = 0; c < m && zlo + c <= zhi; ++c) {
             const int64_t n_all = (zhi - (zlo + c)) / m + 1;
             for (int64_t k0 = 0; k0 < n_all; k0 += run) {
-                const int n = (int)(n_all - k0 < run ? n_all - k0 : run);
-                add_class(cols[0] + (zlo + c + k0 * m) * nxy, m * nxy, n, cols, codes, ni);
+                rs.push_back(zlo + c + k0 * m);
+                rn.push_back(n_all - k0 < run ? n_all - k0 : run);
             }
+        }
+        std::vector<char> used(rs.size(), 0);
+        for (size_t i = 0; i < rs.size(); ++i) {
+            if (used[i]) continue;
+            used[i] = 1;
+            int mir = 0;
+            if (zmir && rn[i] * ni * 2 <= 128) {  // the run whose voxels are this run's mirror images, if it is one
+                const int64_t s2 = nz - 1 - (rs[i] + (rn[i] - 1) * m);
+                for (size_t j = i + 1; j < rs.size(); ++j)
+                    if (!used[j] && rs[j] == s2 && rn[j] == rn[i]) {
+                        used[j] = 1;
+                        mir = 1;
+                        break;
+                    }
+            }
+            add_class(cols[0] + rs[i] * nxy, m * nxy, (int)rn[i], cols, codes, ni, mir);
         }
     };
     for (int64_t ixy = 0; ixy < nxy; ++ixy) {
@@ -440,7 +465,7 @@ int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args
 // into a diagonal-layout copy (FP32 atomics), permuted into y at the end
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              int accumulate, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -474,7 +499,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, g64 == nullptr);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -536,7 +561,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int phase_fill = csr->col != nullptr;
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, true, kShareCsr);
+    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, true, kShareCsr, true);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;

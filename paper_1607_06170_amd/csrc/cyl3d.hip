@@ -70,6 +70,14 @@ __device__ __forceinline__ int64_t tbin_of(int64_t gi, int64_t gj, int64_t Nc) {
 // crystal g of a column seen from its image `code` under the square's symmetry
 // (bit 2: the mirror y -> -y, c -> nc - 1 - c; bits 0-1: quarter turns, a
 // quarter of the ring's crystals each)
+// A class's symmetry word: voxels per column and half (bits 0-7), the axial
+// mirror half (bit 8), the image codes of columns 1..7 (3 bits each from bit 9;
+// column 0 is the reference).  Members go by column, then half, then z: member
+// m is voxel s2 = m % nzc of group g = m / nzc, column g (g / 2 with the
+// mirror half), half g % 2.  A mirror-half voxel is the axial image (rings
+// r -> NR - 1 - r) of reference-half voxel nzc - 1 - s2.
+__device__ __forceinline__ int sym_code(int sy, int ci) { return ci ? (sy >> (3 * ci + 6)) & 7 : 0; }
+
 __device__ __forceinline__ int image_crystal(int code, int g, int Nc, int nc) {
     if (code & 4) {
         g = nc - 1 - g;
@@ -646,12 +654,12 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     }
 }
 
-// The build's slots of each column of a class: the reference column's bins
-// (in K1's order) seen through the column's image code, sorted.  slot_order of
-// the column lists, in bin order, the reference slot of each bin, with bit 30
-// set when the image swaps the photon order (then its ring pair is the
-// reference's transposed); slot_tbin the bins.  One workgroup per column
-// (member blocks of shift 0); the reference column gets the identity.
+// The build's slots of each group (column and half) of a class: the reference
+// column's bins (in K1's order) seen through the column's image code, sorted.
+// slot_order of the group lists, in bin order, the reference slot of each bin,
+// with bit 30 set when the image swaps the photon order (then its ring pair is
+// the reference's transposed); slot_tbin the bins.  One workgroup per group
+// (member blocks of index 0); the reference column's groups get the identity.
 constexpr int kSortSlots = 4096;  // the build's slot capacity at most
 __global__ void __launch_bounds__(512) k_image_slots(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ unsigned long long kv[kSortSlots];
@@ -659,15 +667,20 @@ __global__ void __launch_bounds__(512) k_image_slots(Cyl3D G, Scratch3D S, Args3
     const int4 me = A.mem[grp];
     if (me.y != 0) return;
     const int4 cl = A.cls[me.z];
-    const int nzc = A.sym[me.z] & 0xff, codes = A.sym[me.z] >> 8;
-    const int ci = (grp - cl.y) / nzc, code = (codes >> (3 * ci)) & 7;
+    const int sy = A.sym[me.z], nzc = sy & 0xff, g = (grp - cl.y) / nzc;
+    const int ci = (sy & 0x100) ? g >> 1 : g, code = sym_code(sy, ci);
     const int n = S.n_slots[cl.y];
     int* order = S.slot_order + (int64_t)grp * S.cap_slots;
-    if (ci == 0) {
-        for (int k = tid; k < n; k += bs) order[k] = k;
+    const int* rtb = S.slot_tbin + (int64_t)cl.y * S.cap_slots;
+    if (ci == 0) {  // the reference column (its mirror half takes its bins too)
+        int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+        for (int k = tid; k < n; k += bs) {
+            order[k] = k;
+            if (g != 0) stb[k] = rtb[k];
+        }
+        if (tid == 0 && g != 0) S.n_slots[grp] = n;
         return;
     }
-    const int* rtb = S.slot_tbin + (int64_t)cl.y * S.cap_slots;
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
     for (int k = tid; k < np2; k += bs) {
@@ -1246,12 +1259,10 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         const int64_t sv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 5, 64));
         const int h6 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 6, 64));
         const int h7 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 7, 64));
-        // the class's members: first (batch index) and count, column-major: member
-        // i * nzc + s is voxel s (ring shift s) of column i, the image of the
-        // reference column under `codes` (3 bits per column; column 0 is the reference)
+        // the class's members: first (batch index) and count; h7 its symmetry word
         const int4 cl = make_int4(0, h6 & 0xffff, h6 >> 16, 0);
-        const int nzc = h7 & 0xff, codes = h7 >> 8;
-        const bool imgs = codes != 0;
+        const int nzc = h7 & 0xff;
+        const bool mir = h7 & 0x100, imgs = (h7 >> 9) != 0;
         __builtin_amdgcn_wave_barrier();
         // X = W V: lane l supplies W[l%16][k + l/16] and V[k + l/16][n0 + l%16]
 #pragma unroll
@@ -1398,14 +1409,18 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
             }
         }
-        // emission.  With at most 64 members: lane = (entry, member), the member
-        // fixed per lane (lane mod the member count rounded up to a power of
-        // two); projection sinograms in the diagonal layout, so a lane group
-        // touches consecutive floats.  Otherwise member by member.
-        int lg = 0;
-        while ((1 << lg) < cl.z) ++lg;
-        if (lg <= 6) {
-            const int msk = (1 << lg) - 1, sm = lane & msk;
+        // emission.  With at most 128 members, in passes of up to 64: lane =
+        // (entry, member), the member fixed per lane (lane mod the pass's member
+        // count rounded up to a power of two); projection sinograms in the
+        // diagonal layout, so a lane group touches consecutive floats.
+        // Otherwise member by member.
+        const int npass = (cl.z + 63) >> 6;
+        if (npass <= (kGrad ? 1 : 2)) {
+            int lg = 0;
+            while ((1 << lg) < (cl.z < 64 ? cl.z : 64)) ++lg;
+            const int msk = (1 << lg) - 1;
+            for (int mp = 0; mp < npass; ++mp) {
+            const int sm = (mp << 6) + (lane & msk);  // the lane's member
             int R1 = -1, R2 = -1;
             double xv[8], acc[8];
 #pragma unroll
@@ -1413,15 +1428,14 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 xv[bb] = 0.0;
                 acc[bb] = 0.0;
             }
-            bool mok = false;
-            int code = 0, ci = 0;
+            bool mok = false, mh = false;
+            int code = 0, g = 0, s2 = 0;
             if (sm < cl.z) {
-                int s = sm;  // column and ring shift of the lane's member
-                while (s >= nzc) {
-                    s -= nzc;
-                    ++ci;
-                }
-                code = (codes >> (3 * ci)) & 7;
+                g = sm / nzc;  // group (column and half) and index in it
+                s2 = sm - g * nzc;
+                mh = mir && (g & 1);
+                code = sym_code(h7, mir ? g >> 1 : g);
+                const int s = mh ? nzc - 1 - s2 : s2;  // the reference-half voxel: its ring shift
                 R1 = r1 + s;
                 R2 = r2 + s;
                 mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
@@ -1432,16 +1446,20 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if (bb < nb) xv[bb] = (double)xs[bb];
                 }
             }
-            n_vt += __popcll(__ballot(mok && lane == sm));
-            // build: the lane's column's accumulators, [slot][i][j][s] (members interleaved)
+            n_vt += __popcll(__ballot(mok && lane <= msk));
+            // build: the lane's group's accumulators, [slot][i][j][s2] (members interleaved)
             float* dense = (MODE == kModeCount || MODE == kModeFill) && mok
-                               ? S.dense + (int64_t)(cl.y + ci * nzc) * S.dense_slab : nullptr;
-            const int s_of = R1 - r1, NRr = G.NR + nzc - 1;  // the member's ring shift
+                               ? S.dense + (int64_t)(cl.y + g * nzc) * S.dense_slab : nullptr;
+            const int NRr = G.NR + nzc - 1;
             // one list entry: forward atomics, or the adjoint (and gradient) products
             auto emit = [&](int e, double& gv) {
                 const int mm = L.e.m[e];
-                const int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
+                int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
                 if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
+                if (mh) {  // the axial mirror image
+                    ra = G.NR - 1 - ra;
+                    rb = G.NR - 1 - rb;
+                }
                 const float t = L.e.t[e];
                 bool sw = (mm >> 6) & 1;
                 if (MODE == kModeCount || MODE == kModeFill) {
@@ -1454,8 +1472,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         sw = image_crystal(code, ga, G.Nc, G.nc) > image_crystal(code, gb, G.Nc, G.nc);
                     }
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                    atomicAdd(&dense[(((int64_t)slot * NRr + ri - s_of + nzc - 1) * NRr + rj - s_of + nzc - 1) * nzc + s_of],
-                              t);
+                    atomicAdd(&dense[(((int64_t)slot * NRr + ri - s2 + nzc - 1) * NRr + rj - s2 + nzc - 1) * nzc + s2], t);
                     return;
                 }
                 int64_t tb = L.e.key[e];
@@ -1487,7 +1504,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                     double gv = 0.0;
                     if (mok && e < total) emit(e, gv);
                     for (int off = 1; off <= msk; off <<= 1) gv += __shfl_xor(gv, off, 64);
-                    if (sm == 0 && e < total) L.Gl[e] = (float)gv;
+                    if ((lane & msk) == 0 && e < total) L.Gl[e] = (float)gv;
                 }
             } else if (mok) {
                 double gv = 0.0;
@@ -1499,12 +1516,13 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                     if (bb >= nb) break;
                     double sacc = acc[bb];
                     for (int off = 1 << lg; off < 64; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
-                    if (lane == sm && mok && sacc != 0.0)
+                    if (lane <= msk && mok && sacc != 0.0)
                         atomicAdd(&S.xrep[((int64_t)(wave0 % kXRep) * S.cap_mem + cl.y + sm) * 8 + bb], sacc);
                 }
             }
-        } else if (imgs) {
-            flag |= kStatGeom;  // classes with images have at most 64 members (the plan keeps them so)
+            }
+        } else if (imgs || mir) {
+            flag |= kStatGeom;  // classes with images have at most 128 members (the plan keeps them so)
         } else {
         if constexpr (kGrad)
             for (int e = lane; e < total; e += 64) L.Gl[e] = 0.0f;
@@ -1742,7 +1760,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
-    const int nzc = A.cls[vb].w + 1, NRr = NR + nzc - 1;  // the column's members, interleaved
+    const int nzc = A.cls[vb].w + 1, NRr = NR + nzc - 1;  // the group's members, interleaved
     float* dense = S.dense + (int64_t)grp * S.dense_slab;
     const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
     // the column's slots in its bin order: the reference slot, and whether the
@@ -1751,6 +1769,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     int* ccount = S.chunk_counts + (int64_t)mi * S.max_chunks;
     const int brow0 = A.cls[vb].w + 2 - sh;  // band row of r_i is r_i - shift + s_max + 2
     const int64_t bref = (int64_t)A.cls[vb].y * S.cap_slots * S.band_rows;  // the class's bands
+    // a mirror-half member reads the band of its reference-half voxel, rings
+    // reflected: relative row C - (r_i - shift), columns C + shift - [hi, lo]
+    const bool mh = (A.sym[vb] & 0x100) && (((grp - A.cls[vb].y) / nzc) & 1);
+    const int C = NR - 1 - A.cls[vb].w;
     // the chunk's rows: first column and length (band moved by the shift, cut to the scanner)
     {
         const int r = tid;  // kRowsC == kBlockC
@@ -1759,11 +1781,14 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             const int64_t q = q0 + r;
             const int slot = (int)(q / NR), ri = (int)(q - (int64_t)slot * NR);
             const int ov = order[slot];
-            const int2 b = ((ov & 0x40000000) ? S.bandc : S.band)[bref + (int64_t)(ov & 0x3fffffff) * S.band_rows + ri + brow0];
-            const int l = max(b.x + sh, 0), h = min(b.y + sh, NR - 1);
-            if (b.x <= b.y && l <= h) {
-                lo = l;
-                len = h - l + 1;
+            const int brow = mh ? NR + 1 - ri + sh : ri + brow0;
+            const int2 b = ((ov & 0x40000000) ? S.bandc : S.band)[bref + (int64_t)(ov & 0x3fffffff) * S.band_rows + brow];
+            if (b.x <= b.y) {  // else the row was never reached (and holds the empty sentinel)
+                const int l = max(mh ? C + sh - b.y : b.x + sh, 0), h = min(mh ? C + sh - b.x : b.y + sh, NR - 1);
+                if (l <= h) {
+                    lo = l;
+                    len = h - l + 1;
+                }
             }
         }
         // block exclusive scan of the lengths
