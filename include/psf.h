@@ -162,7 +162,10 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
  * Two phases on the same options:
  *   phase 1 (csr->col == NULL): writes row_ptr and sets csr->nnz; BLOCKS.
  *   phase 2: fills col/val (capacity csr->nnz); BLOCKS; PSF_EOVERFLOW if a
- *   row would exceed what phase 1 allotted. */
+ *   row would exceed what phase 1 allotted.
+ * 3D: PSF_EUNSUPPORTED when a class's accumulator cells (4096 transaxial
+ * slots x (NR + 7)^2 ring pairs x 8 voxels) would not index in 32 bits, that
+ * is for more than about 180 crystal rings. */
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
                      size_t workspace_bytes, psf_csr* csr, void* stream);
 

@@ -553,6 +553,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     if (st) return st;
     const Ws3 L = ws3_layout(h, t, 1, 0, o->flags & PSF_OPT_TABLE_GRAD, stage_rows(h, o));
     if (ws_bytes < L.total) return PSF_ESIZE;
+    if (L.dense_slab * kShareCsr >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;  // a group's cells index in 32 bits
     const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
     if (vb < 0 || ve > h->n_vox || ve < vb) return PSF_EINVAL;
     if (!csr->row_ptr) return PSF_EINVAL;

@@ -98,6 +98,15 @@ __device__ __forceinline__ void voxel_xyz(const Cyl3D& G, int64_t v, double& x, 
 // transaxial bin, (r_i, r_j) goes to the diagonal r_j - r_i (ascending), then
 // r_i.  Voxels of a class differ by whole rings, so one tile entry lands on
 // consecutive floats for consecutive members.
+// 32-bit forms for the emission (bins < 2^31, checked at the entry points)
+__device__ __forceinline__ int tbin32(int gi, int gj, int Nc) { return gi * Nc - ((gi * (gi + 1)) >> 1) + (gj - gi - 1); }
+__device__ __forceinline__ int diag32(int ri, int rj, int NR) {
+    const int d = rj - ri + NR - 1;
+    if (d < NR - 1) return ((d * (d + 1)) >> 1) + (ri - (NR - 1 - d));
+    const int k = d - (NR - 1);
+    return ((NR * (NR - 1)) >> 1) + k * NR - ((k * (k - 1)) >> 1) + ri;
+}
+
 __device__ __forceinline__ int64_t diag_index(int ri, int rj, int NR) {
     const int d = rj - ri + NR - 1;
     if (d < NR - 1) return (int64_t)d * (d + 1) / 2 + (ri - (NR - 1 - d));
@@ -1451,42 +1460,48 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             float* dense = (MODE == kModeCount || MODE == kModeFill) && mok
                                ? S.dense + (int64_t)(cl.y + g * nzc) * S.dense_slab : nullptr;
             const int NRr = G.NR + nzc - 1;
-            // one list entry: forward atomics, or the adjoint (and gradient) products
-            auto emit = [&](int e, double& gv) {
-                const int mm = L.e.m[e];
+            // one list entry (code, value, key, place): forward atomics, or the
+            // adjoint (and gradient) products
+            auto ld = [&](int e, int& mm, float& t, int& key, int& ab) {
+                mm = L.e.m[e];
+                t = L.e.t[e];
+                key = L.e.key[e];
+                ab = (MODE == kModeCount || MODE == kModeFill) && imgs ? L.e.ab[e] : 0;
+            };
+            auto emit = [&](int mm, float t, int key, int ab, double& gv) {
                 int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
                 if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
                 if (mh) {  // the axial mirror image
                     ra = G.NR - 1 - ra;
                     rb = G.NR - 1 - rb;
                 }
-                const float t = L.e.t[e];
                 bool sw = (mm >> 6) & 1;
                 if (MODE == kModeCount || MODE == kModeFill) {
-                    const int slot = L.e.key[e];  // the reference column's slot
+                    const int slot = key;  // the reference column's slot
                     if (imgs) {  // the photon order of the entry's crystals seen from the member's column
-                        const int ab = L.e.ab[e];
                         int ga = g1 + (ab & 0xff) / 5 - 2, gb = g2 + (ab >> 8) / 5 - 2;
                         ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
                         gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
                         sw = image_crystal(code, ga, G.Nc, G.nc) > image_crystal(code, gb, G.Nc, G.nc);
                     }
                     const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                    atomicAdd(&dense[(((int64_t)slot * NRr + ri - s2 + nzc - 1) * NRr + rj - s2 + nzc - 1) * nzc + s2], t);
+                    // the group's cells number below 2^31 (s_max < 8, at most 4096 slots)
+                    atomicAdd(&dense[((slot * NRr + ri - s2 + nzc - 1) * NRr + rj - s2 + nzc - 1) * nzc + s2], t);
                     return;
                 }
-                int64_t tb = L.e.key[e];
+                int tb = key;
                 if (imgs) {  // the entry's crystals seen from the member's column
                     const int ga = image_crystal(code, tb & 0xffff, G.Nc, G.nc);
-                    const int gb = image_crystal(code, (int)(tb >> 16), G.Nc, G.nc);
+                    const int gb = image_crystal(code, tb >> 16, G.Nc, G.nc);
                     sw = ga > gb;
-                    tb = tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
+                    tb = tbin32(sw ? gb : ga, sw ? ga : gb, G.Nc);
                 }
-                const int64_t idx = tb * G.NR * G.NR + (sw ? diag_index(rb, ra, G.NR) : diag_index(ra, rb, G.NR));
+                const int idx = tb * (G.NR * G.NR) + (sw ? diag32(rb, ra, G.NR) : diag32(ra, rb, G.NR));
                 if (MODE == kModeFwd) {
+                    // (float)(x * t) in FP32 equals the FP64 product rounded once (both are FP32 values)
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)(xv[bb] * t));
+                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)xv[bb] * t);
                 } else {
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb) {
@@ -1502,13 +1517,28 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 for (int e0 = 0; e0 < total; e0 += 64 >> lg) {
                     const int e = e0 + (lane >> lg);
                     double gv = 0.0;
-                    if (mok && e < total) emit(e, gv);
+                    if (mok && e < total) {
+                        int mm, key, ab;
+                        float t;
+                        ld(e, mm, t, key, ab);
+                        emit(mm, t, key, ab, gv);
+                    }
                     for (int off = 1; off <= msk; off <<= 1) gv += __shfl_xor(gv, off, 64);
                     if ((lane & msk) == 0 && e < total) L.Gl[e] = (float)gv;
                 }
             } else if (mok) {
-                double gv = 0.0;
-                for (int e = lane >> lg; e < total; e += 64 >> lg) emit(e, gv);
+                // the next entry's loads are in flight while one is emitted
+                const int step = 64 >> lg;
+                int e = lane >> lg, mm = 0, key = 0, ab = 0;
+                float t = 0.0f;
+                if (e < total) ld(e, mm, t, key, ab);
+                for (; e < total; e += step) {
+                    const int cm = mm, ck = key, ca = ab;
+                    const float cv = t;
+                    if (e + step < total) ld(e + step, mm, t, key, ab);
+                    double gv = 0.0;
+                    emit(cm, cv, ck, ca, gv);
+                }
             }
             if (kAdj) {
 #pragma unroll
