@@ -179,6 +179,36 @@ def test_sysmat_clean_workspace_flag(torch, oracle, small_ref):
     _check_rows(oracle, got[0], got[1], got[2], cols, flags, np.arange(vb, ve))
 
 
+# offsets chosen so that no voxel's angle-row decision sits on a rounding tie
+@pytest.mark.parametrize("shift", [dict(nx=9, cx=0.137), dict(nx=9, cx=0.137, cz=0.291)],
+                         ids=["axial-mirror-only", "no-symmetry"])
+def test_sysmat_and_projections_off_centre(torch, oracle, small_ref, shift):
+    """Images the square's symmetry does not map onto themselves (non-square,
+    off-centre): classes keep one column, and join their axial mirror run only
+    when the image is centred axially (first case).  Every row and both
+    projections against the oracle."""
+    cfg = dict(SMALL, **shift)
+    td = small_ref[0]
+    nr = cfg["n_rows"]
+    tab = oracle.TableRef(td, nr, 4, 1.0)
+    n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    cols, flags = oracle.columns_3d(cfg, tab, np.arange(n), cap=1 << 16)
+    sc = _scanner(cfg)
+    t = sc.table_from(td, nr, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0)
+    _check_rows(oracle, rp, col, val, cols, flags, np.arange(n))
+    A_T = _sparse(cols, sc.n_bins)
+    x = S.phantom_uniform(cfg, seed=9, batch=1)
+    xf = x.astype(np.float32).astype(np.float64)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo = (A_T.T @ xf.T).T
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    xb = sc.project_adj(t, torch.tensor(yo, dtype=torch.float32, device="cuda")).cpu().numpy()
+    xbo = (A_T @ yo.astype(np.float32).astype(np.float64).T).T
+    np.testing.assert_allclose(xb, xbo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xbo).max())
+    sc.check()
+
+
 def test_projections_small_scanner(torch, oracle, small_ref):
     td, cols, flags = small_ref
     sc = _scanner(SMALL)
