@@ -1140,17 +1140,27 @@ struct MmaList {
     unsigned short ab[640]; // a | b << 8: the entry's place in the tile
 };
 
-union MmaLds {
-    MmaOps o;
-    MmaList e;
+// classes with images: for each transaxial neighbour pair p = a_t * 5 + b_t
+// of the tile and column ci of the class, entry p * 8 + ci holds the pair's
+// transaxial bin seen from the column, with bit 31 set when the column's
+// image puts photon 2's crystal first
+struct MmaLds {
+    union {
+        MmaOps o;
+        MmaList e;
+    };
+    int ptab[200];
 };
 
 // the adjoint with the table gradient keeps the operands past the emission
 struct MmaLdsGrad {
     MmaOps o;
     MmaList e;
-    float Gm[32][33];  // d loss / d T
-    float Gl[640];     // the same, by list entry
+    union {
+        int ptab[200];     // during the emission
+        float Gm[32][33];  // after it: d loss / d T
+    };
+    float Gl[640];  // the same, by list entry
 };
 
 // the matrix build also gathers each tile's band contribution: for every
@@ -1165,6 +1175,7 @@ struct MmaLdsBuild {
     int2 bnd[125];   // by row: the r_j range
     int2 bndc[125];  // by column: the r_i range (classes with images)
     int bslot[25];
+    int ptab[200];
 };
 
 template <int MODE>
@@ -1366,10 +1377,28 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             L.e.t[pos] = ct[j];
             L.e.key[pos] = key[j];
             L.e.m[pos] = (unsigned char)(a % 5 | ((bz + 2) << 3) | (((swap >> j) & 1u) << 6));
-            if constexpr (kGrad || MODE == kModeCount) L.e.ab[pos] = (unsigned short)(a | (bq << 8));
+            L.e.ab[pos] = (unsigned short)(a | (bq << 8));
             ++pos;
         }
         __builtin_amdgcn_wave_barrier();
+        if (imgs) {  // the neighbour pairs seen from every column of the class
+            const int ni = cl.z / (nzc * (mir ? 2 : 1));
+            for (int it = lane; it < 200; it += 64) {
+                const int pp = it >> 3, ci = it & 7;
+                if (ci >= ni) continue;
+                int ga = g1 + pp / 5 - 2, gb = g2 + pp % 5 - 2;
+                ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                int v = 0;
+                if (ga != gb) {
+                    const int code = sym_code(h7, ci);
+                    const int a = image_crystal(code, ga, G.Nc, G.nc), b = image_crystal(code, gb, G.Nc, G.nc);
+                    v = (a < b ? tbin32(a, b, G.Nc) : tbin32(b, a, G.Nc)) | (a > b ? (int)0x80000000 : 0);
+                }
+                L.ptab[it] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
         if constexpr (MODE == kModeCount) {
             // the reference column's band, in the reference's photon order: the
             // r_j range each (slot, relative r_i) row receives, and with images
@@ -1438,12 +1467,11 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 acc[bb] = 0.0;
             }
             bool mok = false, mh = false;
-            int code = 0, g = 0, s2 = 0;
+            int g = 0, s2 = 0;
             if (sm < cl.z) {
                 g = sm / nzc;  // group (column and half) and index in it
                 s2 = sm - g * nzc;
                 mh = mir && (g & 1);
-                code = sym_code(h7, mir ? g >> 1 : g);
                 const int s = mh ? nzc - 1 - s2 : s2;  // the reference-half voxel: its ring shift
                 R1 = r1 + s;
                 R2 = r2 + s;
@@ -1466,37 +1494,33 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 mm = L.e.m[e];
                 t = L.e.t[e];
                 key = L.e.key[e];
-                ab = (MODE == kModeCount || MODE == kModeFill) && imgs ? L.e.ab[e] : 0;
+                ab = imgs ? L.e.ab[e] : 0;
             };
+            const int s_ref = R1 - r1;  // the reference-half voxel's ring shift
             auto emit = [&](int mm, float t, int key, int ab, double& gv) {
-                int ra = R1 + (mm & 7) - 2, rb = R2 + ((mm >> 3) & 7) - 2;
-                if (ra < 0 || ra >= G.NR || rb < 0 || rb >= G.NR) return;
-                if (mh) {  // the axial mirror image
-                    ra = G.NR - 1 - ra;
-                    rb = G.NR - 1 - rb;
-                }
+                // the entry's rings for the reference voxel; the member's are s_ref rings on
+                const int ai = r1 + (mm & 7) - 2, bj = r2 + ((mm >> 3) & 7) - 2;
+                if ((unsigned)(ai + s_ref) >= (unsigned)G.NR || (unsigned)(bj + s_ref) >= (unsigned)G.NR) return;
                 bool sw = (mm >> 6) & 1;
+                int tb = key;
+                if (imgs) {  // the pair seen from the member's column: p * 8 + ci, p = (a / 5) * 5 + b / 5
+                    const int v = L.ptab[((ab & 0xff) * 13 >> 6) * 40 + ((ab >> 8) * 13 >> 6) * 8 + (mir ? g >> 1 : g)];
+                    sw = v < 0;
+                    tb = v & 0x7fffffff;
+                }
+                const int u = sw ? bj : ai, w = sw ? ai : bj;  // (r_i, r_j) for the reference voxel
                 if (MODE == kModeCount || MODE == kModeFill) {
-                    const int slot = key;  // the reference column's slot
-                    if (imgs) {  // the photon order of the entry's crystals seen from the member's column
-                        int ga = g1 + (ab & 0xff) / 5 - 2, gb = g2 + (ab >> 8) / 5 - 2;
-                        ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
-                        gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-                        sw = image_crystal(code, ga, G.Nc, G.nc) > image_crystal(code, gb, G.Nc, G.nc);
-                    }
-                    const int ri = sw ? rb : ra, rj = sw ? ra : rb;
-                    // the group's cells number below 2^31 (s_max < 8, at most 4096 slots)
-                    atomicAdd(&dense[((slot * NRr + ri - s2 + nzc - 1) * NRr + rj - s2 + nzc - 1) * nzc + s2], t);
+                    // the group's cell: the same for all its members (key: the reference slot)
+                    const int i = mh ? G.NR - 1 - u : u + nzc - 1, j = mh ? G.NR - 1 - w : w + nzc - 1;
+                    atomicAdd(&dense[((key * NRr + i) * NRr + j) * nzc + s2], t);
                     return;
                 }
-                int tb = key;
-                if (imgs) {  // the entry's crystals seen from the member's column
-                    const int ga = image_crystal(code, tb & 0xffff, G.Nc, G.nc);
-                    const int gb = image_crystal(code, tb >> 16, G.Nc, G.nc);
-                    sw = ga > gb;
-                    tb = tbin32(sw ? gb : ga, sw ? ga : gb, G.Nc);
+                int ri = u + s_ref, rj = w + s_ref;
+                if (mh) {  // the axial mirror image
+                    ri = G.NR - 1 - ri;
+                    rj = G.NR - 1 - rj;
                 }
-                const int idx = tb * (G.NR * G.NR) + (sw ? diag32(rb, ra, G.NR) : diag32(ra, rb, G.NR));
+                const int idx = tb * (G.NR * G.NR) + diag32(ri, rj, G.NR);
                 if (MODE == kModeFwd) {
                     // (float)(x * t) in FP32 equals the FP64 product rounded once (both are FP32 values)
 #pragma unroll
