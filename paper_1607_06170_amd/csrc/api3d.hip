@@ -499,7 +499,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, g64 == nullptr);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;

@@ -1453,7 +1453,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         // diagonal layout, so a lane group touches consecutive floats.
         // Otherwise member by member.
         const int npass = (cl.z + 63) >> 6;
-        if (npass <= (kGrad ? 1 : 2)) {
+        if (npass <= 2) {
             int lg = 0;
             while ((1 << lg) < (cl.z < 64 ? cl.z : 64)) ++lg;
             const int msk = (1 << lg) - 1;
@@ -1548,7 +1548,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         emit(mm, t, key, ab, gv);
                     }
                     for (int off = 1; off <= msk; off <<= 1) gv += __shfl_xor(gv, off, 64);
-                    if ((lane & msk) == 0 && e < total) L.Gl[e] = (float)gv;
+                    if ((lane & msk) == 0 && e < total) L.Gl[e] = mp ? L.Gl[e] + (float)gv : (float)gv;
                 }
             } else if (mok) {
                 // the next entry's loads are in flight while one is emitted
