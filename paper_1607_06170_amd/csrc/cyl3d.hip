@@ -626,36 +626,36 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
             }
     }
     __syncthreads();
-    // block scan over the marks (chunks of bs), writing slot indices
+    // the marks numbered in bin order: each thread counts a contiguous range,
+    // one block-wide exclusive scan of the counts, then each thread numbers its range
     int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
-    if (tid == 0) s_run = 0;
-    __syncthreads();
-    for (int64_t b0 = 0; b0 < G.ntbins; b0 += bs) {
-        const int64_t i = b0 + tid;
-        const int mk = i < G.ntbins ? smap[i] : 0;
-        const unsigned long long m = __ballot(mk != 0);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) red[wid] = __popcll(m);
-        __syncthreads();
-        int off = 0, tot = 0;
-        for (int w = 0; w < nw; ++w) {
-            off += w < wid ? red[w] : 0;
-            tot += red[w];
-        }
-        const int run = s_run;
-        if (i < G.ntbins) {
-            if (mk) {
-                const int slot = run + off + pre;
-                smap[i] = slot < S.cap_slots ? slot : -1;
-                if (slot < S.cap_slots) stb[slot] = (int)i;
-            } else {
-                smap[i] = -1;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) s_run = run + tot;
-        __syncthreads();
+    const int64_t per = (G.ntbins + bs - 1) / bs, i0 = tid * per, i1 = i0 + per < G.ntbins ? i0 + per : G.ntbins;
+    int mine = 0;
+    for (int64_t i = i0; i < i1; ++i) mine += smap[i] != 0;
+    int inc = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
     }
+    if (lane == 63) red[wid] = inc;
+    __syncthreads();
+    int slot = inc - mine;
+    for (int w = 0; w < wid; ++w) slot += red[w];
+    if (tid == 0) {
+        int all = 0;
+        for (int w = 0; w < nw; ++w) all += red[w];
+        s_run = all;
+    }
+    for (int64_t i = i0; i < i1; ++i) {
+        if (smap[i]) {
+            smap[i] = slot < S.cap_slots ? slot : -1;
+            if (slot < S.cap_slots) stb[slot] = (int)i;
+            ++slot;
+        } else {
+            smap[i] = -1;
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
         const int nsl = s_run;
         if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
