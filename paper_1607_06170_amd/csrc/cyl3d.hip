@@ -1769,6 +1769,7 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 
 constexpr int kBlockC = 512;
 constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
+constexpr int kMapC = 8192;  // flat entries of a chunk mapped to their rows in LDS
 
 // kCompactStage (count phase with staging): one pass; each chunk reserves
 // room for all the cells it reads in its row's stage region (a per-row
@@ -1799,6 +1800,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     __shared__ int wave_tot[kBlockC / 64];
     __shared__ int64_t s_run, s_base;
     __shared__ int rlo[kRowsC], rpre[kRowsC + 1];
+    __shared__ int rbase[kRowsC], rbin[kRowsC];  // a row's cells: dense[rbase + col * nzc], bin rbin + col
+    __shared__ unsigned short rowof[kMapC];      // the row of each flat entry, when the chunk has at most kMapC
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
     const int mi = blockIdx.y;  // member of the batch
     const int4 me = A.mem[mi];
@@ -1832,9 +1835,11 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         const int r = tid;  // kRowsC == kBlockC
         int lo = 0, len = 0;
         if (r < nq) {
-            const int64_t q = q0 + r;
-            const int slot = (int)(q / NR), ri = (int)(q - (int64_t)slot * NR);
+            const int q = (int)(q0 + r);  // rows of a member: below 4096 slots x NR
+            const int slot = q / NR, ri = q - slot * NR;
             const int ov = order[slot];
+            rbase[r] = (((ov & 0x3fffffff) * NRr + ri - sh + nzc - 1) * NRr - sh + nzc - 1) * nzc + sh;
+            rbin[r] = stb[slot] * (NR * NR) + ri * NR;
             const int brow = mh ? NR + 1 - ri + sh : ri + brow0;
             const int2 b = ((ov & 0x40000000) ? S.bandc : S.band)[bref + (int64_t)(ov & 0x3fffffff) * S.band_rows + brow];
             if (b.x <= b.y) {  // else the row was never reached (and holds the empty sentinel)
@@ -1864,6 +1869,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         __syncthreads();
     }
     const int T = rpre[kRowsC];
+    if (T <= kMapC) {
+        for (int i = rpre[tid]; i < rpre[tid + 1]; ++i) rowof[i] = (unsigned short)tid;  // kRowsC == kBlockC
+        __syncthreads();
+    }
     int64_t start = 0, cap = 0;
     if (MODE == kCompactStage) {
         if (tid == 0) {
@@ -1903,19 +1912,20 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     for (int f0 = 0; f0 < T; f0 += bs) {
         const int f = f0 + tid;
         float a = 0.0f;
-        int64_t di = 0, q = 0;
-        int col = 0;
+        int lo = 0, col = 0;
         if (f < T) {
-            int lo = 0, hi = nq - 1;  // the row holding flat entry f: last r with rpre[r] <= f
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rpre[mid] <= f) lo = mid;
-                else hi = mid - 1;
+            if (T <= kMapC) {  // the row holding flat entry f
+                lo = rowof[f];
+            } else {  // last r with rpre[r] <= f
+                int hi = nq - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rpre[mid] <= f) lo = mid;
+                    else hi = mid - 1;
+                }
             }
             col = rlo[lo] + (f - rpre[lo]);
-            q = q0 + lo;
-            const int64_t slot = q / NR, k = order[slot] & 0x3fffffff;
-            di = ((k * NRr + (q - slot * NR) - sh + nzc - 1) * NRr + col - sh + nzc - 1) * nzc + sh;
+            const int di = rbase[lo] + col * nzc;
             a = dense[di];
             if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
         }
@@ -1932,8 +1942,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         const int64_t run = s_run;
         if ((MODE == kCompactFill || (MODE == kCompactStage && start >= 0)) && keep) {
             const int64_t pos = run + off + pre;
-            const int64_t slot = q / NR, rr = (q - slot * NR) * NR + col;
-            const int32_t b = (int32_t)((int64_t)stb[slot] * nrr + rr);
+            const int32_t b = rbin[lo] + col;
             if (MODE == kCompactStage) {  // pos < T: the chunk's reservation
                 A.stage_col[start + pos] = b;
                 A.stage_val[start + pos] = a;
