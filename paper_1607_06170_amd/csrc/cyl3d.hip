@@ -1126,6 +1126,8 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
 // which are spent by then); the emission then walks the members, each with its
 // rings shifted, the lanes spread over the list.
 
+constexpr int kGE = 4;  // adjoint list entries whose sinogram loads are in flight together
+
 struct MmaOps {
     float W[16][17];
     float U[16][25];
@@ -1142,14 +1144,17 @@ struct MmaList {
 
 // classes with images: for each transaxial neighbour pair p = a_t * 5 + b_t
 // of the tile and column ci of the class, entry p * 8 + ci holds the pair's
-// transaxial bin seen from the column, with bit 31 set when the column's
-// image puts photon 2's crystal first
+// transaxial bin seen from the column times NR^2 (the bin's first ring pair),
+// with bit 31 set when the column's image puts photon 2's crystal first.
+// The projections also keep, per list entry, the start of its ring-pair
+// diagonal for both photon orders (see the emission).
 struct MmaLds {
     union {
         MmaOps o;
         MmaList e;
     };
     int ptab[200];
+    unsigned int dd[640];
 };
 
 // the adjoint with the table gradient keeps the operands past the emission
@@ -1355,7 +1360,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                     continue;
                 }
             } else {
-                key[j] = imgs ? (ga | (gb << 16)) : tb_;
+                key[j] = imgs ? 0 : tb_ * (G.NR * G.NR);  // with images the pair table gives the bin
             }
             live |= 1u << j;
             swap |= sw ? 1u << j : 0u;
@@ -1380,6 +1385,29 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             L.e.ab[pos] = (unsigned short)(a | (bq << 8));
             ++pos;
         }
+        if constexpr (MODE == kModeFwd || MODE == kModeAdj) {
+            // the projections: ab packs the rings, the photon order and the pair's
+            // row of the pair table, (a_z + 2) | (b_z + 2) << 3 | swap << 6 | p << 7,
+            // and dd the start of the entry's ring-pair diagonal offset by NR (ring
+            // pair (r_i, r_j) sits at diag32(r_i, r_j) = start(r_j - r_i) + r_i), with
+            // photon 1 first (low half) and photon 2 first (high half): r_j - r_i is
+            // the same for every member up to that order and the axial mirror.
+            // Rings are below 256 (checked at the entry points), so starts fit 16 bits.
+            __builtin_amdgcn_wave_barrier();
+            const int NR = G.NR;
+            auto start = [&](int d) -> int {  // diag32(r_i, r_j) - r_i + NR, d = r_j - r_i + NR - 1
+                if (d < NR - 1) return ((d * (d + 1)) >> 1) - (NR - 1 - d) + NR;
+                const int k = d - (NR - 1);
+                return ((NR * (NR - 1)) >> 1) + k * NR - ((k * (k - 1)) >> 1) + NR;
+            };
+            for (int e = lane; e < total; e += 64) {
+                const int mm = L.e.m[e], ab = L.e.ab[e], a = ab & 0xff, b = ab >> 8;
+                const int dl = ((mm >> 3) & 7) - (mm & 7) + r2 - r1;  // r_j - r_i, photon 1 first
+                // (an entry whose difference leaves the scanner reaches no member: masked)
+                L.dd[e] = (unsigned int)(start(NR - 1 + dl) & 0xffff) | ((unsigned int)(start(NR - 1 - dl) & 0xffff) << 16);
+                L.e.ab[e] = (unsigned short)(mm | ((a / 5 * 5 + b / 5) << 7));
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         if (imgs) {  // the neighbour pairs seen from every column of the class
             const int ni = cl.z / (nzc * (mir ? 2 : 1));
@@ -1393,7 +1421,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 if (ga != gb) {
                     const int code = sym_code(h7, ci);
                     const int a = image_crystal(code, ga, G.Nc, G.nc), b = image_crystal(code, gb, G.Nc, G.nc);
-                    v = (a < b ? tbin32(a, b, G.Nc) : tbin32(b, a, G.Nc)) | (a > b ? (int)0x80000000 : 0);
+                    v = (a < b ? tbin32(a, b, G.Nc) : tbin32(b, a, G.Nc)) * (G.NR * G.NR) | (a > b ? (int)0x80000000 : 0);
                 }
                 L.ptab[it] = v;
             }
@@ -1476,7 +1504,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 R1 = r1 + s;
                 R2 = r2 + s;
                 mok = R1 >= 0 && R1 < G.NR && R2 >= 0 && R2 < G.NR;
-                if ((MODE == kModeFwd || kGrad) && mok) {
+                if (kGrad && mok) {
                     const float* xs = S.xm + (int64_t)(cl.y + sm) * 8;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb)
@@ -1497,10 +1525,12 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 ab = imgs ? L.e.ab[e] : 0;
             };
             const int s_ref = R1 - r1;  // the reference-half voxel's ring shift
-            auto emit = [&](int mm, float t, int key, int ab, double& gv) {
+            // the entry's cell for the lane's member: the accumulator cell (build) or
+            // the sinogram bin (projections); -1 when a ring leaves the scanner
+            auto locate = [&](int mm, int key, int ab) -> int {
                 // the entry's rings for the reference voxel; the member's are s_ref rings on
                 const int ai = r1 + (mm & 7) - 2, bj = r2 + ((mm >> 3) & 7) - 2;
-                if ((unsigned)(ai + s_ref) >= (unsigned)G.NR || (unsigned)(bj + s_ref) >= (unsigned)G.NR) return;
+                if ((unsigned)(ai + s_ref) >= (unsigned)G.NR || (unsigned)(bj + s_ref) >= (unsigned)G.NR) return -1;
                 bool sw = (mm >> 6) & 1;
                 int tb = key;
                 if (imgs) {  // the pair seen from the member's column: p * 8 + ci, p = (a / 5) * 5 + b / 5
@@ -1512,47 +1542,129 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 if (MODE == kModeCount || MODE == kModeFill) {
                     // the group's cell: the same for all its members (key: the reference slot)
                     const int i = mh ? G.NR - 1 - u : u + nzc - 1, j = mh ? G.NR - 1 - w : w + nzc - 1;
-                    atomicAdd(&dense[((key * NRr + i) * NRr + j) * nzc + s2], t);
-                    return;
+                    return ((key * NRr + i) * NRr + j) * nzc + s2;
                 }
                 int ri = u + s_ref, rj = w + s_ref;
                 if (mh) {  // the axial mirror image
                     ri = G.NR - 1 - ri;
                     rj = G.NR - 1 - rj;
                 }
-                const int idx = tb * (G.NR * G.NR) + diag32(ri, rj, G.NR);
-                if (MODE == kModeFwd) {
+                return tb + diag32(ri, rj, G.NR);
+            };
+            const int step = 64 >> lg;
+            if constexpr (MODE == kModeFwd || MODE == kModeAdj) {
+                // the lane's member: its column's row in the pair table, the axial
+                // mirror, and the rings of a list entry: offsets from r1s, r2s
+                const int ci = mir ? g >> 1 : g;
+                const int r1s = R1 - 2, r2s = R2 - 2, NR = G.NR;
+                auto cell = [&](int e, float& t) -> int {  // the entry's sinogram bin, or -1
+                    const int ab = L.e.ab[e];
+                    t = L.e.t[e];
+                    const int ai = r1s + (ab & 7), bj = r2s + ((ab >> 3) & 7);
+                    if ((unsigned)ai >= (unsigned)NR || (unsigned)bj >= (unsigned)NR) return -1;
+                    int tb;
+                    bool sw;
+                    if (imgs) {
+                        const int v = L.ptab[((ab >> 7) << 3) + ci];
+                        sw = v < 0;
+                        tb = v & 0x7fffffff;
+                    } else {
+                        sw = ab & 64;
+                        tb = L.e.key[e];
+                    }
+                    const unsigned int dd = L.dd[e];
+                    const int st = (int)(sw != mh ? dd >> 16 : dd & 0xffff) - NR;
+                    const int ri = sw ? bj : ai;
+                    return tb + st + (mh ? NR - 1 - ri : ri);
+                };
+                // image by image; kGE entries at a time: their bins first, then their
+                // atomics, or their sinogram loads (all in flight together) and the
+                // products in entry order
+                for (int bb = 0; bb < nb; ++bb) {
+                    const float* yb = A.yin + (int64_t)bb * G.nbins;
+                    float* ob = A.y + (int64_t)bb * G.nbins;
                     // (float)(x * t) in FP32 equals the FP64 product rounded once (both are FP32 values)
+                    const float xb = MODE == kModeFwd && mok ? S.xm[(int64_t)(cl.y + sm) * 8 + bb] : 0.0f;
+                    double acc1 = 0.0;
+                    if (mok && (MODE == kModeAdj || xb != 0.0f)) {
+                        for (int e0 = lane >> lg; e0 < total; e0 += kGE * step) {
+                            int c[kGE];
+                            float tv[kGE];
 #pragma unroll
-                    for (int bb = 0; bb < 8; ++bb)
-                        if (bb < nb && xv[bb] != 0.0) atomicAdd(&A.y[(int64_t)bb * G.nbins + idx], (float)xv[bb] * t);
-                } else {
+                            for (int u = 0; u < kGE; ++u) {
+                                const int e = e0 + u * step;
+                                c[u] = -1;
+                                tv[u] = 0.0f;
+                                if (e < total) c[u] = cell(e, tv[u]);
+                            }
+                            if constexpr (MODE == kModeFwd) {
+#pragma unroll
+                                for (int u = 0; u < kGE; ++u)
+                                    if (c[u] >= 0) atomicAdd(&ob[c[u]], xb * tv[u]);
+                            } else {
+                                float yv[kGE];
+#pragma unroll
+                                for (int u = 0; u < kGE; ++u) yv[u] = c[u] < 0 ? 0.0f : (A.ones ? 1.0f : yb[c[u]]);
+#pragma unroll
+                                for (int u = 0; u < kGE; ++u)
+                                    if (c[u] >= 0) acc1 += (double)tv[u] * (double)yv[u];
+                            }
+                        }
+                    }
+                    if constexpr (MODE == kModeAdj) {  // the member's sum over its lanes
+                        for (int off = 1 << lg; off < 64; off <<= 1) acc1 += __shfl_xor(acc1, off, 64);
+                        if (lane <= msk && mok && acc1 != 0.0)
+                            atomicAdd(&S.xrep[((int64_t)(wave0 % kXRep) * S.cap_mem + cl.y + sm) * 8 + bb], acc1);
+                    }
+                }
+            } else if constexpr (kGrad) {
+                // kGE entries at a time: their bins first, then all their sinogram
+                // loads in flight together, then the products in entry order.  With the
+                // table gradient every lane runs the same trip count: an entry's
+                // gradient sums across its member lanes.
+                for (int e0 = lane >> lg; e0 - (lane >> lg) < total; e0 += kGE * step) {
+                    int c[kGE];
+                    float tv[kGE];
+#pragma unroll
+                    for (int u = 0; u < kGE; ++u) {
+                        const int e = e0 + u * step;
+                        c[u] = -1;
+                        tv[u] = 0.0f;
+                        if (mok && e < total) {
+                            int mm, key, ab;
+                            ld(e, mm, tv[u], key, ab);
+                            c[u] = locate(mm, key, ab);
+                        }
+                    }
+                    double gv[kGE];
+#pragma unroll
+                    for (int u = 0; u < kGE; ++u) gv[u] = 0.0;
 #pragma unroll
                     for (int bb = 0; bb < 8; ++bb) {
                         if (bb >= nb) continue;
-                        const double yv = A.ones ? 1.0 : (double)A.yin[(int64_t)bb * G.nbins + idx];
-                        acc[bb] += (double)t * yv;
-                        if constexpr (kGrad) gv += xv[bb] * yv;
+                        float yv[kGE];
+#pragma unroll
+                        for (int u = 0; u < kGE; ++u)
+                            yv[u] = c[u] < 0 ? 0.0f : (A.ones ? 1.0f : A.yin[(int64_t)bb * G.nbins + c[u]]);
+#pragma unroll
+                        for (int u = 0; u < kGE; ++u) {
+                            if (c[u] < 0) continue;
+                            acc[bb] += (double)tv[u] * (double)yv[u];
+                            if constexpr (kGrad) gv[u] += xv[bb] * (double)yv[u];
+                        }
                     }
-                }
-            };
-            if constexpr (kGrad) {
-                // every lane runs the same trip count: the entry's gradient sums across its member lanes
-                for (int e0 = 0; e0 < total; e0 += 64 >> lg) {
-                    const int e = e0 + (lane >> lg);
-                    double gv = 0.0;
-                    if (mok && e < total) {
-                        int mm, key, ab;
-                        float t;
-                        ld(e, mm, t, key, ab);
-                        emit(mm, t, key, ab, gv);
+                    if constexpr (kGrad) {
+#pragma unroll
+                        for (int u = 0; u < kGE; ++u) {
+                            double g = gv[u];
+                            for (int off = 1; off <= msk; off <<= 1) g += __shfl_xor(g, off, 64);
+                            const int e = e0 + u * step;
+                            if ((lane & msk) == 0 && e < total) L.Gl[e] = mp ? L.Gl[e] + (float)g : (float)g;
+                        }
                     }
-                    for (int off = 1; off <= msk; off <<= 1) gv += __shfl_xor(gv, off, 64);
-                    if ((lane & msk) == 0 && e < total) L.Gl[e] = mp ? L.Gl[e] + (float)gv : (float)gv;
                 }
             } else if (mok) {
-                // the next entry's loads are in flight while one is emitted
-                const int step = 64 >> lg;
+                // the build: the next entry's loads are in flight while one is emitted
                 int e = lane >> lg, mm = 0, key = 0, ab = 0;
                 float t = 0.0f;
                 if (e < total) ld(e, mm, t, key, ab);
@@ -1560,11 +1672,11 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                     const int cm = mm, ck = key, ca = ab;
                     const float cv = t;
                     if (e + step < total) ld(e + step, mm, t, key, ab);
-                    double gv = 0.0;
-                    emit(cm, cv, ck, ca, gv);
+                    const int c = locate(cm, ck, ca);
+                    if (c >= 0) atomicAdd(&dense[c], cv);
                 }
             }
-            if (kAdj) {
+            if constexpr (kGrad) {
 #pragma unroll
                 for (int bb = 0; bb < 8; ++bb) {
                     if (bb >= nb) break;
@@ -1602,7 +1714,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 const bool sw = (mm >> 6) & 1;
                 const int ri = sw ? rb : ra, rj = sw ? ra : rb;
                 if (MODE == kModeFwd || kAdj) {
-                    const int64_t idx = (int64_t)L.e.key[e] * G.NR * G.NR + diag_index(ri, rj, G.NR);
+                    const int64_t idx = (int64_t)L.e.key[e] + diag_index(ri, rj, G.NR);
                     if (MODE == kModeFwd) {
 #pragma unroll
                         for (int bb = 0; bb < 8; ++bb)
