@@ -137,6 +137,7 @@ def main():
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     rec = dict(build=[], fwd=[], adj=[], nnz=0, tiles=0, vtiles=0)
+    last = {}   # the last timed step's outputs
 
     def step(record):
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
@@ -164,6 +165,7 @@ def main():
             rec["nnz"] += int(col.numel())
             rec["tiles"] += t_build + t_fwd + t_adj
             rec["vtiles"] += v_build + v_fwd + v_adj
+            last.update(rp=rp, col=col, val=val, y=y, xb=xb)
         return xb
 
     def log(msg):
@@ -243,6 +245,8 @@ def main():
                            "launches": k_launches}
     if meta["mode3d"]:
         out.update(extra_rows_3d(sc, tab, x, xb_last[0], cfg, prec, log))
+        if prec == 0:
+            out["forms"] = forms_rows(sc, tab, x, last, thr, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(cfg, meta, x_np, thr)
@@ -298,6 +302,50 @@ def extra_rows_3d(sc, tab, x, xt, cfg, prec, log):
     res["listmode"] = {"events": int(events.shape[0]), "ms": ms, "events_per_s": events.shape[0] / (ms * 1e-3),
                        "what": "one LM-OSEM subset update (M = 10), forward rows of the events and their back projection"}
     log(f"list-mode subset update: {events.shape[0]} events in {ms:.1f} ms")
+    return res
+
+
+def forms_rows(sc, tab, x, ref, thr, log):
+    """The BF16 forms of the tile contraction beside the FP32 form, on the same
+    workload and GPU: one step each (matrix build, forward of the phantom,
+    adjoint of the FP32 form's sinogram), timed after a warm-up step, and the
+    results against the FP32 form's (max over elements of |d| / |ref| for the
+    matrix when both have the same pattern; max |d| / max |ref| and the
+    relative 2-norm for the projections)."""
+    import torch
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    res = {}
+
+    def rel(a, b):
+        a, b = a.double(), b.double()
+        d = a - b
+        return {"max_rel_to_max": float(d.abs().max() / b.abs().max()),
+                "rel_l2": float(d.norm() / b.norm())}
+
+    for p, name in ((1, "bf16"), (2, "bf16x2")):
+        for _ in range(2):
+            e = [ev() for _ in range(4)]
+            e[0].record()
+            rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=p)
+            e[1].record()
+            y = sc.project_fwd(tab, x, precision=p)
+            e[2].record()
+            xb = sc.project_adj(tab, ref["y"], precision=p)
+            e[3].record()
+            torch.cuda.synchronize()
+        r = {"build_ms": e[0].elapsed_time(e[1]), "fwd_ms": e[1].elapsed_time(e[2]),
+             "adj_ms": e[2].elapsed_time(e[3]), "nnz": int(col.numel()),
+             "same_pattern": bool(torch.equal(rp, ref["rp"]) and torch.equal(col, ref["col"]))}
+        if r["same_pattern"]:
+            v32 = ref["val"].double()
+            r["matrix_max_rel_err"] = float(((val.double() - v32).abs() / v32.abs()).max())
+        r["fwd_vs_fp32"] = rel(y, ref["y"])
+        r["adj_vs_fp32"] = rel(xb, ref["xb"])
+        res[name] = r
+        log(f"{name}: build {r['build_ms']:.1f} ms, fwd {r['fwd_ms']:.1f} ms, adj {r['adj_ms']:.1f} ms; "
+            f"matrix max rel err {r.get('matrix_max_rel_err', float('nan')):.2e}, "
+            f"fwd {r['fwd_vs_fp32']['max_rel_to_max']:.2e}, adj {r['adj_vs_fp32']['max_rel_to_max']:.2e} vs FP32")
+        del rp, col, val, y, xb
     return res
 
 

@@ -249,6 +249,13 @@ def test_precision_forms_small_scanner(torch, oracle, small_ref):
             assert (np.abs(val[rp[r]:rp[r + 1]] - v) / v).max() <= e_tol
         y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda"), precision=prec).cpu().numpy()[0]
         assert (np.abs(y - yo)[big] / yo[big]).max() <= p_tol
+        # each projection as a whole (relative 2-norm): 1e-3 for BF16, 1e-5 for hi/lo
+        n_tol = 1e-3 if prec == 1 else 1e-5
+        assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= n_tol
+        ya = yo.astype(np.float32)
+        xo = A_T @ ya.astype(np.float64)
+        xa = sc.project_adj(t, torch.tensor(ya[None], device="cuda"), precision=prec).cpu().numpy()[0]
+        assert np.linalg.norm(xa - xo) / np.linalg.norm(xo) <= n_tol
 
 
 def _events3(oracle, cfg, A_T, x, n_true, n_rand, seed):
