@@ -874,6 +874,7 @@ constexpr int kQueue = 128;  // candidate queue (a power of two >= 127)
 struct WaveLds {
     float Wr[kR2Chunk][kMaxK][16];  // ring r2c + j, sample k: weights between pz1 * P + pz2
     int q[kQueue];
+    unsigned char cks[kR2Chunk * kMaxK];  // (ring, sample) pairs that pass the whole-face test
     double ta[kMaxK], tb[kMaxK];
     double ca[kMaxK], sa[kMaxK], cb[kMaxK], sb[kMaxK];  // unit vectors of the bundle's ends
     double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
@@ -999,7 +1000,39 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
             __builtin_amdgcn_wave_barrier();
             unsigned int jm = 0u;  // rings whose tile got a weight (this lane's share)
             int head = 0, tail = 0;
-            const int nk = nsmp * K, ncand = nj * nk;
+            // The quick test below, on the whole crystal faces of ring r1 and r2
+            // (the extreme sub-patches' own bounds, so the same rounding): its
+            // slope bounds grow with the face's z range when the direction cosines
+            // are positive, so a (ring, sample) pair that fails it fails for every
+            // pair of sub-patches and is dropped at once.
+            int nsurv = 0;
+            for (int c0 = 0; c0 < nj * nsmp; c0 += 64) {
+                const int c = c0 + lane;
+                bool pass = false;
+                if (c < nj * nsmp) {
+                    const int j = (c * smag) >> 16, k = c - j * nsmp;
+                    if ((jok >> j) & 1u) {
+                        pass = true;
+                        if (L.c1lo[k] > 0.0 && L.c2lo[k] > 0.0) {
+                            const int r2 = r2c + j;
+                            const double z1lo = G.z0 + (r1 + 0.0) * G.lz, z1hi = G.z0 + (r1 + 1.0) * G.lz;
+                            const double z2lo = G.z0 + (r2 + 0.0) * G.lz, z2hi = G.z0 + (r2 + 1.0) * G.lz;
+                            const double a1lo = (z1lo - vz) * invD1, a1hi = (z1hi - vz) * invD1;
+                            const double a2lo = (vz - z2hi) * invD2, a2hi = (vz - z2lo) * invD2;
+                            const double t1hi_max = a1hi * (a1hi >= 0.0 ? L.c1hi[k] : L.c1lo[k]);
+                            const double t1lo_min = a1lo * (a1lo >= 0.0 ? L.c1lo[k] : L.c1hi[k]);
+                            const double t2hi_max = a2hi * (a2hi >= 0.0 ? L.c2hi[k] : L.c2lo[k]);
+                            const double t2lo_min = a2lo * (a2lo >= 0.0 ? L.c2lo[k] : L.c2hi[k]);
+                            pass = !(t1hi_max <= t2lo_min || t2hi_max <= t1lo_min);
+                        }
+                    }
+                }
+                const unsigned long long bal = __ballot(pass);
+                if (pass) L.cks[nsurv + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned char)c;
+                nsurv += __popcll(bal);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int ncand = nsurv * K;
             // W3 of queue entry head + lane, when it exists
             auto eval = [&](int count) {
                 if (lane < count) {
@@ -1024,7 +1057,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                 bool pass = false;
                 int item = 0;
                 if (c < ncand) {
-                    const int ck = c / K, q = c - ck * K;
+                    const int sv = c / K, q = c - sv * K, ck = L.cks[sv];
                     const int j = (ck * smag) >> 16, k = ck - j * nsmp;
                     const int pz1 = q / P, pz2 = q - pz1 * P;
                     if ((jok >> j) & 1u) {
@@ -1062,14 +1095,16 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                 // range errors count only for response rows that carry weight
                 if (lane < 2 * K) {
                     const int l = lane < K ? lane : lane - K;
-                    const int pt = l / P, pz = l % P;
-                    float sum = 0.0f;
-                    for (int k = 0; k < nsmp; ++k) {
-                        if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
-                        for (int q = 0; q < P; ++q) sum += lane < K ? L.Wr[j][k][pz * P + q] : L.Wr[j][k][q * P + pz];
-                    }
                     const int m = lane < K ? umask[g1 * nr1 + r1 + smax] : umask[g2 * nr1 + r2 + smax];
-                    if (sum != 0.0f && ((m >> l) & 1)) flag |= kStatRange;
+                    if ((m >> l) & 1) {  // a row out of the table's range: an error if it carries weight
+                        const int pt = l / P, pz = l % P;
+                        float sum = 0.0f;
+                        for (int k = 0; k < nsmp; ++k) {
+                            if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
+                            for (int q = 0; q < P; ++q) sum += lane < K ? L.Wr[j][k][pz * P + q] : L.Wr[j][k][q * P + pz];
+                        }
+                        if (sum != 0.0f) flag |= kStatRange;
+                    }
                 }
                 // append the tile record: header, sample sub-segments, weight blocks
                 if (slot_next == slot_end) {
