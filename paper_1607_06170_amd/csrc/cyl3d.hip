@@ -875,6 +875,7 @@ struct WaveLds {
     float Wr[kR2Chunk][kMaxK][16];  // ring r2c + j, sample k: weights between pz1 * P + pz2
     int q[kQueue];
     unsigned char cks[kR2Chunk * kMaxK];  // (ring, sample) pairs that pass the whole-face test
+    unsigned char alive[kR2Chunk * kMaxK];  // by j * nsmp + k: whether the pair passed
     double ta[kMaxK], tb[kMaxK];
     double ca[kMaxK], sa[kMaxK], cb[kMaxK], sb[kMaxK];  // unit vectors of the bundle's ends
     double c1lo[kMaxK], c1hi[kMaxK], c2lo[kMaxK], c2hi[kMaxK];  // cos(theta - psi) ranges over the bundle
@@ -996,8 +997,6 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                 if (slo <= shi) jok |= 1u << j;
             }
             if (!jok) continue;
-            for (int e = lane; e < nj * kMaxK * 16; e += 64) L.Wr[e >> 8][(e >> 4) & 15][e & 15] = 0.0f;
-            __builtin_amdgcn_wave_barrier();
             unsigned int jm = 0u;  // rings whose tile got a weight (this lane's share)
             int head = 0, tail = 0;
             // The quick test below, on the whole crystal faces of ring r1 and r2
@@ -1030,6 +1029,14 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                 const unsigned long long bal = __ballot(pass);
                 if (pass) L.cks[nsurv + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned char)c;
                 nsurv += __popcll(bal);
+                if (c < nj * nsmp) L.alive[c] = pass;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // only the passing pairs' weight rows are cleared, read and written back
+            auto is_alive = [&](int j, int k) -> bool { return L.alive[j * nsmp + k] != 0; };
+            for (int e = lane; e < nsurv * 16; e += 64) {
+                const int ck = L.cks[e >> 4], j = (ck * smag) >> 16;
+                L.Wr[j][ck - j * nsmp][e & 15] = 0.0f;
             }
             __builtin_amdgcn_wave_barrier();
             const int ncand = nsurv * K;
@@ -1100,7 +1107,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                         const int pt = l / P, pz = l % P;
                         float sum = 0.0f;
                         for (int k = 0; k < nsmp; ++k) {
-                            if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt) continue;
+                            if ((lane < K ? L.pt1[k] : L.pt2[k]) != pt || !is_alive(j, k)) continue;
                             for (int q = 0; q < P; ++q) sum += lane < K ? L.Wr[j][k][pz * P + q] : L.Wr[j][k][q * P + pz];
                         }
                         if (sum != 0.0f) flag |= kStatRange;
@@ -1132,7 +1139,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
                     h[7] = A.sym[vb];
                 }
                 if (lane < nsmp) h[kRecPts + lane] = L.pt1[lane] | (L.pt2[lane] << 8);
-                for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = L.Wr[j][e >> 4][e & 15];
+                for (int e = lane; e < nsmp * 16; e += 64) rec[kRecHead + e] = is_alive(j, e >> 4) ? L.Wr[j][e >> 4][e & 15] : 0.0f;
             }
             __builtin_amdgcn_wave_barrier();
         }
