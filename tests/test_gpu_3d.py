@@ -345,3 +345,65 @@ def test_sysmat_full_scanner_sampled(torch, oracle, ijk):
     t = sc.table_from(td, 61, 4, 1.0)
     rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=v, vox_end=v + 1)
     _check_rows(oracle, rp, col, val, {v: cols[0]}, {v: flags[0]}, [v])
+
+
+def test_bench_workload_sampled(torch, oracle):
+    """The configuration the benchmark times: full scanner, central 16^3 voxels,
+    analytic table, every class (z-runs, square-symmetry images, axial mirrors)
+    in one call.  Sampled voxels' matrix rows, their adjoint and sensitivity
+    entries, and the forward projection of those voxels alone against the
+    oracle; <A x, y> = <x, A^T y> on dense seeded inputs."""
+    cfg = dict(CFG3, nx=16, ny=16, nz=16)
+    nr, P, step = cfg["n_rows"], cfg["n_sub"], cfg["step_deg"]
+    rt, rz = np.meshgrid(np.arange(nr), np.arange(nr), indexing="ij")
+    # the oracle's table, rounded to FP32 so that both sides read the same entries
+    td = oracle.table3_rows(cfg, rt.ravel(), rz.ravel(), P, step, 16).astype(np.float32).astype(np.float64)
+    samp = [(7, 8, 5), (8, 7, 10), (1, 4, 2), (13, 6, 9), (10, 2, 14), (5, 11, 1)]
+    vox = [(iz * 16 + iy) * 16 + ix for ix, iy, iz in samp]
+    cols, flags = oracle.columns_3d(cfg, oracle.TableRef(td, nr, P, step), vox, cap=1 << 21)
+    sc = _scanner(cfg)
+    t = sc.table_from(td, nr, P, step)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=cfg["threshold"])
+    rpc = rp.cpu().numpy()
+    exact = []
+    for v, (ob, ov), fl in zip(vox, cols, flags):
+        g = col[rpc[v]:rpc[v + 1]].cpu().numpy().astype(np.int64)
+        gv = val[rpc[v]:rpc[v + 1]].cpu().numpy()
+        if fl & oracle.F_TIES == 0:
+            assert np.array_equal(g, ob), f"voxel {v}: pattern differs ({len(g)} vs {len(ob)})"
+            np.testing.assert_allclose(gv, ov, rtol=RTOL, atol=0, err_msg=f"voxel {v}")
+            exact.append((v, ob, ov))
+        else:
+            m = dict(zip(ob.tolist(), ov.tolist()))
+            common = [k for k in range(len(g)) if int(g[k]) in m]
+            assert len(common) >= 0.99 * len(ob)
+            np.testing.assert_allclose(gv[common], [m[int(g[k])] for k in common], rtol=RTOL)
+    assert len(exact) >= 3
+    del col, val
+    # sensitivity and adjoint entries of the exact voxels: their columns summed, and against y
+    s = sc.sensitivity(t).cpu().numpy()
+    rng = np.random.default_rng(5)
+    yd = rng.random(sc.n_bins, dtype=np.float32)
+    xa = sc.project_adj(t, torch.from_numpy(yd[None]).cuda()).cpu().numpy()[0]
+    for v, ob, ov in exact:
+        np.testing.assert_allclose(s[v], ov.sum(), rtol=RTOL)
+        np.testing.assert_allclose(xa[v], ov @ yd[ob].astype(np.float64), rtol=RTOL)
+    # the forward projection of the exact voxels alone, bin by bin
+    xs = np.zeros(sc.n_voxels, np.float32)
+    ye = {}
+    for k, (v, ob, ov) in enumerate(exact):
+        xs[v] = 1.0 + 0.5 * k
+        for b, a in zip(ob.tolist(), ov.tolist()):
+            ye[b] = ye.get(b, 0.0) + float(xs[v]) * a
+    y = sc.project_fwd(t, torch.from_numpy(xs[None]).cuda())[0]
+    bins = np.fromiter(ye.keys(), np.int64)
+    ref = np.fromiter(ye.values(), np.float64)
+    got = y[torch.from_numpy(bins).cuda()].cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=RTOL, atol=0)
+    assert int((y != 0).sum().item()) == int(np.count_nonzero(ref))
+    # the adjoint identity at full size, dense seeded images
+    xd = torch.from_numpy(rng.random((1, sc.n_voxels), dtype=np.float32)).cuda()
+    yt = torch.from_numpy(yd[None]).cuda()
+    lhs = torch.dot(sc.project_fwd(t, xd)[0].double(), yt[0].double()).item()
+    rhs = torch.dot(xd[0].double(), torch.from_numpy(xa).cuda().double()).item()
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
