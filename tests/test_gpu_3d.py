@@ -407,3 +407,40 @@ def test_bench_workload_sampled(torch, oracle):
     lhs = torch.dot(sc.project_fwd(t, xd)[0].double(), yt[0].double()).item()
     rhs = torch.dot(xd[0].double(), torch.from_numpy(xa).cuda().double()).item()
     assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
+
+
+def test_bench_workload_table_grad_and_listmode(torch):
+    """Properties that hold at any size, on the benchmark's configuration:
+    f(table) = <y, A(table) x> is homogeneous of degree 2 in the table (each
+    tile is linear in U and in V, both linear in the table entries, the
+    block-edge remap included), so <grad f, table> = 2 f; list-mode rows
+    (per event, either photon order) equal the full forward projection at the
+    events' bins, and their back projection equals the adjoint of the events'
+    histogram."""
+    cfg = dict(CFG3, nx=16, ny=16, nz=16)
+    sc = _scanner(cfg)
+    t = sc.build_table(cfg["n_rows"], cfg["n_sub"], cfg["step_deg"])
+    rng = np.random.default_rng(9)
+    xt = torch.from_numpy(rng.random((1, sc.n_voxels), dtype=np.float32)).cuda()
+    yd = torch.from_numpy(rng.random((1, sc.n_bins), dtype=np.float32)).cuda()
+    yf = sc.project_fwd(t, xt)
+    f = torch.dot(yf[0].double(), yd[0].double()).item()
+    xb, grad = sc.project_adj(t, yd, xt=xt, want_table_grad=True)
+    g = torch.dot(grad.double(), t.data.double()).item()
+    assert abs(g - 2.0 * f) <= 1e-5 * abs(2.0 * f)
+    # list mode: 1e5 events on bins the phantom reaches
+    live = torch.nonzero(yf[0] > 0).reshape(-1).cpu().numpy()
+    bins = np.sort(rng.choice(live, 100_000))
+    gi, ri, gj, rj = _unbin3(bins, cfg)
+    Nc = cfg["n_blocks"] * cfg["n_ct"]
+    ci, cj = ri * Nc + gi, rj * Nc + gj
+    sw = rng.random(len(bins)) < 0.5
+    ev = torch.from_numpy(np.stack([np.where(sw, cj, ci), np.where(sw, ci, cj)], 1).astype(np.int32)).cuda()
+    q = sc.project_fwd(t, xt, events=ev)[0]
+    bt = torch.from_numpy(bins).cuda()
+    np.testing.assert_allclose(q.cpu().numpy(), yf[0][bt].cpu().numpy(), rtol=RTOL)
+    w = torch.from_numpy(rng.random(len(bins), dtype=np.float32)).cuda()
+    xl = sc.project_adj(t, w[None], events=ev)[0]
+    hist = torch.zeros(sc.n_bins, dtype=torch.float64, device="cuda").index_add_(0, bt, w.double())
+    xh = sc.project_adj(t, hist.float()[None])[0]
+    np.testing.assert_allclose(xl.cpu().numpy(), xh.cpu().numpy(), rtol=RTOL, atol=RTOL * 1e-2 * float(xh.abs().max()))
