@@ -80,7 +80,7 @@ struct Scratch3D {
     int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
     float* recs;       // [cap_recs][kRecFloats]  tile records (header, sample blocks of W)
-    unsigned int* rec_count;
+    unsigned int* rec_count;  // [0] records appended, [1] the geometry's next work unit (both reset by K1)
     int64_t cap_recs;
     // response rows of every (crystal g, relative ring r) of each class: slot
     // uvoff[class] + g * (NR + s_max) + (r + s_max) holds P^2 rows of 25

@@ -454,7 +454,10 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     const int vb = blockIdx.x;  // class of the batch
     const int64_t v = A.cls[vb].x;
     const int M1 = G.nc * G.P + 1, spb = G.nc * G.P;
-    if (vb == 0 && tid == 0) *S.rec_count = 0u;  // the batch's tile records start empty
+    if (vb == 0 && tid == 0) {  // the batch's tile records start empty, and so does the geometry's unit queue
+        S.rec_count[0] = 0u;
+        S.rec_count[1] = 0u;
+    }
     double* th = (double*)smem3;                    // [R * M1]
     double* unw = th + G.R * M1;                    // [nseg]
     int* cnt = (int*)(unw + G.nseg);                // [nseg + 1]
@@ -857,8 +860,10 @@ hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D&
 // lines reach, and that some member sees with both rings inside the scanner,
 // it computes the P^2 x P^2 weights W, one P x P block per line bundle
 // (sample), and when any is non-zero appends the record (header and the
-// blocks) for the contraction kernel.  The tasks of a class are dealt
-// round-robin to its workgroups; the batch gets about kGeomWG workgroups.
+// blocks) for the contraction kernel.  The units come from one queue: each
+// wavefront takes the batch's next unit (classes in order) from a device
+// counter until none is left, so that classes and units of unequal cost even
+// out over the kGeomWG workgroups.
 // Each wavefront takes record slots kSlotChunk at a time from the shared
 // counter and marks the ones it leaves unused empty (no samples).
 
@@ -895,25 +900,32 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
     constexpr int K = P * P;
     __shared__ WaveLds wl[kWavesT];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int vb = blockIdx.y;  // class of the batch
-    const int4 cl = A.cls[vb];
-    const int64_t v = cl.x;
-    const int smax = cl.w;
     WaveLds& L = wl[wid];
-    const int np = S.n_pairs[vb];
-    const int nr1 = G.NR + smax;
-    const int nrun = (nr1 + kR1Run - 1) / kR1Run;
-    const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
-    const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
-    const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
-    const int* umask = S.uvmask + A.uvoff[vb];
-    double vx, vy, vz;
-    voxel_xyz(G, v, vx, vy, vz);
     int flag = 0;
     unsigned int slot_next = 0, slot_end = 0;  // this wave's reserved record slots
     unsigned long long n_tiles = 0;
-    const int nunit = np * nrun;
-    for (int u = blockIdx.x * kWavesT + wid; u < nunit; u += gridDim.x * kWavesT) {
+    for (;;) {
+        // the next unit of the batch: classes in order, each np * nrun units
+        unsigned int next = 0;
+        if (lane == 0) next = atomicAdd(S.rec_count + 1, 1u);
+        int u = __builtin_amdgcn_readfirstlane(__shfl(next, 0, 64));
+        int vb = 0;
+        for (; vb < A.n_cls; ++vb) {
+            const int nu = S.n_pairs[vb] * ((G.NR + A.cls[vb].w + kR1Run - 1) / kR1Run);
+            if (u < nu) break;
+            u -= nu;
+        }
+        if (vb >= A.n_cls) break;  // every unit is taken
+        const int4 cl = A.cls[vb];
+        const int smax = cl.w;
+        const int nr1 = G.NR + smax;
+        const int nrun = (nr1 + kR1Run - 1) / kR1Run;
+        const int4* pairs = S.pairs + (int64_t)vb * S.cap_pairs;
+        const int* sidx = S.sidx + (int64_t)vb * S.cap_samples;
+        const double* sth = S.sth + (int64_t)vb * S.cap_samples * 2;
+        const int* umask = S.uvmask + A.uvoff[vb];
+        double vx, vy, vz;
+        voxel_xyz(G, cl.x, vx, vy, vz);
         const int pi = u / nrun;
         const int r1a = (u - pi * nrun) * kR1Run - smax, r1e = min(r1a + kR1Run, G.NR);
         const int4 pr = pairs[pi];
@@ -1831,9 +1843,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
 
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_cls <= 0) return hipSuccess;
-    int per_cls = (kGeomWG + a.n_cls - 1) / a.n_cls;
-    per_cls = per_cls < 8 ? 8 : (per_cls > 512 ? 512 : per_cls);
-    const dim3 grid(per_cls, a.n_cls), block(64 * kWavesT);
+    const dim3 grid(kGeomWG), block(64 * kWavesT);
     switch (G.P) {
         case 1: hipLaunchKernelGGL(k_cyl3d_geom<1>, grid, block, 0, st, G, S, a); break;
         case 2: hipLaunchKernelGGL(k_cyl3d_geom<2>, grid, block, 0, st, G, S, a); break;
