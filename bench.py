@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--workload", default="cyl3d_sub16", choices=["cyl3d_sub16", "ring2d_64"])
     ap.add_argument("--precision", type=int, default=0, help="0 FP32 plain, 1 BF16, 2 BF16 hi/lo")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-rows", action="store_true",
+                    help="skip the rows timed after the steps (table gradient, list mode, BF16 forms), e.g. under a "
+                         "profiler, so that its kernel mix is the timed step's")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB on the device (a kernel of known traffic, to scale PMC byte counters)")
     return ap.parse_args()
@@ -243,7 +246,7 @@ def main():
                            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                            "kernel": "k_voxel2d (per-voxel sweep, all modes)", "avg_launch_ms": avg_ms,
                            "launches": k_launches}
-    if meta["mode3d"]:
+    if meta["mode3d"] and not args.no_extra_rows:
         out.update(extra_rows_3d(sc, tab, x, xb_last[0], cfg, prec, log))
         if prec == 0:
             out["forms"] = forms_rows(sc, tab, x, last, thr, log)
