@@ -14,7 +14,8 @@ namespace {
 
 constexpr int kBatchCsr = 512;    // voxels per batch of the matrix build (dense accumulators, FP32)
 constexpr int kShareCsr = 8;      // voxels of one column in a class of the matrix build (interleaved accumulators)
-constexpr int kBatchProj = 512;   // voxels per batch of the projections
+constexpr int kBatchProj = 4096;  // voxels per batch of the projections (fewer, fuller launches)
+constexpr int kClsBatch = 2047;   // classes per batch: a tile record's header holds the class index in 11 bits
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
@@ -310,8 +311,8 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
     auto add_class = [&](int64_t v0, int64_t step, int nzc, const int64_t* cols, const int* codes, int ni, int mir) {
         const int n = nzc * ni * (mir ? 2 : 1);
         const int64_t need = class_recs(L, NR, nzc), uv = Nc * (NR + nzc - 1);
-        if (cur.nmem > 0 &&
-            (cur.nmem + n > bmax || cur_recs + need > L.cap_recs || cur.uv_slots + uv > L.cap_uv)) {
+        if (cur.nmem > 0 && (cur.nmem + n > bmax || cur.ncls + 1 > kClsBatch || cur_recs + need > L.cap_recs ||
+                             cur.uv_slots + uv > L.cap_uv)) {
             pl.batches.push_back(cur);
             cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0, 0};
             cur_recs = 0;

@@ -1333,7 +1333,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         const int g1 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 0, 64));
         const int g2 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 1, 64));
         const int hv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 2, 64));
-        const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512, vb = hv >> 20;
+        const int r1 = (hv & 1023) - 512, r2 = ((hv >> 10) & 1023) - 512;
         const int64_t su = __builtin_amdgcn_readfirstlane(__shfl(hcur, 4, 64));
         const int64_t sv = __builtin_amdgcn_readfirstlane(__shfl(hcur, 5, 64));
         const int h6 = __builtin_amdgcn_readfirstlane(__shfl(hcur, 6, 64));
@@ -2148,25 +2148,60 @@ __global__ void k_stage_batch(Args3D A) {
 
 // fill phase: staged rows of the members [0, n) copied to their CSR place,
 // chunk by chunk
-__global__ void __launch_bounds__(256) k_stage_copy(Args3D A, int64_t max_chunks) {
+// One workgroup per row. The row's chunk records are read kCopyTile at a time
+// (one per thread), their counts prefix-summed into output offsets, and the
+// chunks copied by the workgroup's wavefronts side by side.
+constexpr int kCopyTile = 512;
+
+__global__ void __launch_bounds__(kCopyTile) k_stage_copy(Args3D A, int64_t max_chunks) {
+    __shared__ int64_t csrc[kCopyTile];
+    __shared__ int64_t cdst[kCopyTile];
+    __shared__ int ccnt[kCopyTile];
+    __shared__ int wsum[kCopyTile / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kCopyTile / 64;
     const int64_t row = A.mem[blockIdx.x].w;
     int64_t dst = A.row_ptr[row];
     const int nch = A.stage_nch[row];
-    for (int c = 0; c < nch; ++c) {
-        const int64_t src = A.stage_cb[row * max_chunks + c];
-        const int n = A.stage_cn[row * max_chunks + c];
-        if (src >= 0)
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                A.col[dst + i] = A.stage_col[src + i];
-                A.val[dst + i] = A.stage_val[src + i];
-            }
-        dst += n;
+    for (int c0 = 0; c0 < nch; c0 += kCopyTile) {
+        const int c = c0 + tid;
+        const int n = c < nch ? A.stage_cn[row * max_chunks + c] : 0;
+        const int64_t src = c < nch ? A.stage_cb[row * max_chunks + c] : -1;
+        // exclusive prefix sum of the counts over the workgroup
+        int inc = n;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int base = 0, all = 0;
+        for (int w = 0; w < nw; ++w) {
+            base += w < wid ? wsum[w] : 0;
+            all += wsum[w];
+        }
+        csrc[tid] = src;
+        cdst[tid] = dst + base + inc - n;
+        ccnt[tid] = n;
+        __syncthreads();
+        const int nt = nch - c0 < kCopyTile ? nch - c0 : kCopyTile;
+        for (int k = wid; k < nt; k += nw) {
+            const int64_t s = csrc[k], d = cdst[k];
+            const int m = ccnt[k];
+            if (s >= 0)
+                for (int i = lane; i < m; i += 64) {
+                    A.col[d + i] = A.stage_col[s + i];
+                    A.val[d + i] = A.stage_val[s + i];
+                }
+        }
+        dst += all;
+        __syncthreads();  // before the next tile's records overwrite these
     }
 }
 
 hipError_t launch_stage_copy(const Args3D& a, int n_rows, int64_t max_chunks, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stage_copy, dim3(n_rows), dim3(256), 0, st, a, max_chunks);
+    hipLaunchKernelGGL(k_stage_copy, dim3(n_rows), dim3(kCopyTile), 0, st, a, max_chunks);
     return hipGetLastError();
 }
 
