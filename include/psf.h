@@ -172,12 +172,15 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
 /* Forward projection y = A x on the fly, without storing A (paper Table 2's
  * projector).  x_dev: [batch][n_voxels]; y_dev: [batch][n_bins] when
  * events_dev is NULL, else [batch][n_events] with events_dev an int32
- * [n_events][2] list of crystal pairs (list-mode rows). */
+ * [n_events][2] list of crystal pairs (list-mode rows).  An empty list
+ * (events_dev not NULL, n_events 0) writes nothing (y_dev may be NULL). */
 int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x_dev, int32_t batch,
                 const int32_t* events_dev, int64_t n_events, float* y_dev, void* workspace_dev,
                 size_t workspace_bytes, void* stream);
 
-/* Back projection x = A^T y (layouts as project_fwd).  If grad_table_dev is
+/* Back projection x = A^T y (layouts as project_fwd; an empty event list
+ * gives x = 0, or leaves x as it is with opts->accumulate, and y_dev may then
+ * be NULL).  If grad_table_dev is
  * not NULL, also accumulates d <y, A xt> / d table into it (FP32, table
  * layout, summed over the batch) with xt = xt_dev [batch][n_voxels]: each
  * response entry U[p][a] (Eq.6-7, with its mirror and two-block remap) is a

@@ -34,6 +34,20 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def _events_ptr(events):
+    """The event list's address: NULL means "every bin" to the library, so an
+    empty list (whose tensor has no storage) is passed as a non-NULL address
+    that is never read."""
+    if events is None:
+        return C.c_void_p(0)
+    if events.numel() == 0:
+        return C.c_void_p(C.addressof(_EMPTY_EVENTS))
+    return C.c_void_p(events.data_ptr())
+
+
+_EMPTY_EVENTS = C.c_int64(0)  # host storage whose address stands for an empty list
+
+
 def _dev_f32(t, name):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -173,7 +187,7 @@ class Scanner:
         o = self.opts(precision, accumulate=accumulate)
         ws = self.workspace(table, batch, ne, o)
         tc = table.c()
-        check(self.L.project_fwd(self.h, C.byref(tc), C.byref(o), _ptr(x2), batch, _ptr(events), ne, _ptr(y),
+        check(self.L.project_fwd(self.h, C.byref(tc), C.byref(o), _ptr(x2), batch, _events_ptr(events), ne, _ptr(y),
                                  _ptr(ws), ws.numel(), _stream()), "project_fwd")
         return y
 
@@ -184,7 +198,7 @@ class Scanner:
         y = _dev_f32(y, "y")
         ne = 0 if events is None else int(events.shape[0])
         nin = self.n_bins if events is None else ne
-        y2 = y.reshape(-1, nin)
+        y2 = y.reshape(-1, nin) if nin > 0 else y.reshape(y.shape[0] if y.dim() > 1 else 1, 0)
         batch = y2.shape[0]
         if x is None:
             x = torch.empty(batch, self.n_voxels, dtype=torch.float32, device=self.device)
@@ -195,7 +209,7 @@ class Scanner:
         o = self.opts(precision, accumulate=accumulate, flags=_lib.PSF_OPT_TABLE_GRAD if want_table_grad else 0)
         ws = self.workspace(table, batch, ne, o)
         tc = table.c()
-        check(self.L.project_adj(self.h, C.byref(tc), C.byref(o), _ptr(y2), batch, _ptr(events), ne, _ptr(x),
+        check(self.L.project_adj(self.h, C.byref(tc), C.byref(o), _ptr(y2), batch, _events_ptr(events), ne, _ptr(x),
                                  _ptr(xt if want_table_grad else None), _ptr(grad), _ptr(ws), ws.numel(),
                                  _stream()), "project_adj")
         return (x, grad) if want_table_grad else x

@@ -368,8 +368,9 @@ extern "C" {
 
 int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int32_t batch,
                 const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, void* stream) {
-    if (!h || !x || !y || !ws || batch < 1 || n_events < 0) return PSF_EINVAL;
-    if (events && n_events == 0) return PSF_OK;
+    if (!h || !x || batch < 1 || n_events < 0) return PSF_EINVAL;
+    if (events && n_events == 0) return PSF_OK;  // an empty event list: y has no entries
+    if (!y || !ws) return PSF_EINVAL;
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
@@ -393,11 +394,16 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
 int project_adj(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int32_t batch,
                 const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
                 size_t ws_bytes, void* stream) {
-    if (!h || !y || !x || !ws || batch < 1 || n_events < 0) return PSF_EINVAL;
+    if (!h || !x || batch < 1 || n_events < 0) return PSF_EINVAL;
     if (grad && !xt) return PSF_EINVAL;
     int st = check_table(h, table);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
+    if (events && n_events == 0) {  // an empty event list: x = 0 (kept when accumulating), nothing added to grad
+        if (!opts->accumulate) HIP_TRY(launch_zero_f32(x, (int64_t)batch * h->n_vox, (hipStream_t)stream));
+        return PSF_OK;
+    }
+    if (!y || !ws) return PSF_EINVAL;
     if (h->mode3d)
         return project_adj_3d(h, table, opts, y, 0, batch, events, n_events, x, grad ? xt : nullptr, grad, ws,
                               ws_bytes, (hipStream_t)stream);

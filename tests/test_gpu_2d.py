@@ -322,3 +322,28 @@ def test_listmode_bad_event_reported(torch):
         sc.check()
     assert e.value.code == -1
     assert q[0, 1].item() == 0.0 and q[0, 2].item() == 0.0
+
+
+def test_degenerate_inputs(torch, oracle, ref1):
+    """An empty voxel range, an all-zero image, a batch of 10 images, and an
+    empty event list."""
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=1e-6, vox_begin=5, vox_end=5)
+    assert rp.cpu().tolist() == [0] and col.numel() == 0 and val.numel() == 0
+    z = torch.zeros(2, sc.n_voxels, device="cuda")
+    assert int((sc.project_fwd(t, z) != 0).sum().item()) == 0
+    x = S.phantom_uniform(CFG, seed=21, batch=10)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo = oracle.project_fwd(cols, x.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    yc = yo.astype(np.float32)
+    xb = sc.project_adj(t, torch.tensor(yc, device="cuda")).cpu().numpy()
+    xbo = oracle.project_adj(cols, yc.astype(np.float64))
+    np.testing.assert_allclose(xb, xbo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xbo).max())
+    ev = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    q = sc.project_fwd(t, torch.tensor(x[:2], dtype=torch.float32, device="cuda"), events=ev)
+    assert tuple(q.shape) == (2, 0)
+    xe = sc.project_adj(t, torch.zeros(2, 0, device="cuda"), events=ev)
+    assert tuple(xe.shape) == (2, sc.n_voxels) and int((xe != 0).sum().item()) == 0

@@ -444,3 +444,30 @@ def test_bench_workload_table_grad_and_listmode(torch):
     hist = torch.zeros(sc.n_bins, dtype=torch.float64, device="cuda").index_add_(0, bt, w.double())
     xh = sc.project_adj(t, hist.float()[None])[0]
     np.testing.assert_allclose(xl.cpu().numpy(), xh.cpu().numpy(), rtol=RTOL, atol=RTOL * 1e-2 * float(xh.abs().max()))
+
+
+def test_degenerate_inputs(torch, oracle, small_ref):
+    """An empty voxel range, an all-zero image, a batch of 10 images (a chunk of
+    8 and one of 2), and an empty event list."""
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=5, vox_end=5)
+    assert rp.cpu().tolist() == [0] and col.numel() == 0 and val.numel() == 0
+    z = torch.zeros(2, sc.n_voxels, device="cuda")
+    assert int((sc.project_fwd(t, z) != 0).sum().item()) == 0
+    A_T = _sparse(cols, sc.n_bins)
+    x = S.phantom_uniform(SMALL, seed=21, batch=10)
+    xf = x.astype(np.float32).astype(np.float64)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo = (A_T.T @ xf.T).T
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    yc = yo.astype(np.float32)
+    xb = sc.project_adj(t, torch.tensor(yc, device="cuda")).cpu().numpy()
+    xbo = (A_T @ yc.astype(np.float64).T).T
+    np.testing.assert_allclose(xb, xbo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(xbo).max())
+    ev = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    q = sc.project_fwd(t, torch.tensor(x[:2], dtype=torch.float32, device="cuda"), events=ev)
+    assert tuple(q.shape) == (2, 0)
+    xe = sc.project_adj(t, torch.zeros(2, 0, device="cuda"), events=ev)
+    assert tuple(xe.shape) == (2, sc.n_voxels) and int((xe != 0).sum().item()) == 0
