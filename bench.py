@@ -369,9 +369,17 @@ def cpu_baseline(cfg, meta, x_np, thr):
         cols, _ = O.columns_3d(cfg, tab, vox, cap=1 << 21, nthreads=nthreads)
         t1 = time.perf_counter()
         nnz = sum(len(b) for b, _ in cols)
+        # one thread, two of the same voxels
+        v1 = vox[[len(vox) // 3, 2 * len(vox) // 3]]
+        t2 = time.perf_counter()
+        cols1, _ = O.columns_3d(cfg, tab, v1, cap=1 << 21, nthreads=1)
+        t3 = time.perf_counter()
+        nnz1 = sum(len(b) for b, _ in cols1)
         return {"value": nnz / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
                 "sample": f"{len(vox)} voxels spread over the 16^3 sub-volume: FP64 sparse columns "
-                          f"(table build of {t_tab:.1f} s not counted)", "seconds": t1 - t0}
+                          f"(table build of {t_tab:.1f} s not counted)", "seconds": t1 - t0,
+                "single_thread": {"value": nnz1 / (t3 - t2), "unit": "elements/s", "voxels": len(v1),
+                                  "seconds": t3 - t2}}
     t0 = time.perf_counter()
     tab = O.table_2d(cfg)
     cols, _ = O.columns_2d(cfg, tab, np.arange(cfg["nx"] * cfg["ny"]), nthreads=nthreads)
