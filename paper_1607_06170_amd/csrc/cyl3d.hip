@@ -114,27 +114,27 @@ __device__ __forceinline__ int64_t diag_index(int ri, int rj, int NR) {
     return (int64_t)NR * (NR - 1) / 2 + (int64_t)k * NR - (int64_t)k * (k - 1) / 2 + ri;
 }
 
-// to_user: user[b] (+)= diag[...]; else diag[...] = user[b]; nb images of nbins
-__global__ void k_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate) {
-    const int64_t nrr = (int64_t)NR * NR;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nbins * nb;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i / nbins, u = i - b * nbins;
-        const int64_t tb = u / nrr, rr = u - tb * nrr;
-        const int ri = (int)(rr / NR), rj = (int)(rr - (int64_t)ri * NR);
-        const int64_t di = b * nbins + tb * nrr + diag_index(ri, rj, NR);
-        if (to_user) dst[i] = accumulate ? dst[i] + src[di] : src[di];
-        else dst[di] = src[i];
+// to_user: user[b] (+)= diag[...]; else diag[...] = user[b].  One workgroup per
+// (image, transaxial bin): its NR^2 ring pairs, user order r_i NR + r_j on one
+// side, the diagonal order on the other, both inside the bin's NR^2 floats.
+__global__ void __launch_bounds__(256) k_diag_perm(const float* src, float* dst, int NR, int to_user, int accumulate) {
+    const int nrr = NR * NR;
+    const int64_t base = (int64_t)blockIdx.x * nrr;  // blockIdx.x = image * transaxial bins + bin
+    for (int rr = threadIdx.x; rr < nrr; rr += blockDim.x) {
+        const int ri = rr / NR, rj = rr - ri * NR;
+        const int64_t u = base + rr, d = base + diag32(ri, rj, NR);
+        if (to_user) dst[u] = accumulate ? dst[u] + src[d] : src[d];
+        else dst[d] = src[u];
     }
 }
 
 hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR, int nb, int to_user, int accumulate,
                             hipStream_t st) {
-    const int64_t n = nbins * nb;
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_diag_perm, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, src, dst,
-                       nbins, NR, nb, to_user, accumulate);
+    const int64_t nrr = (int64_t)NR * NR;
+    const int64_t blocks = nbins / nrr * nb;  // the sinogram holds whole transaxial bins of NR^2 ring pairs
+    if (blocks <= 0) return hipSuccess;
+    if (blocks * nrr != nbins * nb || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_diag_perm, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, NR, to_user, accumulate);
     return hipGetLastError();
 }
 
