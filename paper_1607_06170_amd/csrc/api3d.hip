@@ -129,7 +129,9 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     L.bandc = off;
     off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
     L.chunks = off;
-    L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR);
+    // chunks of a row: over member rows (slot, r_i), or over a column group's
+    // accumulator rows (slot, i < NR + s_max), whichever are more
+    L.max_chunks = cyl3d_max_chunks(L.cap_slots, (int)NR + kShareCsr - 1);
     off += align256(sizeof(int) * (size_t)L.bcsr * L.max_chunks);
     {
         L.per_vox = Nc * NR * 2 < kRecsPerVoxel ? (Nc * NR * 2 > 1024 ? Nc * NR * 2 : 1024) : kRecsPerVoxel;

@@ -2136,6 +2136,196 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     }
 }
 
+// The count phase with staging, one workgroup per (chunk, column group): the
+// group's n members (n <= 8) are interleaved in the accumulators, member s of
+// cell (slot k, i, j) at ((k (NR + n - 1) + i)(NR + n - 1) + j) n + s, so the
+// workgroup reads and clears each cell's n floats together.  A cell's band row
+// and column range are the same for every member (the bands are kept relative
+// to the reference voxel); member s owns cell (i, j) as ring pair
+// (i + s - n + 1, j + s - n + 1) when both rings are inside the scanner, and its
+// bin is the cell's plus s (NR + 1).  Each member's entries come out in its
+// bin order, as in the member-by-member kernel, into its own stage region.
+// Chunks are kRowsC accumulator rows (slot, i) of the group.
+__global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratch3D S, Args3D A) {
+    __shared__ int wave_tot[8][kBlockC / 64];
+    __shared__ int64_t s_base[8];
+    __shared__ int s_run[8];
+    __shared__ int rlo[kRowsC], rpre[kRowsC + 1], wave_len[kBlockC / 64];
+    __shared__ int rcell[kRowsC], rbin[kRowsC];  // a row's cell (j = 0), its bin for member 0 at j = n - 1
+    __shared__ unsigned short rowof[kMapC];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kBlockC / 64;
+    const int grp = blockIdx.y;  // the member index of the group's first voxel
+    const int4 me = A.mem[grp];
+    if (me.y != 0) return;  // not the first voxel of its column group
+    const int vb = me.z;
+    const int NR = G.NR;
+    const int nzc = A.cls[vb].w + 1, c = nzc - 1, NRr = NR + c;
+    const int nsl = S.n_slots[grp];
+    const int64_t nrows = (int64_t)nsl * NRr;
+    const int64_t chunk = blockIdx.x;
+    const int64_t q0 = chunk * kRowsC;
+    if (chunk == 0 && tid < nzc) A.stage_nch[A.mem[grp + tid].w] = (int)((nrows + kRowsC - 1) / kRowsC);
+    if (q0 >= nrows) return;
+    const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
+    float* dense = S.dense + (int64_t)grp * S.dense_slab;
+    const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+    const int* order = S.slot_order + (int64_t)grp * S.cap_slots;
+    const int64_t bref = (int64_t)A.cls[vb].y * S.cap_slots * S.band_rows;
+    const bool mh = (A.sym[vb] & 0x100) && (((grp - A.cls[vb].y) / nzc) & 1);
+    const int C = NR - 1 - c;
+    int tot_s[8];  // the chunk's cells of each member (its stage reservation)
+    {
+        const int r = tid;  // kRowsC == kBlockC
+        int lo = 0, len = 0;
+        int ls[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) ls[s] = 0;
+        if (r < nq) {
+            const int q = (int)(q0 + r);
+            const int slot = q / NRr, i = q - slot * NRr;
+            const int ov = order[slot];
+            rcell[r] = ((ov & 0x3fffffff) * NRr + i) * NRr * nzc;
+            rbin[r] = stb[slot] * (NR * NR) + (i - c) * NR - c;
+            const int brow = mh ? NR + nzc - i : i + 2;
+            const int2 b = ((ov & 0x40000000) ? S.bandc : S.band)[bref + (int64_t)(ov & 0x3fffffff) * S.band_rows + brow];
+            if (b.x <= b.y) {  // else the row was never reached
+                const int l = max(mh ? C - b.y + c : b.x + c, 0), h = min(mh ? C - b.x + c : b.y + c, NRr - 1);
+                if (l <= h) {
+                    lo = l;
+                    len = h - l + 1;
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        // member s: rows and columns c - s .. NR - 1 + c - s
+                        if (s < nzc && i >= c - s && i <= NR - 1 + c - s) {
+                            const int l2 = max(l, c - s), h2 = min(h, NR - 1 + c - s);
+                            ls[s] = h2 >= l2 ? h2 - l2 + 1 : 0;
+                        }
+                    }
+                }
+            }
+        }
+        // block exclusive scan of the lengths, and each member's total
+        int inc = len;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            int v = ls[s];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) wave_tot[s][wid] = v;
+        }
+        if (lane == 63) wave_len[wid] = inc;
+        __syncthreads();
+        int base = 0, all = 0;
+        for (int w = 0; w < nw; ++w) {
+            base += w < wid ? wave_len[w] : 0;
+            all += wave_len[w];
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            int t = 0;
+            for (int w = 0; w < nw; ++w) t += wave_tot[s][w];
+            tot_s[s] = t;
+        }
+        rlo[r] = lo;
+        rpre[r] = base + inc - len;
+        __syncthreads();
+        if (tid == 0) rpre[kRowsC] = all;
+        __syncthreads();
+    }
+    const int T = rpre[kRowsC];
+    if (T <= kMapC) {
+        for (int i = rpre[tid]; i < rpre[tid + 1]; ++i) rowof[i] = (unsigned short)tid;
+        __syncthreads();
+    }
+    // each member's reservation in its stage region
+    if (tid < nzc) {
+        const int s = tid;
+        int64_t b = -1;
+        int ts = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u == s) ts = tot_s[u];
+        const int64_t row = A.mem[grp + s].w;
+        if (ts > 0) {
+            if (row < A.stage_rows) {
+                const int cnt = atomicAdd(&A.stage_cnt[row], ts);
+                if ((int64_t)cnt + ts <= A.stage_per_row) b = row * A.stage_per_row + cnt;
+            }
+            if (b < 0) atomicOr(A.stage_full, 1);
+        }
+        s_base[s] = b;
+        s_run[s] = 0;
+    }
+    __syncthreads();
+    for (int f0 = 0; f0 < T; f0 += kBlockC) {
+        const int f = f0 + tid;
+        float a[8];
+        unsigned int keep = 0u;
+        int lo = 0, j = 0;
+        if (f < T) {
+            if (T <= kMapC) {
+                lo = rowof[f];
+            } else {
+                int hi = nq - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rpre[mid] <= f) lo = mid;
+                    else hi = mid - 1;
+                }
+            }
+            j = rlo[lo] + (f - rpre[lo]);
+            const int i = (int)((q0 + lo) % NRr);
+            float* cell = dense + rcell[lo] + j * nzc;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                a[s] = 0.0f;
+                if (s < nzc) {
+                    a[s] = cell[s];
+                    cell[s] = 0.0f;  // leave the accumulator clean
+                    const bool ok = i >= c - s && i <= NR - 1 + c - s && j >= c - s && j <= NR - 1 + c - s;
+                    if (ok && a[s] > 0.0f && (double)a[s] >= A.threshold) keep |= 1u << s;
+                }
+            }
+        }
+        int pre[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const unsigned long long m = __ballot((keep >> s) & 1u);
+            pre[s] = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wave_tot[s][wid] = __popcll(m);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            if (!((keep >> s) & 1u)) continue;
+            const int64_t start = s_base[s];
+            if (start < 0) continue;
+            int off = 0;
+            for (int w = 0; w < wid; ++w) off += wave_tot[s][w];
+            const int64_t pos = s_run[s] + off + pre[s];  // below the member's reservation
+            A.stage_col[start + pos] = rbin[lo] + j + s * (NR + 1);
+            A.stage_val[start + pos] = a[s];
+        }
+        __syncthreads();
+        if (tid < nzc) {
+            int t = 0;
+            for (int w = 0; w < nw; ++w) t += wave_tot[tid][w];
+            s_run[tid] += t;
+        }
+        __syncthreads();
+    }
+    if (tid < nzc) {
+        const int64_t row = A.mem[grp + tid].w;
+        const int n = s_run[tid];
+        atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
+        A.stage_cb[row * S.max_chunks + chunk] = s_base[tid];
+        A.stage_cn[row * S.max_chunks + chunk] = n;
+    }
+}
+
 int64_t cyl3d_max_chunks(int cap_slots, int NR) {
     return ((int64_t)cap_slots * NR + kRowsC - 1) / kRowsC;
 }
@@ -2209,7 +2399,7 @@ hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, co
     if (a.n_mem <= 0) return hipSuccess;
     const dim3 grid((unsigned)S.max_chunks, a.n_mem), block(kBlockC);
     if (mode == kModeCount && a.stage) {
-        hipLaunchKernelGGL(k_cyl3d_compact<kCompactStage>, grid, block, 0, st, G, S, a);
+        hipLaunchKernelGGL(k_cyl3d_compact_group, grid, block, 0, st, G, S, a);
         hipLaunchKernelGGL(k_stage_batch, dim3(1), dim3(64), 0, st, a);
     } else if (mode == kModeCount) {
         hipLaunchKernelGGL(k_cyl3d_compact<kCompactCount>, grid, block, 0, st, G, S, a);
