@@ -1928,18 +1928,14 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 // phase: a first pass stores the per-chunk counts, the second writes each
 // chunk at its offset (row start + counts of the chunks before it), in order.
 // The last pass over a chunk clears what it read for the next batch.  Count
-// phase with staging: one pass (kCompactStage below); the fill phase copies
-// each row's chunks in order (k_stage_copy).
+// phase with staging: one pass per column group (k_cyl3d_compact_group
+// below); the fill phase copies each row's chunks in order (k_stage_copy).
 
 constexpr int kBlockC = 512;
 constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
 constexpr int kMapC = 8192;  // flat entries of a chunk mapped to their rows in LDS
 
-// kCompactStage (count phase with staging): one pass; each chunk reserves
-// room for all the cells it reads in its row's stage region (a per-row
-// counter), writes its kept entries there in order, and records (stage
-// offset, count) for the fill phase's copy.
-enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2, kCompactStage = 3 };
+enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
 
 __global__ void k_band_init(Scratch3D S, Args3D A) {
     const int grp = blockIdx.y;  // a member; the first voxel of each class holds the class's bands
@@ -1962,7 +1958,7 @@ hipError_t launch_band_init(const Scratch3D& S, const Args3D& a, hipStream_t st)
 template <int MODE>
 __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ int wave_tot[kBlockC / 64];
-    __shared__ int64_t s_run, s_base;
+    __shared__ int64_t s_run;
     __shared__ int rlo[kRowsC], rpre[kRowsC + 1];
     __shared__ int rbase[kRowsC], rbin[kRowsC];  // a row's cells: dense[rbase + col * nzc], bin rbin + col
     __shared__ unsigned short rowof[kMapC];      // the row of each flat entry, when the chunk has at most kMapC
@@ -1977,7 +1973,6 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int nsl = S.n_slots[grp];
     const int64_t nrows = (int64_t)nsl * NR;
     const int64_t q0 = chunk * kRowsC;
-    if (MODE == kCompactStage && chunk == 0 && threadIdx.x == 0) A.stage_nch[row] = (int)((nrows + kRowsC - 1) / kRowsC);
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
@@ -2038,22 +2033,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
         __syncthreads();
     }
     int64_t start = 0, cap = 0;
-    if (MODE == kCompactStage) {
-        if (tid == 0) {
-            int64_t b = -1;
-            if (T > 0) {
-                if (row < A.stage_rows) {
-                    const int c = atomicAdd(&A.stage_cnt[row], T);
-                    if ((int64_t)c + T <= A.stage_per_row) b = row * A.stage_per_row + c;
-                }
-                if (b < 0) atomicOr(A.stage_full, 1);
-            }
-            s_base = b;
-            s_run = 0;
-        }
-        __syncthreads();
-        start = s_base;
-    } else if (MODE == kCompactFill) {
+    if (MODE == kCompactFill) {
         // kept entries of the chunks before this one
         int64_t part = 0;
         for (int64_t c = tid; c < chunk; c += bs) part += ccount[c];
@@ -2104,13 +2084,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             tot += wave_tot[w];
         }
         const int64_t run = s_run;
-        if ((MODE == kCompactFill || (MODE == kCompactStage && start >= 0)) && keep) {
+        if (MODE == kCompactFill && keep) {
             const int64_t pos = run + off + pre;
             const int32_t b = rbin[lo] + col;
-            if (MODE == kCompactStage) {  // pos < T: the chunk's reservation
-                A.stage_col[start + pos] = b;
-                A.stage_val[start + pos] = a;
-            } else if (pos < cap) {
+            if (pos < cap) {
                 A.col[start + pos] = b;
                 A.val[start + pos] = a;
             } else {
@@ -2123,12 +2100,8 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     }
     if (tid == 0) {
         const int64_t n = s_run - run0;
-        if (MODE == kCompactCount || MODE == kCompactStage)
-            atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
-        if (MODE == kCompactStage) {
-            A.stage_cb[row * S.max_chunks + chunk] = start;
-            A.stage_cn[row * S.max_chunks + chunk] = (int)n;
-        } else if (MODE == kCompactChunks) {
+        if (MODE == kCompactCount) atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
+        if (MODE == kCompactChunks) {
             ccount[chunk] = (int)n;
         } else if (MODE == kCompactFill && q0 + nq == nrows && s_run != cap) {
             atomicOr(A.status, kStatOverflow);
