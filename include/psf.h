@@ -118,7 +118,7 @@ typedef struct {
  * skips clearing its accumulators (every build leaves them clear; the last
  * 32 bytes of the workspace header record the handle and layout that did, and
  * the clear is skipped only when they match).  A wrong assertion gives wrong
- * matrices; without the flag every build clears them (about 25 GB). */
+ * matrices; without the flag every build clears them (about 50 GB). */
 #define PSF_OPT_WS_CLEAN 4
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */

@@ -12,7 +12,7 @@ using namespace psf;
 
 namespace {
 
-constexpr int kBatchCsr = 512;    // voxels per batch of the matrix build (dense accumulators, FP32)
+constexpr int kBatchCsr = 1024;   // voxels per batch of the matrix build (dense accumulators, FP32: about 50 GB)
 constexpr int kShareCsr = 8;      // voxels of one column in a class of the matrix build (interleaved accumulators)
 constexpr int kBatchProj = 4096;  // voxels per batch of the projections (fewer, fuller launches)
 constexpr int kClsBatch = 2047;   // classes per batch: a tile record's header holds the class index in 11 bits
