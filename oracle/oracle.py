@@ -125,6 +125,8 @@ def _bind3d(L, G, I, T):
     L.og_columns_3d.argtypes = [G, T, I, _i64p, C.c_int64, C.c_int64, _i64p, _dp, _i64p, _i32p, C.c_int]
     L.og_table_grad_3d.restype = None
     L.og_table_grad_3d.argtypes = [G, T, I, _i64p, _dp, C.c_int64, _i64p, _dp, C.c_int64, _dp, C.c_int]
+    L.og3_set_full_ring_scan.restype = None
+    L.og3_set_full_ring_scan.argtypes = [C.c_int]
     L.og_w3_pair.restype = C.c_double
     L.og_w3_pair.argtypes = [G, C.c_int, _dp, C.c_int, C.c_int, C.c_int, C.c_int]
 
@@ -354,6 +356,12 @@ def columns_3d(cfg: dict, tab: TableRef, vox, cap: int = 1 << 20, nthreads: int 
         assert n <= cap, "column capacity exceeded"
         out.append((bins[k * cap:k * cap + n].copy(), vals[k * cap:k * cap + n].copy()))
     return out, flags
+
+
+def set_full_ring_scan(on: bool) -> None:
+    """Test switch: the 3D columns pair every ring with every ring instead of
+    the rings their lines can reach (the window's pin)."""
+    lib().og3_set_full_ring_scan(int(bool(on)))
 
 
 def table_grad_3d(cfg: dict, tab: TableRef, vox, xv, gy_bins, gy_vals, nthreads: int = 0):

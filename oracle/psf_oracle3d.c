@@ -243,6 +243,10 @@ void og_table3_rows(const og_geom* G, int P, double step_deg, const int32_t* row
 /* ------------------------------------------------------------------ */
 
 static int n_rings(const og_geom* G) { return G->n_cz * G->n_brings; }
+
+/* 1: column3 pairs every ring r1 with every ring r2 (no window); for tests */
+static int g_full_ring_scan = 0;
+void og3_set_full_ring_scan(int on) { g_full_ring_scan = on ? 1 : 0; }
 static double z_first(const og_geom* G) { return -0.5 * n_rings(G) * G->pitch_z; }
 
 static int64_t tab3_index(int nr, int P, int rt, int rz, int pt, int pz, int at, int az) {
@@ -582,11 +586,15 @@ static int column3(const og_geom* G, const og_table* T, const double* c, int64_t
                         }
                     }
                 }
-                /* widen by one ring each way: the extremes over theta are
-                 * within a fraction of a ring of the sampled ones */
+                /* z2 is linear in z1, and monotone in theta over a bundle
+                 * (d2/d1 is proportional to cos(th - phi1) / cos(th - phi2 - pi),
+                 * whose derivative has the sign of sin(phi1 - phi2 - pi) for
+                 * every th), so its extremes are at the sampled ends; one ring
+                 * more each way absorbs rounding.  og3_set_full_ring_scan(1)
+                 * scans every ring instead (the pin of this window). */
                 int r2a = (int)floor((zmin - z0) / lz) - 1, r2b = (int)floor((zmax - z0) / lz) + 1;
-                if (r2a < 0) r2a = 0;
-                if (r2b > NR - 1) r2b = NR - 1;
+                if (r2a < 0 || g_full_ring_scan) r2a = 0;
+                if (r2b > NR - 1 || g_full_ring_scan) r2b = NR - 1;
                 for (int r2 = r2a; r2 <= r2b; r2++) {
                     int any = 0;
                     memset(tile, 0, sizeof(tile));

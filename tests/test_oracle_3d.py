@@ -282,3 +282,30 @@ def test_w3_vs_brute_force_integration(oracle):
                 f = np.where(hi > lo, hi / np.sqrt(1 + hi * hi) - lo / np.sqrt(1 + lo * lo), 0.0)
                 ref = f.sum() * (tb - ta) / n / (2 * np.pi)
                 assert abs(w - ref) <= 1e-7 * max(ref, 1e-12), (vid, a, b, q1, q2, w, ref)
+
+
+@pytest.mark.parametrize("which", ["small", "full"])
+def test_ring_window_drops_nothing(oracle, which):
+    """The 3D columns pair each ring r1 only with the rings r2 that lines
+    through the voxel can reach from r1 (a window from the bundle's end
+    directions).  Scanning every ring instead gives the same columns, bit for
+    bit, on the small scanner and on an off-centre voxel of the 48-ring one."""
+    if which == "small":
+        cfg, nr = S.CFG_3D_SMALL, 91
+        vox = [0, 57, 311, 599]
+        tab = oracle.TableRef(S.random_table((nr, nr, 4, 4, 5, 5), seed=31), nr, 4, 1.0)
+    else:
+        cfg, nr = S.CFG_3D, 61
+        nx, ny = cfg["nx"], cfg["ny"]
+        vox = [(5 * ny + 120) * nx + 9]   # iz = 5 (near an axial end), near a corner column
+        tab = oracle.TableRef(S.random_table((nr, nr, 4, 4, 5, 5), seed=32), nr, 4, 1.0)
+    ref, fr = oracle.columns_3d(cfg, tab, vox, cap=1 << 21)
+    oracle.set_full_ring_scan(True)
+    try:
+        full, ff = oracle.columns_3d(cfg, tab, vox, cap=1 << 21)
+    finally:
+        oracle.set_full_ring_scan(False)
+    assert np.array_equal(fr, ff)
+    for (b0, v0), (b1, v1) in zip(ref, full):
+        assert np.array_equal(b0, b1) and np.array_equal(v0, v1)
+        assert len(b0) > 0
