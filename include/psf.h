@@ -48,7 +48,12 @@ enum {
     PSF_ESIZE = -4,        /* a buffer is too small; the required size is written back */
     PSF_EHIP = -5,         /* a HIP runtime error (see psf_last_hip_error) */
     PSF_EOVERFLOW = -6,    /* fill phase produced more entries than the count phase allotted */
-    PSF_EUNSUPPORTED = -7  /* geometry or option combination this build does not handle */
+    PSF_EUNSUPPORTED = -7, /* geometry or option combination this build does not handle */
+    PSF_ECAPACITY = -8     /* 3D: a voxel's lines exceeded a fixed scratch capacity (more than 4096
+                            * sub-segment pairs or 1024 crystal pairs seen from one voxel, more than
+                            * 16 sub-segment pairs per crystal pair, more than 4096 transaxial bins
+                            * under one image column, or a batch's tile records beyond the record
+                            * buffer); the output is incomplete and must not be used */
 };
 
 /* precision of the tile contraction T = U^T W V (paper Sec 2.2-2.3, Eq.10, 12) */

@@ -20,6 +20,7 @@ PSF_ESIZE = -4
 PSF_EHIP = -5
 PSF_EOVERFLOW = -6
 PSF_EUNSUPPORTED = -7
+PSF_ECAPACITY = -8
 
 PSF_OPT_TABLE_GRAD = 1
 PSF_OPT_STAGE_CSR = 2

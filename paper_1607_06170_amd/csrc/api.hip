@@ -109,6 +109,7 @@ const char* psf_status_string(int s) {
         case PSF_EHIP: return "HIP runtime error";
         case PSF_EOVERFLOW: return "fill phase exceeded the counted row sizes";
         case PSF_EUNSUPPORTED: return "unsupported geometry or options";
+        case PSF_ECAPACITY: return "a fixed scratch capacity was exceeded (output incomplete)";
         default: return "unknown status";
     }
 }
@@ -192,6 +193,7 @@ int read_status(void* ws, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(&s, ws, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (s & kStatOverflow) return PSF_EOVERFLOW;
+    if (s & kStatScratch) return PSF_ECAPACITY;
     if (s & kStatRange) return PSF_ERANGE;
     if (s & kStatGeom) return PSF_EGEOM;
     if (s & kStatEventBad) return PSF_EINVAL;

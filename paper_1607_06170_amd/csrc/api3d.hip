@@ -686,9 +686,10 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
         const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
         HIP_TRY(launch_lm_gather(nullptr, y32, h->n_bins, events, n_events, batch, G.Nc, NR, y, o->accumulate,
                                  (int*)ws, s));
-        return PSF_OK;
+        return read_status(ws, s);
     }
-    return fwd3_all(h, G, S, L, x, batch, y, o->accumulate, ws, s);
+    if ((st = fwd3_all(h, G, S, L, x, batch, y, o->accumulate, ws, s))) return st;
+    return read_status(ws, s);  // blocks: a capacity or range flag means y is incomplete
 }
 
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
@@ -722,7 +723,7 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
     if ((st = adj3_all(h, G, S, L, ybins, ones, batch, x64, xt, g64, ws, s))) return st;
     HIP_TRY(launch_finalize(x64, x, (int64_t)batch * h->n_vox, ones ? 0 : o->accumulate, s));
     if (grad) HIP_TRY(launch_finalize(g64, grad, L.table_elems, 1, s));
-    return PSF_OK;
+    return read_status(ws, s);  // blocks: a capacity or range flag means x is incomplete
 }
 
 int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
@@ -750,5 +751,5 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
     if ((st = adj3_all(h, G, S, L, h32, 0, 1, x64, nullptr, nullptr, ws, s))) return st;
     HIP_TRY(launch_finalize(x64, back, h->n_vox, 0, s));
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
-    return PSF_OK;
+    return read_status(ws, s);
 }

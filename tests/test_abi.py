@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_status_strings():
     L = _lib.load()
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert L.psf_status_string(code)
     assert L.psf_status_string(-99) == b"unknown status"
 

@@ -471,3 +471,30 @@ def test_degenerate_inputs(torch, oracle, small_ref):
     assert tuple(q.shape) == (2, 0)
     xe = sc.project_adj(t, torch.zeros(2, 0, device="cuda"), events=ev)
     assert tuple(xe.shape) == (2, sc.n_voxels) and int((xe != 0).sum().item()) == 0
+
+
+def test_capacity_exceeded_is_an_error(torch):
+    """A ring of 1280 crystals (80 blocks of 16, nearly no gaps) shows a voxel
+    more than 4096 transaxial sub-segment pairs and 1024 crystal pairs, beyond
+    the per-class scratch of the 3D kernels.  The kernels drop that class and
+    exit normally with the capacity flag set; every 3D entry point must then
+    return PSF_ECAPACITY instead of an incomplete result."""
+    import math
+
+    from paper_1607_06170_amd import PsfError, _lib
+    cfg = dict(CFG3, n_blocks=80, n_ct=16, n_cz=1, n_brings=2, r_face=16.0 / math.tan(math.pi / 80) + 0.5,
+               nx=2, ny=2, nz=2, n_rows=61)
+    sc = _scanner(cfg)
+    t = sc.build_table(61, 4, 1.0)
+    x = torch.ones(1, sc.n_voxels, device="cuda")
+    for call in (lambda: sc.project_fwd(t, x), lambda: sc.project_adj(t, torch.ones(1, sc.n_bins, device="cuda")),
+                 lambda: sc.sensitivity(t), lambda: sc.build_psf_sysmat(t)):
+        with pytest.raises(PsfError) as ei:
+            call()
+        assert ei.value.code == _lib.PSF_ECAPACITY
+    # the same scanner with 40 blocks stays within the scratch and runs
+    ok = dict(cfg, n_blocks=40, r_face=16.0 / math.tan(math.pi / 40) + 0.5)
+    sc2 = _scanner(ok)
+    t2 = sc2.build_table(61, 4, 1.0)
+    y = sc2.project_fwd(t2, torch.ones(1, sc2.n_voxels, device="cuda"))
+    assert float(y.sum()) > 0
