@@ -125,6 +125,16 @@ typedef struct {
  * the clear is skipped only when they match).  A wrong assertion gives wrong
  * matrices; without the flag every build clears them (about 50 GB). */
 #define PSF_OPT_WS_CLEAN 4
+/* psf_opts.flags (build_psf_sysmat): [vox_begin, vox_end) counts positions in
+ * the library's voxel order (psf_voxel_order) instead of linear voxel indices;
+ * CSR row k is then voxel order[vox_begin + k].  In that order the voxels that
+ * share their line bundles and tiles (Sec 2.3 computes each voxel's bundle
+ * separately; a ring shift along z, the square's quarter turns and mirrors and
+ * the axial mirror leave a bundle's tiles unchanged up to a relabelling of the
+ * crystals) lie side by side, so a range of it builds at the rate of a whole
+ * image.  A range may cut a group; its voxels inside the range are then built
+ * one by one.  2D: the order is the linear one. */
+#define PSF_OPT_CLASS_ORDER 8
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
 typedef struct {
@@ -173,6 +183,12 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
  * is for more than about 180 crystal rings. */
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
                      size_t workspace_bytes, psf_csr* csr, void* stream);
+
+/* The voxel order of PSF_OPT_CLASS_ORDER: order_host[k] (host memory,
+ * n_voxels entries) is the linear index of the voxel at position k.  Every
+ * voxel appears once.  The first call on a 3D handle plans the whole image
+ * (tens of milliseconds on the host); the plan is kept in the handle. */
+int psf_voxel_order(psf_handle* h, int64_t* order_host);
 
 /* Forward projection y = A x on the fly, without storing A (paper Table 2's
  * projector).  x_dev: [batch][n_voxels]; y_dev: [batch][n_bins] when

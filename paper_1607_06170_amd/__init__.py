@@ -142,13 +142,25 @@ class Scanner:
         t = torch.as_tensor(data, dtype=torch.float32).reshape(-1).to(self.device).contiguous()
         return Table(t, n_rows, n_sub, step_deg)
 
+    def voxel_order(self):
+        """Linear voxel index of each position of the library's voxel order
+        (psf_voxel_order): numpy int64 [n_voxels]."""
+        import numpy as np
+        out = np.zeros(self.n_voxels, dtype=np.int64)
+        check(self.L.psf_voxel_order(self.h, C.c_void_p(out.ctypes.data)), "psf_voxel_order")
+        return out
+
     def build_psf_sysmat(self, table: Table, threshold: float = 0.0, vox_begin: int = 0, vox_end: int = -1,
-                         precision: int = PSF_FP32, stage: bool = True, counters: list | None = None):
+                         precision: int = PSF_FP32, stage: bool = True, counters: list | None = None,
+                         class_order: bool = False):
         """CSR of A^T for voxels [vox_begin, vox_end): (row_ptr int64, col int32, val float32).
         stage: the count phase keeps its rows in the workspace for the fill phase (3D).
-        counters: if a list, each phase appends its header_counters() snapshot (3D)."""
+        counters: if a list, each phase appends its header_counters() snapshot (3D).
+        class_order: the range counts positions of voxel_order() (row k is voxel
+        voxel_order()[vox_begin + k])."""
         torch = _torch()
-        o = self.opts(precision, threshold, vox_begin, vox_end, flags=_lib.PSF_OPT_STAGE_CSR if stage else 0)
+        flags = (_lib.PSF_OPT_STAGE_CSR if stage else 0) | (_lib.PSF_OPT_CLASS_ORDER if class_order else 0)
+        o = self.opts(precision, threshold, vox_begin, vox_end, flags=flags)
         ve = self.n_voxels if vox_end is None or vox_end < 0 else vox_end
         n = ve - vox_begin
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=self.device)

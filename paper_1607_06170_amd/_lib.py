@@ -25,6 +25,7 @@ PSF_ECAPACITY = -8
 PSF_OPT_TABLE_GRAD = 1
 PSF_OPT_STAGE_CSR = 2
 PSF_OPT_WS_CLEAN = 4
+PSF_OPT_CLASS_ORDER = 8
 
 PSF_FP32 = 0
 PSF_BF16 = 1
@@ -77,6 +78,7 @@ SIGNATURES = {
     "psf_sensitivity": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, _P, C.c_size_t, _P]),
     "psf_lm_osem_update": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int64, C.c_float, _P,
                                      C.c_int32, _P, _P, _P, C.c_size_t, _P]),
+    "psf_voxel_order": (C.c_int, [_H, _P]),
     "psf_check": (C.c_int, [_H, _P, _P]),
     "psf_profile": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_void_p]),
     "psf_status_string": (C.c_char_p, [C.c_int]),

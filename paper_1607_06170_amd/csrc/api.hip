@@ -518,6 +518,15 @@ int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches) {
     return st;
 }
 
+int psf_voxel_order(psf_handle* h, int64_t* order) {
+    if (!h || !order) return PSF_EINVAL;
+    if (!h->mode3d) {
+        for (int64_t k = 0; k < h->n_vox; ++k) order[k] = k;
+        return PSF_OK;
+    }
+    return voxel_order_3d(h, order);
+}
+
 int psf_check(psf_handle* h, void* ws, void* stream) {
     if (!h || !ws) return PSF_EINVAL;
     return read_status(ws, (hipStream_t)stream);

@@ -416,6 +416,84 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
     return pl;
 }
 
+// The classes of a whole-image build plan, in order (cached in the handle):
+// position k of the class order is voxel order.mem[k].x.
+const ClassOrderCache& class_order(psf_handle* h, const Ws3& L) {
+    ClassOrderCache& C = h->order;
+    const int64_t key[3] = {L.bcsr, L.cap_recs, L.cap_uv_rings};
+    if (C.valid && C.key[0] == key[0] && C.key[1] == key[1] && C.key[2] == key[2]) return C;
+    const Plan3 all = plan3(h, L, 0, h->n_vox, L.bcsr, true, kShareCsr, true);
+    C.cls.clear();
+    C.sym.clear();
+    C.first.clear();
+    C.mem.clear();
+    C.mem.reserve(all.mem.size());
+    for (const Batch3& b : all.batches)
+        for (int c = 0; c < b.ncls; ++c) {
+            const int4 cl = all.cls[b.cls0 + c];
+            C.cls.push_back(cl);
+            C.sym.push_back(all.sym[b.cls0 + c]);
+            C.first.push_back((int64_t)C.mem.size());
+            for (int i = 0; i < cl.z; ++i) {
+                const int4 m = all.mem[b.mem0 + cl.y + i];
+                C.mem.push_back(make_int2(m.x, m.y));
+            }
+        }
+    for (int i = 0; i < 3; ++i) C.key[i] = key[i];
+    C.valid = true;
+    return C;
+}
+
+// Build plan for positions [vb, ve) of the class order: classes inside the
+// range whole, and the members of a class the range cuts as classes of one
+// voxel each.  CSR row = position - vb.
+Plan3 plan3_order(psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax) {
+    const ClassOrderCache& C = class_order(h, L);
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
+    Plan3 pl;
+    Batch3 cur = {0, 0, 0, 0, 0};
+    int64_t cur_recs = 0;
+    // a class of n members (voxel, shift) at positions p0.. (rows p - vb); nzc voxels per column
+    auto push = [&](int v0, int n, int nzc, int sym, const int2* mm, int64_t p0) {
+        const int64_t need = class_recs(L, NR, nzc), uv = Nc * (NR + nzc - 1);
+        if (cur.nmem > 0 && (cur.nmem + n > bmax || cur.ncls + 1 > kClsBatch || cur_recs + need > L.cap_recs ||
+                             cur.uv_slots + uv > L.cap_uv)) {
+            pl.batches.push_back(cur);
+            cur = {(int)pl.cls.size(), 0, (int)pl.mem.size(), 0, 0};
+            cur_recs = 0;
+        }
+        pl.cls.push_back(make_int4(v0, cur.nmem, n, nzc - 1));
+        pl.uvoff.push_back((int)cur.uv_slots);
+        pl.sym.push_back(sym);
+        for (int i = 0; i < n; ++i) pl.mem.push_back(make_int4(mm[i].x, mm[i].y, cur.ncls, (int)(p0 + i - vb)));
+        cur.uv_slots += uv;
+        cur.ncls += 1;
+        cur.nmem += n;
+        cur_recs += need;
+    };
+    // the first class that reaches past vb
+    int64_t lo = 0, hi = (int64_t)C.first.size();
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (C.first[mid] + C.cls[mid].z <= vb) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int64_t c = lo; c < (int64_t)C.first.size() && C.first[c] < ve; ++c) {
+        const int64_t f = C.first[c], n = C.cls[c].z;
+        if (f >= vb && f + n <= ve) {
+            push(C.cls[c].x, (int)n, C.sym[c] & 0xff, C.sym[c], &C.mem[f], f);
+        } else {
+            for (int64_t k = f > vb ? f : vb; k < f + n && k < ve; ++k) {
+                const int2 one = make_int2(C.mem[k].x, 0);
+                push(one.x, 1, 1, 1, &one, k);
+            }
+        }
+    }
+    if (cur.nmem > 0) pl.batches.push_back(cur);
+    return pl;
+}
+
 struct PlanDev {
     const int4 *cls, *mem;
     const int *uvoff, *sym;
@@ -565,7 +643,8 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int phase_fill = csr->col != nullptr;
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
-    const Plan3 pl = plan3(h, L, vb, ve, L.bcsr, true, kShareCsr, true);
+    const Plan3 pl = (o->flags & PSF_OPT_CLASS_ORDER) ? plan3_order(h, L, vb, ve, L.bcsr)
+                                                       : plan3(h, L, vb, ve, L.bcsr, true, kShareCsr, true);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;
@@ -752,4 +831,17 @@ int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32
     HIP_TRY(launch_finalize(x64, back, h->n_vox, 0, s));
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
     return read_status(ws, s);
+}
+
+int voxel_order_3d(psf_handle* h, int64_t* order) {
+    // the plan's limits do not depend on the table beyond its presence
+    psf_table t;
+    memset(&t, 0, sizeof(t));
+    t.n_rows = 1;
+    t.n_sub = 4;
+    const Ws3 L = ws3_layout(h, &t, 1, 0, 0, 0);
+    const ClassOrderCache& C = class_order(h, L);
+    if ((int64_t)C.mem.size() != h->n_vox) return PSF_EINVAL;
+    for (int64_t k = 0; k < h->n_vox; ++k) order[k] = C.mem[k].x;
+    return PSF_OK;
 }

@@ -8,7 +8,20 @@
 
 #include "common.hpp"
 
+// The 3D build's voxels in class order (voxels that share tiles side by side):
+// the classes of a whole-image plan, each with its first position and its
+// members (voxel, ring shift), in order.  Computed once per handle.
+struct ClassOrderCache {
+    bool valid = false;
+    int64_t key[3] = {0, 0, 0};     // the plan's limits it was made with
+    std::vector<int4> cls;          // reference voxel, -, member count, largest shift
+    std::vector<int> sym;           // the class's symmetry word
+    std::vector<int64_t> first;     // position of the class's first member
+    std::vector<int2> mem;          // by position: voxel, ring shift
+};
+
 struct psf_handle {
+    ClassOrderCache order;
     psf_geometry g;
     psf_image im;
     int mode3d;
@@ -74,6 +87,7 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
                    const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
                    size_t ws_bytes, hipStream_t s);
+int voxel_order_3d(psf_handle* h, int64_t* order);
 int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
                float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
                size_t ws_bytes, hipStream_t s);

@@ -103,6 +103,21 @@ def test_sysmat_small_ranges(torch, oracle, small_ref, vb, ve):
     _check_rows(oracle, rp, col, val, cols, flags, np.arange(vb, ve))
 
 
+def test_sysmat_class_order(torch, oracle, small_ref):
+    """Ranges of the library's voxel order (voxels sharing tiles side by side):
+    the order lists every voxel once, and two ranges that cut a group of
+    sharing voxels build each voxel's row as the oracle does."""
+    td, cols, flags = small_ref
+    sc = _scanner(SMALL)
+    t = sc.table_from(td, SMALL["n_rows"], 4, 1.0)
+    order = sc.voxel_order()
+    n = sc.n_voxels
+    assert np.array_equal(np.sort(order), np.arange(n))
+    for vb, ve in ((0, 301), (301, n), (17, 19)):
+        rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, vox_begin=vb, vox_end=ve, class_order=True)
+        _check_rows(oracle, rp, col, val, cols, flags, order[vb:ve])
+
+
 def test_sysmat_staging_paths(torch, oracle, small_ref):
     """The fill phase copies what the count phase staged; without staging, or
     when another call used the workspace in between, it recomputes: the three
