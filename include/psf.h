@@ -199,6 +199,20 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
                 const int32_t* events_dev, int64_t n_events, float* y_dev, void* workspace_dev,
                 size_t workspace_bytes, void* stream);
 
+/* project_fwd for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation on a 2D handle, with its scratch (a status word and the
+ * FP64 bin accumulator, 256 + 8 * batch * n_bins bytes) in a 16 MiB device
+ * array the library owns instead of a workspace; the caller passes inputs and
+ * outputs only.  No hipMalloc, hipFree or other allocation happens in the call.
+ * PSF_ESIZE if the scratch would exceed 16 MiB (at most 258 images of the
+ * 128-crystal ring); PSF_EUNSUPPORTED on a 3D handle.  Each GPU has one such
+ * array, shared by every call on it: calls that overlap on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the
+ * caller.  Status flags of the call (psf_check) are not kept. */
+int project_fwd_noalloc(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x_dev,
+                        int32_t batch, const int32_t* events_dev, int64_t n_events, float* y_dev, void* stream);
+
 /* Back projection x = A^T y (layouts as project_fwd; an empty event list
  * gives x = 0, or leaves x as it is with opts->accumulate, and y_dev may then
  * be NULL).  If grad_table_dev is

@@ -73,6 +73,8 @@ SIGNATURES = {
                                    C.POINTER(psf_csr), _P]),
     "project_fwd": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int32, _P, C.c_int64, _P, _P,
                               C.c_size_t, _P]),
+    "project_fwd_noalloc": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int32, _P, C.c_int64,
+                                      _P, _P]),
     "project_adj": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int32, _P, C.c_int64, _P, _P,
                               _P, _P, C.c_size_t, _P]),
     "psf_sensitivity": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, _P, C.c_size_t, _P]),

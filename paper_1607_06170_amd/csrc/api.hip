@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "api_internal.hpp"
@@ -12,6 +13,32 @@ using namespace psf;
 
 namespace psf {
 thread_local int g_last_hip = 0;
+}
+
+// Scratch of project_fwd_noalloc: the status word and the FP64 bin accumulator
+// of one call, in device memory the library owns.  Each GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives for the device (the array's
+// name is a host-side stand-in).
+constexpr size_t kNoAllocScratch = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// once per device, with that device current
+static int scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return PSF_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return PSF_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        psf::g_last_hip = (int)e;
+        return PSF_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+    return PSF_OK;
 }
 
 
@@ -68,6 +95,7 @@ int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, p
         fr[2 * b + 1] = sin(phi);
     }
     hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess && scratch_init(h->device) != PSF_OK) e = (hipError_t)psf::g_last_hip;
     if (e == hipSuccess) e = hipMalloc((void**)&h->frames_dev, sizeof(double) * 2 * geom->n_blocks);
     if (e == hipSuccess) e = hipMemcpy(h->frames_dev, fr, sizeof(double) * 2 * geom->n_blocks, hipMemcpyHostToDevice);
     free(fr);
@@ -314,7 +342,7 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
 
 // y64[batch][n_bins] = A x (FP64 accumulation), on the fly
 static int fwd_bins(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int batch,
-                    double* y64, void* ws, hipStream_t s) {
+                    double* y64, void* ws, hipStream_t s, bool prof = true) {
     Ring2D G = make_ring2d(h, table, opts);
     int st = check_2d_support(h, G, kModeFwd);
     if (st) return st;
@@ -327,6 +355,10 @@ static int fwd_bins(psf_handle* h, const psf_table* table, const psf_opts* opts,
     a.y64 = y64;
     a.status = (int*)ws;
     HIP_TRY(launch_zero_f64(y64, (int64_t)batch * h->n_bins, s));
+    if (!prof) {  // no timing events (they are created per launch)
+        HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
+        return PSF_OK;
+    }
     {
         ProfScope ps_(h, s);
         HIP_TRY(launch_voxel2d(kModeFwd, G, a, s));
@@ -384,6 +416,32 @@ int project_fwd(psf_handle* h, const psf_table* table, const psf_opts* opts, con
     if ((st = zero_header(ws, s))) return st;
     double* y64 = at<double>(ws, L.y64);
     if ((st = fwd_bins(h, table, opts, x, batch, y64, ws, s))) return st;
+    if (events) {
+        HIP_TRY(launch_lm_gather(y64, nullptr, h->n_bins, events, n_events, batch, h->n_crystals, 1, y,
+                                 opts->accumulate, (int*)ws, s));
+    } else {
+        HIP_TRY(launch_finalize(y64, y, (int64_t)batch * h->n_bins, opts->accumulate, s));
+    }
+    return PSF_OK;
+}
+
+int project_fwd_noalloc(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* x, int32_t batch,
+                        const int32_t* events, int64_t n_events, float* y, void* stream) {
+    if (!h || !x || batch < 1 || n_events < 0) return PSF_EINVAL;
+    if (events && n_events == 0) return PSF_OK;
+    if (!y) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (h->mode3d) return PSF_EUNSUPPORTED;
+    const WsLayout L = ws_layout(h, table, batch, 0);  // header and the FP64 bin accumulator only
+    if (L.g64 > kNoAllocScratch) return PSF_ESIZE;
+    void* ws = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch_dev[h->device] : nullptr;
+    if (!ws) return PSF_EHIP;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    double* y64 = at<double>(ws, L.y64);
+    if ((st = fwd_bins(h, table, opts, x, batch, y64, ws, s, false))) return st;
     if (events) {
         HIP_TRY(launch_lm_gather(y64, nullptr, h->n_bins, events, n_events, batch, h->n_crystals, 1, y,
                                  opts->accumulate, (int*)ws, s));
