@@ -1202,10 +1202,26 @@ struct MmaList {
 // with bit 31 set when the column's image puts photon 2's crystal first.
 // The projections also keep, per list entry, the start of its ring-pair
 // diagonal for both photon orders (see the emission).
+// The forward's emission by runs: a tile's entries grouped by transaxial
+// neighbour pair p and axial diagonal bz - az.  Along such a group the bins of
+// consecutive az lie on one ring-pair diagonal, one ring apart, and so do the
+// class's members of one column and half (one ring shift apart), so the group
+// reaches, for each column and half, one run of consecutive floats of the
+// diagonal sinogram: float u = s + az - az_lo sums the entries' products with
+// the member of shift s.  One atomic add per float of the run.
+constexpr int kFwdGroups = 225;   // 25 transaxial pairs x 9 axial diagonals
+struct MmaFwdRuns {
+    float gt[1152];                 // [group][az + 2]: the tile's entries (1125 used; cleared as float4)
+    float xs[128];                  // [column and half][ring shift]: the members' image values, 0 if the tile misses them
+    unsigned short gl[kFwdGroups + 3];  // groups present in the tile
+    unsigned int gmask[8];
+};
+
 struct MmaLds {
     union {
         MmaOps o;
         MmaList e;
+        MmaFwdRuns f;
     };
     int ptab[200];
     unsigned int dd[640];
@@ -1387,6 +1403,125 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             }
         }
         __builtin_amdgcn_wave_barrier();
+        if constexpr (MODE == kModeFwd) {
+          if (cl.z <= 128) {
+            // the forward: emission by runs (see MmaFwdRuns); the operands are spent
+            const int nhg = cl.z / nzc;  // columns x halves
+            float4* g4 = (float4*)L.f.gt;
+            for (int i = lane; i < 288; i += 64) g4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (lane < 8) L.f.gmask[lane] = 0u;
+            if (imgs) {  // the neighbour pairs seen from every column of the class
+                const int ni = cl.z / (nzc * (mir ? 2 : 1));
+                for (int it = lane; it < 200; it += 64) {
+                    const int pp = it >> 3, ci = it & 7;
+                    if (ci >= ni) continue;
+                    int ga = g1 + pp / 5 - 2, gb = g2 + pp % 5 - 2;
+                    ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                    gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                    int v = 0;
+                    if (ga != gb) {
+                        const int code = sym_code(h7, ci);
+                        const int a = image_crystal(code, ga, G.Nc, G.nc), b = image_crystal(code, gb, G.Nc, G.nc);
+                        v = (a < b ? tbin32(a, b, G.Nc) : tbin32(b, a, G.Nc)) * (G.NR * G.NR) | (a > b ? (int)0x80000000 : 0);
+                    }
+                    L.ptab[it] = v;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            {  // the tile's live entries into their groups
+                const int bt_ = m / 5, bz_ = m % 5 - 2;
+                int gbb = g2 + bt_ - 2;
+                gbb = gbb < 0 ? gbb + G.Nc : (gbb >= G.Nc ? gbb - G.Nc : gbb);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int a = 8 * (j >> 2) + 4 * hk + (j & 3);
+                    if (m >= 25 || a >= 25 || ct[j] == 0.0f) continue;
+                    int ga = g1 + a / 5 - 2;
+                    ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                    if (ga == gbb) continue;
+                    const int az_ = a % 5 - 2;
+                    const int gi = ((a / 5) * 5 + bt_) * 9 + (bz_ - az_ + 4);
+                    L.f.gt[gi * 5 + az_ + 2] = ct[j];
+                    atomicOr(&L.f.gmask[gi >> 5], 1u << (gi & 31));
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < 8) {  // list the present groups
+                const unsigned int w = L.f.gmask[lane];
+                int pre = __popc(w), incl = pre;
+                for (int off = 1; off < 8; off <<= 1) {
+                    const int o = __shfl_up(incl, off, 8);
+                    if (lane >= off) incl += o;
+                }
+                int at = incl - pre;
+                for (unsigned int b = w; b; b &= b - 1) L.f.gl[at++] = (unsigned short)(lane * 32 + __ffs(b) - 1);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int ngr = __builtin_amdgcn_readfirstlane(__popc(L.f.gmask[0]) + __popc(L.f.gmask[1]) + __popc(L.f.gmask[2]) +
+                                                           __popc(L.f.gmask[3]) + __popc(L.f.gmask[4]) + __popc(L.f.gmask[5]) +
+                                                           __popc(L.f.gmask[6]) + __popc(L.f.gmask[7]));
+            const int npair = ngr * nhg;
+            const int NR = G.NR, o = lane & 15;
+            for (int bb = 0; bb < nb; ++bb) {
+                // the members' values by (column and half, ring shift)
+                for (int sm = lane; sm < 128; sm += 64) {
+                    float xv = 0.0f;
+                    bool ok = false;
+                    if (sm < cl.z) {
+                        const int hg = sm / nzc, s2 = sm - hg * nzc;
+                        const bool mh = mir && (hg & 1);
+                        const int sh = mh ? nzc - 1 - s2 : s2;
+                        ok = r1 + sh >= 0 && r1 + sh < NR && r2 + sh >= 0 && r2 + sh < NR;
+                        if (ok) xv = S.xm[(int64_t)(cl.y + sm) * 8 + bb];
+                        L.f.xs[hg * nzc + sh] = xv;
+                    }
+                    if (bb == 0) n_vt += __popcll(__ballot(ok)) * (lane == 0);
+                }
+                __builtin_amdgcn_wave_barrier();
+                float* ob = A.y + (int64_t)bb * G.nbins;
+                for (int base = 0; base < npair; base += 4) {
+                    const int pi = base + (lane >> 4);
+                    if (pi >= npair) continue;
+                    const int gq = pi / nhg, hg = pi - gq * nhg;
+                    const int g = L.f.gl[gq];
+                    const int p = g / 9, dz = g - p * 9 - 4;
+                    const int azlo = dz > 0 ? -2 : -2 - dz, azhi = dz > 0 ? 2 - dz : 2;
+                    if (o >= nzc + azhi - azlo) continue;
+                    const int u = o + azlo;  // ring shift plus az
+                    const int ri = r1 + u, rj = r2 + dz + u;
+                    if ((unsigned)ri >= (unsigned)NR || (unsigned)rj >= (unsigned)NR) continue;
+                    float val = 0.0f;
+                    for (int az = azlo; az <= azhi; ++az) {
+                        const int sh = u - az;
+                        if (sh >= 0 && sh < nzc) val += L.f.gt[g * 5 + az + 2] * L.f.xs[hg * nzc + sh];
+                    }
+                    if (val == 0.0f) continue;
+                    const bool mh = mir && (hg & 1);
+                    int tb;
+                    bool sw;
+                    if (imgs) {
+                        const int v = L.ptab[(p << 3) + (mir ? hg >> 1 : hg)];
+                        sw = v < 0;
+                        tb = v & 0x7fffffff;
+                    } else {
+                        int ga = g1 + p / 5 - 2, gb = g2 + p % 5 - 2;
+                        ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                        gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                        sw = ga > gb;
+                        tb = (sw ? tbin32(gb, ga, G.Nc) : tbin32(ga, gb, G.Nc)) * (NR * NR);
+                    }
+                    int rb = sw ? rj : ri, rc = sw ? ri : rj;  // the bin's rings, photon order of the bin
+                    if (mh) {
+                        rb = NR - 1 - rb;
+                        rc = NR - 1 - rc;
+                    }
+                    atomicAdd(&ob[tb + diag32(rb, rc, NR)], val);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            continue;
+          }
+        }
         // live entries (crystals distinct, inside the 25 x 25 tile, non-zero) and
         // the transaxial part of their bins
         const int bq = m;
