@@ -2,18 +2,22 @@
 """Throughput of the P-SPIR system-matrix hot path on one MI355X.
 
 One step = one pass of the whole path over one synthetic input:
-  build_psf_sysmat (count + fill phases: CSR of A^T over the voxel range),
-  project_fwd (y = A x on the fly) and project_adj (A^T y on the fly).
+  build_psf_sysmat (count + fill phases: CSR of A^T, every voxel of the image;
+  the 3D image is built in ranges of the library's voxel order, each range's
+  CSR overwriting the last), project_fwd (y = A x on the fly) and project_adj
+  (A^T y on the fly).
 Prints ONE JSON line.  ``value`` is system-matrix elements (CSR non-zeros)
 produced per second of the build; the same line carries the forward+adjoint
 projection rate in LORs/s, a roofline object for the dominant kernel (timed
-with HIP events around its launches, on the stream it runs on) and the FP64
+with HIP events around its launches, on the stream it runs on), the error of
+each precision form against the FP64 oracle on sampled voxels, and the FP64
 oracle timed on the host cores.
 
 Workloads (all inputs seeded and synthetic, resident in HBM before timing):
-  cyl3d_sub16  3D scanner of 32 blocks x 12 x 12 crystals (2 x 2 x 15 mm),
-               4 block rings, faces at 130 mm; the central 16 x 16 x 16 voxels
-               (1 mm) of its 128 x 128 x 96 image; analytic 61x61x4x4x5x5 table.
+  cyl3d_full   3D scanner of 32 blocks x 12 x 12 crystals (2 x 2 x 15 mm),
+               4 block rings, faces at 130 mm; the whole 128 x 128 x 96 image
+               (1 mm voxels); analytic 61x61x4x4x5x5 table; all non-zeros kept.
+  cyl3d_sub16  the same scanner, the central 16 x 16 x 16 voxels only.
   ring2d_64    2D ring of 16 blocks x 8 crystals, faces at 65 mm; 64 x 64 image;
                61 x 4 x 5 table; CSR threshold 1e-6.
 """
@@ -31,11 +35,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+T_START = time.perf_counter()
+WALL_BUDGET_S = 520.0        # extras after the timed steps run only while the whole run stays under this
+
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32
-FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64
 FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix cores
 BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
+PREC_NAMES = ["fp32", "bf16", "bf16x2"]
 
 
 def parse():
@@ -43,15 +49,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="cyl3d_sub16", choices=["cyl3d_sub16", "ring2d_64"])
+    ap.add_argument("--workload", default="cyl3d_full", choices=["cyl3d_full", "cyl3d_sub16", "ring2d_64"])
     ap.add_argument("--precision", type=int, default=0, help="0 FP32 plain, 1 BF16, 2 BF16 hi/lo")
+    ap.add_argument("--slab", type=int, default=16384, help="voxels per build range of the full 3D image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-rows", action="store_true",
-                    help="skip the rows timed after the steps (table gradient, list mode, BF16 forms), e.g. under a "
-                         "profiler, so that its kernel mix is the timed step's")
+                    help="skip the rows timed after the steps (table gradient, list mode, precision forms), e.g. "
+                         "under a profiler, so that its kernel mix is the timed step's")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB on the device (a kernel of known traffic, to scale PMC byte counters)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {time.perf_counter() - T_START:7.1f} s  {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_digest():
@@ -85,16 +96,22 @@ def measured_traffic(kernel_file):
 
 def workload(name):
     from paper_1607_06170_amd import synth
+    if name == "cyl3d_full":
+        cfg = dict(synth.CFG_3D)
+        desc = ("3D: 32 blocks x 12x12 LYSO crystals (2x2x15 mm), 4 block rings (48 crystal rings), faces at "
+                "130 mm; the whole 128x128x96 image of 1 mm voxels (1,572,864 voxels); analytic 61x61x4x4x5x5 "
+                "table; all non-zeros kept; matrix built in ranges of the voxel order, each range's CSR "
+                "overwriting the last")
+        return cfg, dict(workload=desc, mode3d=True, full=True, batch=1, steps=2, warmup=1)
     if name == "cyl3d_sub16":
         cfg = dict(synth.CFG_3D, nx=16, ny=16, nz=16)
-        desc = ("3D: 32 blocks x 12x12 LYSO crystals (2x2x15 mm), 4 block rings (48 crystal rings), faces at "
-                "130 mm; central 16x16x16 voxels (1 mm) of the 128x128x96 image; analytic 61x61x4x4x5x5 table; "
-                "all non-zeros kept")
-        return cfg, dict(workload=desc, mode3d=True, batch=1, steps=3, warmup=1)
+        desc = ("3D: the same scanner; the central 16x16x16 voxels (1 mm) of the 128x128x96 image; analytic "
+                "61x61x4x4x5x5 table; all non-zeros kept")
+        return cfg, dict(workload=desc, mode3d=True, full=False, batch=1, steps=3, warmup=1)
     cfg = dict(synth.CFG_2D)
     desc = ("2D ring: 16 blocks x 8 LYSO crystals (2 mm, 15 mm deep), faces at 65 mm; 64x64 image of 1 mm "
             "voxels; 61 x 4 x 5 table; threshold 1e-6")
-    return cfg, dict(workload=desc, mode3d=False, batch=1, steps=20, warmup=3)
+    return cfg, dict(workload=desc, mode3d=False, full=False, batch=1, steps=20, warmup=3)
 
 
 def phantom(cfg, meta):
@@ -102,8 +119,9 @@ def phantom(cfg, meta):
     if meta["mode3d"]:
         full = dict(cfg, nx=128, ny=128, nz=96)
         img = synth.phantom_blobs(full, seed=2).reshape(96, 128, 128)
-        sub = img[40:56, 56:72, 56:72]   # the central 16^3 voxels
-        return np.ascontiguousarray(sub.reshape(1, -1))
+        if not meta["full"]:
+            img = img[40:56, 56:72, 56:72]   # the central 16^3 voxels
+        return np.ascontiguousarray(img.reshape(1, -1))
     return synth.phantom_uniform(cfg, seed=1, batch=meta["batch"])
 
 
@@ -136,11 +154,14 @@ def main():
     prec = args.precision
     ones = torch.ones(1, sc.n_voxels, device=dev)
     lors = int((sc.project_fwd(tab, ones) > 0).sum().item())   # bins with sensitivity > 0
+    del ones
     torch.cuda.synchronize()
+    full = meta["full"]
+    slabs = [(v, min(v + args.slab, sc.n_voxels)) for v in range(0, sc.n_voxels, args.slab)] if full \
+        else [(0, sc.n_voxels)]
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     rec = dict(build=[], fwd=[], adj=[], nnz=0, tiles=0, vtiles=0)
-    last = {}   # the last timed step's outputs
 
     def step(record):
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
@@ -148,7 +169,12 @@ def main():
         # tile counters of each call (each build phase): copied on the device, in stream order, read after
         # the step; a fill phase that copies the rows its count phase staged contracts nothing
         h_build = [] if meta["mode3d"] and record else None
-        rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=prec, counters=h_build)
+        nnz = 0
+        for vb, ve in slabs:
+            rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, vox_begin=vb, vox_end=ve, precision=prec,
+                                               counters=h_build, class_order=full)
+            nnz += int(col.numel())
+            del rp, col, val
         e1.record()
         y = sc.project_fwd(tab, x, precision=prec)
         e2.record()
@@ -165,16 +191,13 @@ def main():
             rec["build"].append(e0.elapsed_time(e1))
             rec["fwd"].append(e1.elapsed_time(e2))
             rec["adj"].append(e2.elapsed_time(e3))
-            rec["nnz"] += int(col.numel())
+            rec["nnz"] += nnz
             rec["tiles"] += t_build + t_fwd + t_adj
             rec["vtiles"] += v_build + v_fwd + v_adj
-            last.update(rp=rp, col=col, val=val, y=y, xb=xb)
-        return xb
+        return y, xb
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    log(f"workload {args.workload}: {sc.n_voxels} voxels, {sc.n_bins} bins; warmup {warmup}, steps {steps}")
+    log(f"workload {args.workload}: {sc.n_voxels} voxels, {sc.n_bins} bins, {len(slabs)} build ranges; "
+        f"warmup {warmup}, steps {steps}")
     for i in range(warmup):
         step(False)
         torch.cuda.synchronize()
@@ -182,9 +205,9 @@ def main():
     torch.cuda.synchronize()
     sc.profile_start()
     t0 = time.perf_counter()
-    xb_last = [None]
+    last = [None, None]
     for i in range(steps):
-        xb_last[0] = step(True)
+        last[:] = step(True)
         log(f"step {i + 1}: build {rec['build'][-1]:.1f} ms, fwd {rec['fwd'][-1]:.1f} ms, adj {rec['adj'][-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -206,35 +229,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ["f32", "bf16", "bf16x2"][prec] + " tiles, f64 geometry and weights",
-        "data": "synthetic (seeded phantom, analytic response table)",
+        "dtype": "f32" if prec == 0 else PREC_NAMES[prec],
+        "data": "synthetic (seeded blob phantom, analytic response table)",
         "config": {"workload": meta["workload"], "voxels": sc.n_voxels, "bins": sc.n_bins,
-                   "batch": meta["batch"], "nnz": nnz, "lors": lors},
+                   "batch": meta["batch"], "nnz": nnz, "lors": lors, "build_ranges": len(slabs)},
         "fwd_adj_lors_per_s": lors * meta["batch"] * steps / proj_s,
         "build_ms": float(np.mean(rec["build"])), "fwd_ms": float(np.mean(rec["fwd"])),
         "adj_ms": float(np.mean(rec["adj"])),
-        "rel_err_vs_fp64": "<= 1e-5 per element, FP32 form (tests/test_gpu_2d.py, tests/test_gpu_3d.py)",
     }
     avg_ms = k_ms / max(k_launches, 1)
     if meta["mode3d"]:
         K = cfg["n_sub"] ** 2
         flops_tile = 2 * (K * K * 25 + 25 * K * 25)   # X = W V, then T = U^T X (unpadded): 32 800 for P = 4
-        # algorithmic units: (voxel, tile) pairs -- the tiles a voxel-by-voxel method contracts; a contracted
-        # tile serves every voxel of its z-column class that sees both its rings
-        vtiles_per_launch = rec["vtiles"] / max(k_launches, 1)
         tiles_per_launch = rec["tiles"] / max(k_launches, 1)
-        achieved = vtiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
+        vtiles_per_launch = rec["vtiles"] / max(k_launches, 1)
         executed = tiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
+        amortised = vtiles_per_launch * flops_tile / (avg_ms * 1e-3) / 1e12
         peak = [FP32_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS, BF16_MATRIX_TFLOPS][prec]
-        traffic = measured_traffic(f"k_cyl3d_mma.{args.workload}.{['fp32', 'bf16', 'bf16x2'][prec]}.pmc.txt")
-        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": traffic,
-                           "kernel": "k_cyl3d_mma (tile contraction T = U^T (W V) on matrix cores, "
-                                     + ["FP32", "BF16", "BF16 hi/lo"][prec] + ", and its emission; all modes)",
-                           "avg_launch_ms": avg_ms, "launches": k_launches,
-                           "voxel_tiles_per_launch": vtiles_per_launch, "flops_per_voxel_tile": flops_tile,
-                           "tiles_contracted_per_launch": tiles_per_launch,
-                           "executed_tflops": executed, "executed_frac": executed / peak}
+        traffic = measured_traffic(f"k_cyl3d_mma.{args.workload}.{PREC_NAMES[prec]}.pmc.txt")
+        out["roofline"] = {
+            "bound": "mfma", "achieved": executed, "peak": peak, "unit": "TFLOP/s", "frac": executed / peak,
+            "traffic": traffic,
+            "kernel": "k_cyl3d_mma (tile contraction T = U^T (W V) on matrix cores, "
+                      + ["FP32", "BF16", "BF16 hi/lo"][prec] + ", and its emission; all modes)",
+            "avg_launch_ms": avg_ms, "launches": k_launches, "flops_per_tile": flops_tile,
+            "tiles_contracted_per_launch": tiles_per_launch,
+            "note": "achieved counts the tiles the kernel contracts; each also serves the other voxels of its "
+                    "symmetry class (below), whose work a voxel-by-voxel method would repeat",
+            "voxel_tiles_per_launch": vtiles_per_launch,
+            "symmetry_amortised_tflops": amortised}
         out["geometry_kernel"] = {"kernel": "k_cyl3d_geom (FP64 homogenization weights and response rows)",
                                   "total_ms_per_step": g_ms / steps, "launches": g_launches,
                                   "contraction_total_ms_per_step": k_ms / steps}
@@ -246,147 +269,309 @@ def main():
                            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                            "kernel": "k_voxel2d (per-voxel sweep, all modes)", "avg_launch_ms": avg_ms,
                            "launches": k_launches}
+    skipped = []
     if meta["mode3d"] and not args.no_extra_rows:
-        out.update(extra_rows_3d(sc, tab, x, xb_last[0], cfg, prec, log))
-        if prec == 0:
-            out["forms"] = forms_rows(sc, tab, x, last, thr, log)
+        per_step = (time.perf_counter() - t0) / max(steps, 1)
+        out.update(extra_rows_3d(sc, tab, x, last[0], last[1], cfg, prec, per_step, skipped))
+    del last
+    vox, loc = _sample_voxels(cfg, meta)
+    gpu = None
+    if not args.no_cpu_baseline:
+        gpu = gpu_samples(sc, tab, cfg, meta, vox)    # the sampled voxels' rows, all forms
+    if meta["mode3d"]:
+        sc._ws = None   # release the workspace before the 16^3 grid's handle takes its own
+        torch.cuda.empty_cache()
+        s16 = None
+        if not args.no_extra_rows or gpu is not None:
+            from paper_1607_06170_amd import Scanner as _S
+            c16, m16 = workload("cyl3d_sub16")
+            s16 = _S(c16, mode3d=True)
+        if not args.no_extra_rows:
+            out["forms"] = forms_rows(s16, skipped)
+        if gpu is not None and loc is not None:
+            gpu.update(gpu_projections_16(s16, loc))
+        del s16
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(cfg, meta, x_np, thr)
+        out["cpu_baseline"], out["rel_err_vs_fp64"] = cpu_baseline(cfg, meta, sc, lors, vox, loc, gpu)
+    if skipped:
+        out["skipped_rows"] = skipped
+    log("done")
     print(json.dumps(out))
 
 
-def extra_rows_3d(sc, tab, x, xt, cfg, prec, log):
+def _left():
+    return WALL_BUDGET_S - (time.perf_counter() - T_START)
+
+
+def extra_rows_3d(sc, tab, x, y, xt, cfg, prec, per_step_s, skipped):
     """The hot path's other two rows on the same workload, each timed once
-    after a warm-up call (outside the timed steps above):
+    after the timed steps:
       - the adjoint with the table gradient d <y, A xt> / d table;
       - one list-mode OSEM subset update of 1e6 events (9e5 drawn from the
-        forward projection of the phantom, 1e5 uniform over the LORs, seeded)."""
+        forward projection of the phantom, 1e5 uniform over the LORs, seeded).
+    Each runs only while the whole run stays within its wall-clock budget."""
     import torch
     ev = lambda: torch.cuda.Event(enable_timing=True)
     res = {}
-    y = sc.project_fwd(tab, x, precision=prec)
-    for _ in range(2):
+    if _left() > 2.0 * per_step_s:
         e0, e1 = ev(), ev()
         e0.record()
         sc.project_adj(tab, y, xt=xt, want_table_grad=True, precision=prec)
         e1.record()
         torch.cuda.synchronize()
-    res["table_grad"] = {"ms": e0.elapsed_time(e1), "table_entries": int(tab.data.numel()),
-                         "what": "x = A^T y and d<y, A xt>/d table, one image"}
-    log(f"adjoint with table gradient: {res['table_grad']['ms']:.1f} ms")
-    # events: bins drawn on the device from the expected counts, then crystal pairs
-    g = torch.Generator(device="cuda").manual_seed(300)
-    w = y[0].double().clamp_min(0)
-    cdf = torch.cumsum(w, 0)
-    n_true, n_rand = 900_000, 100_000
-    trues = torch.searchsorted(cdf, torch.rand(n_true, generator=g, device="cuda", dtype=torch.float64) * cdf[-1])
-    lors = torch.nonzero(w > 0).reshape(-1)
-    rnd = lors[torch.randint(0, lors.numel(), (n_rand,), generator=g, device="cuda")]
-    bins = torch.cat([trues.clamp_max(w.numel() - 1), rnd])
-    bins = bins[torch.randperm(bins.numel(), generator=g, device="cuda")]
-    Nc = cfg["n_blocks"] * cfg["n_ct"]
-    NR = cfg["n_cz"] * cfg["n_brings"]
-    tb, rr = bins // (NR * NR), bins % (NR * NR)
-    starts = torch.tensor([i * Nc - i * (i + 1) // 2 for i in range(Nc)], device="cuda", dtype=torch.int64)
-    gi = torch.searchsorted(starts, tb, right=True) - 1
-    gj = tb - starts[gi] + gi + 1
-    events = torch.stack([(rr // NR) * Nc + gi, (rr % NR) * Nc + gj], 1).to(torch.int32).contiguous()
-    sens = sc.sensitivity(tab, precision=prec)
-    x0 = torch.ones_like(x[0])
-    randoms = 0.1 * float(w.mean())
-    for _ in range(2):
+        res["table_grad"] = {"ms": e0.elapsed_time(e1), "table_entries": int(tab.data.numel()),
+                             "what": "x = A^T y and d<y, A xt>/d table, one image"}
+        log(f"adjoint with table gradient: {res['table_grad']['ms']:.1f} ms")
+    else:
+        skipped.append("table_grad (wall-clock budget)")
+    if _left() > 2.0 * per_step_s:
+        # events: bins drawn on the device from the expected counts, then crystal pairs
+        g = torch.Generator(device="cuda").manual_seed(300)
+        w = y[0].double().clamp_min(0)
+        cdf = torch.cumsum(w, 0)
+        n_true, n_rand = 900_000, 100_000
+        trues = torch.searchsorted(cdf, torch.rand(n_true, generator=g, device="cuda", dtype=torch.float64) * cdf[-1])
+        lors = torch.nonzero(w > 0).reshape(-1)
+        rnd = lors[torch.randint(0, lors.numel(), (n_rand,), generator=g, device="cuda")]
+        bins = torch.cat([trues.clamp_max(w.numel() - 1), rnd])
+        bins = bins[torch.randperm(bins.numel(), generator=g, device="cuda")]
+        del cdf, trues, lors, rnd
+        Nc = cfg["n_blocks"] * cfg["n_ct"]
+        NR = cfg["n_cz"] * cfg["n_brings"]
+        tb, rr = bins // (NR * NR), bins % (NR * NR)
+        starts = torch.tensor([i * Nc - i * (i + 1) // 2 for i in range(Nc)], device="cuda", dtype=torch.int64)
+        gi = torch.searchsorted(starts, tb, right=True) - 1
+        gj = tb - starts[gi] + gi + 1
+        events = torch.stack([(rr // NR) * Nc + gi, (rr % NR) * Nc + gj], 1).to(torch.int32).contiguous()
+        sens = sc.sensitivity(tab, precision=prec)
+        x0 = torch.ones_like(x[0])
+        randoms = 0.1 * float(w.mean())
+        del w
         e0, e1 = ev(), ev()
         e0.record()
         sc.lm_osem_update(tab, events, x0, sens, 10, randoms, precision=prec)
         e1.record()
         torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    res["listmode"] = {"events": int(events.shape[0]), "ms": ms, "events_per_s": events.shape[0] / (ms * 1e-3),
-                       "what": "one LM-OSEM subset update (M = 10), forward rows of the events and their back projection"}
-    log(f"list-mode subset update: {events.shape[0]} events in {ms:.1f} ms")
+        ms = e0.elapsed_time(e1)
+        res["listmode"] = {"events": int(events.shape[0]), "ms": ms, "events_per_s": events.shape[0] / (ms * 1e-3),
+                           "what": "one LM-OSEM subset update (M = 10) of the whole image: forward rows of the "
+                                   "events and their back projection"}
+        log(f"list-mode subset update: {events.shape[0]} events in {ms:.1f} ms")
+    else:
+        skipped.append("listmode (wall-clock budget)")
     return res
 
 
-def forms_rows(sc, tab, x, ref, thr, log):
-    """The BF16 forms of the tile contraction beside the FP32 form, on the same
-    workload and GPU: one step each (matrix build, forward of the phantom,
-    adjoint of the FP32 form's sinogram), timed after a warm-up step, and the
-    results against the FP32 form's (max over elements of |d| / |ref| for the
-    matrix when both have the same pattern; max |d| / max |ref| and the
-    relative 2-norm for the projections)."""
+def forms_rows(sc, skipped):
+    """The three precision forms of the tile contraction on the central
+    16 x 16 x 16 voxels: one step each (matrix build, forward of the phantom,
+    adjoint of the sinogram), timed after a warm-up step; their errors against
+    the FP64 oracle are in rel_err_vs_fp64."""
     import torch
+    if _left() < 30.0:
+        skipped.append("forms (wall-clock budget)")
+        return None
+    c16, m16 = workload("cyl3d_sub16")
+    tab = sc.build_table(c16["n_rows"], c16["n_sub"], c16["step_deg"])
+    x = torch.tensor(phantom(c16, m16), dtype=torch.float32, device="cuda")
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    res = {}
-
-    def rel(a, b):
-        a, b = a.double(), b.double()
-        d = a - b
-        return {"max_rel_to_max": float(d.abs().max() / b.abs().max()),
-                "rel_l2": float(d.norm() / b.norm())}
-
-    for p, name in ((1, "bf16"), (2, "bf16x2")):
+    res = {"workload": "the central 16x16x16 voxels of the 128x128x96 image, one call each"}
+    for p, name in enumerate(PREC_NAMES):
         for _ in range(2):
             e = [ev() for _ in range(4)]
             e[0].record()
-            rp, col, val = sc.build_psf_sysmat(tab, threshold=thr, precision=p)
+            rp, col, val = sc.build_psf_sysmat(tab, threshold=0.0, precision=p)
             e[1].record()
             y = sc.project_fwd(tab, x, precision=p)
             e[2].record()
-            xb = sc.project_adj(tab, ref["y"], precision=p)
+            sc.project_adj(tab, y, precision=p)
             e[3].record()
             torch.cuda.synchronize()
-        r = {"build_ms": e[0].elapsed_time(e[1]), "fwd_ms": e[1].elapsed_time(e[2]),
-             "adj_ms": e[2].elapsed_time(e[3]), "nnz": int(col.numel()),
-             "same_pattern": bool(torch.equal(rp, ref["rp"]) and torch.equal(col, ref["col"]))}
-        if r["same_pattern"]:
-            v32 = ref["val"].double()
-            r["matrix_max_rel_err"] = float(((val.double() - v32).abs() / v32.abs()).max())
-        r["fwd_vs_fp32"] = rel(y, ref["y"])
-        r["adj_vs_fp32"] = rel(xb, ref["xb"])
-        res[name] = r
-        log(f"{name}: build {r['build_ms']:.1f} ms, fwd {r['fwd_ms']:.1f} ms, adj {r['adj_ms']:.1f} ms; "
-            f"matrix max rel err {r.get('matrix_max_rel_err', float('nan')):.2e}, "
-            f"fwd {r['fwd_vs_fp32']['max_rel_to_max']:.2e}, adj {r['adj_vs_fp32']['max_rel_to_max']:.2e} vs FP32")
-        del rp, col, val, y, xb
+        res[name] = {"build_ms": e[0].elapsed_time(e[1]), "fwd_ms": e[1].elapsed_time(e[2]),
+                     "adj_ms": e[2].elapsed_time(e[3]), "nnz": int(col.numel())}
+        log(f"{name} on 16^3: build {res[name]['build_ms']:.1f} ms, fwd {res[name]['fwd_ms']:.1f} ms, "
+            f"adj {res[name]['adj_ms']:.1f} ms")
+        del rp, col, val, y
     return res
 
 
-def cpu_baseline(cfg, meta, x_np, thr):
-    """The FP64 oracle, as it stands, on the host cores."""
+def _sample_voxels(cfg, meta):
+    """Voxels the oracle computes: 12 spread over the image (seeded) and, for the
+    3D scanner, 12 of its central 16^3 voxels (full-image indices)."""
+    rng = np.random.default_rng(7)
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg.get("nz", 1)
+    if not meta["mode3d"]:
+        return np.arange(nx * ny), None
+    if meta["full"]:
+        spread = rng.choice(nx * ny * nz, 12, replace=False)
+        loc = rng.choice(16 ** 3, 12, replace=False)
+        li, lj, lk = loc % 16, (loc // 16) % 16, loc // 256
+        central = ((lk + 40) * ny + lj + 56) * nx + li + 56
+        return np.concatenate([spread, central]).astype(np.int64), loc
+    loc = rng.choice(16 ** 3, 24, replace=False)
+    return loc.astype(np.int64), None
+
+
+def gpu_samples(sc, tab, cfg, meta, vox):
+    """The GPU path's matrix rows of the sampled voxels (each built alone), in
+    every precision form, copied to the host."""
+    res = {}
+    for p, name in enumerate(PREC_NAMES):
+        if meta["mode3d"]:
+            rows = []
+            for v in vox:
+                rp, col, val = sc.build_psf_sysmat(tab, threshold=0.0, vox_begin=int(v), vox_end=int(v) + 1,
+                                                   precision=p)
+                rows.append((col.cpu().numpy().astype(np.int64), val.cpu().numpy().astype(np.float64)))
+            res[name] = {"rows": rows}
+        else:
+            rp, col, val = sc.build_psf_sysmat(tab, threshold=0.0, precision=p)
+            res[name] = {"csr": (rp.cpu().numpy(), col.cpu().numpy().astype(np.int64),
+                                 val.cpu().numpy().astype(np.float64))}
+    return res
+
+
+def _sparse_phantom_16(loc):
+    c16, m16 = workload("cyl3d_sub16")
+    ph = phantom(c16, m16)[0]
+    xs = np.zeros(16 ** 3, np.float32)
+    xs[loc] = ph[loc]
+    return xs
+
+
+def gpu_projections_16(s16, loc):
+    """On the central 16^3 grid: the forward projection of an image non-zero on
+    the sampled central voxels only, and the adjoint of a seeded uniform
+    sinogram at those voxels, in every precision form (host copies)."""
+    import torch
+    c16, _ = workload("cyl3d_sub16")
+    t16 = s16.build_table(c16["n_rows"], c16["n_sub"], c16["step_deg"])
+    xs_d = torch.tensor(_sparse_phantom_16(loc), device="cuda")[None]
+    ysyn = np.random.default_rng(8).random(s16.n_bins, dtype=np.float32)
+    ysyn_d = torch.tensor(ysyn, device="cuda")[None]
+    res = {"proj": {}}
+    for p, name in enumerate(PREC_NAMES):
+        y = s16.project_fwd(t16, xs_d, precision=p)[0]
+        nzb = torch.nonzero(y).reshape(-1)
+        xb = s16.project_adj(t16, ysyn_d, precision=p)[0][torch.tensor(loc, device="cuda")]
+        res["proj"][name] = (nzb.cpu().numpy(), y[nzb].double().cpu().numpy(), xb.double().cpu().numpy())
+    res["ysyn"] = ysyn
+    return res
+
+
+def cpu_baseline(cfg, meta, sc, lors, vox, loc, gpu):
+    """The FP64 oracle, as it stands, on the host cores, on a sample of the
+    workload's voxels (their full matrix columns); and, on the same voxels, the
+    error of each precision form of the GPU path against it:
+      - matrix rows of the sampled voxels (pattern and values);
+      - 3D: on the central 16^3 voxels (their own image grid), the forward
+        projection of an image that is non-zero on the sampled central voxels
+        only (every bin) and the adjoint of a seeded uniform sinogram at those
+        voxels."""
     from oracle import oracle as O
-    nthreads = min(16, os.cpu_count() or 1)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS") or (os.cpu_count() or 1))
     if meta["mode3d"]:
         nr, P = cfg["n_rows"], cfg["n_sub"]
         rt, rz = np.meshgrid(np.arange(nr), np.arange(nr), indexing="ij")
         t0 = time.perf_counter()
-        tab = O.TableRef(O.table3_rows(cfg, rt.ravel(), rz.ravel(), P, cfg["step_deg"], nthreads), nr, P,
-                         cfg["step_deg"])
+        otab = O.TableRef(O.table3_rows(cfg, rt.ravel(), rz.ravel(), P, cfg["step_deg"], nthreads), nr, P,
+                          cfg["step_deg"])
         t_tab = time.perf_counter() - t0
-        print(f"[bench] oracle table: {t_tab:.1f} s", file=sys.stderr, flush=True)
-        vox = np.linspace(0, 16 ** 3 - 1, 2 * nthreads).astype(np.int64)
+        log(f"oracle table: {t_tab:.1f} s")
         t0 = time.perf_counter()
-        cols, _ = O.columns_3d(cfg, tab, vox, cap=1 << 21, nthreads=nthreads)
+        cols, flags = O.columns_3d(cfg, otab, vox, cap=1 << 21, nthreads=nthreads)
         t1 = time.perf_counter()
         nnz = sum(len(b) for b, _ in cols)
-        # one thread, two of the same voxels
-        v1 = vox[[len(vox) // 3, 2 * len(vox) // 3]]
         t2 = time.perf_counter()
-        cols1, _ = O.columns_3d(cfg, tab, v1, cap=1 << 21, nthreads=1)
+        cols1, _ = O.columns_3d(cfg, otab, vox[:1], cap=1 << 21, nthreads=1)
         t3 = time.perf_counter()
-        nnz1 = sum(len(b) for b, _ in cols1)
-        return {"value": nnz / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
-                "sample": f"{len(vox)} voxels spread over the 16^3 sub-volume: FP64 sparse columns "
-                          f"(table build of {t_tab:.1f} s not counted)", "seconds": t1 - t0,
-                "single_thread": {"value": nnz1 / (t3 - t2), "unit": "elements/s", "voxels": len(v1),
-                                  "seconds": t3 - t2}}
-    t0 = time.perf_counter()
-    tab = O.table_2d(cfg)
-    cols, _ = O.columns_2d(cfg, tab, np.arange(cfg["nx"] * cfg["ny"]), nthreads=nthreads)
-    rp, col, val = O.csr_from_columns(cols, thr)
-    t1 = time.perf_counter()
-    return {"value": len(col) / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
-            "sample": "full workload: every voxel's FP64 column and the CSR", "seconds": t1 - t0}
+        nnz1, single_n = len(cols1[0][0]), 1
+        what = ("12 voxels spread over the image and 12 of its central 16^3" if meta["full"]
+                else "24 voxels of the workload")
+    else:
+        t_tab = 0.0
+        t0 = time.perf_counter()
+        otab = O.table_2d(cfg)
+        cols, flags = O.columns_2d(cfg, otab, vox, nthreads=nthreads)
+        t1 = time.perf_counter()
+        nnz = int(((cols > 0) & (cols >= cfg["threshold"])).sum())
+        t2 = time.perf_counter()
+        c1, _ = O.columns_2d(cfg, otab, vox[:64], nthreads=1)
+        t3 = time.perf_counter()
+        nnz1, single_n = int(((c1 > 0) & (c1 >= cfg["threshold"])).sum()), 64
+        what = "every voxel of the workload"
+    t_all = (t1 - t0) * sc.n_voxels / len(vox)    # every voxel's column, extrapolated by voxel count
+    base = {"value": nnz / (t1 - t0), "unit": "elements/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{what}: FP64 matrix columns (oracle table of {t_tab:.1f} s not counted)",
+            "seconds": t1 - t0,
+            "extrapolated_to_workload": {
+                "what": "every voxel's column at the sample's per-voxel cost (forward and adjoint projections "
+                        "and a list-mode update need them all; their products are not counted)",
+                "build_s": t_all, "fwd_adj_lors_per_s": lors / t_all, "listmode_events_per_s": 1e6 / t_all},
+            "single_thread": {"value": nnz1 / (t3 - t2), "unit": "elements/s", "voxels": single_n,
+                              "seconds": t3 - t2}}
+    errs = None
+    if gpu is not None:
+        errs = rel_errors(meta, vox, loc, cols, flags, gpu, O)
+    return base, errs
+
+
+def rel_errors(meta, vox, loc, cols, flags, gpu, O):
+    """Each precision form against the FP64 oracle on the sampled voxels."""
+    res = {}
+    if not meta["mode3d"]:
+        for name in PREC_NAMES:
+            rp, col, val = gpu[name]["csr"]
+            worst = 0.0
+            for v in range(len(rp) - 1):
+                g, gv = col[rp[v]:rp[v + 1]], val[rp[v]:rp[v + 1]]
+                ov = cols[v, g]
+                ok = ov > 0
+                if ok.any():
+                    worst = max(worst, float(np.max(np.abs(gv[ok] - ov[ok]) / ov[ok])))
+            res[name] = {"matrix_max_rel": worst}
+        return res
+    for name in PREC_NAMES:
+        worst, same, n = 0.0, True, 0
+        for k, (g, gv) in enumerate(gpu[name]["rows"]):
+            if flags[k] & O.F_TIES:
+                continue
+            ob, ov = cols[k]
+            n += 1
+            if not np.array_equal(g, ob):
+                same = False
+                continue
+            worst = max(worst, float(np.max(np.abs(gv - ov) / ov)))
+        res[name] = {"matrix_rows": {"voxels": n, "same_pattern": same, "max_rel": worst}}
+    if loc is None or "proj" not in gpu:
+        return res
+    central = cols[len(vox) - len(loc):]
+    xs = _sparse_phantom_16(loc).astype(np.float64)
+    yo = {}
+    for (b, v), xv in zip(central, xs[loc]):
+        for bb, vv in zip(b.tolist(), v.tolist()):
+            yo[bb] = yo.get(bb, 0.0) + vv * xv
+    bins = np.array(sorted(yo), dtype=np.int64)
+    yref = np.array([yo[b] for b in bins])
+    ysyn = gpu["ysyn"].astype(np.float64)
+    xref = np.array([float(np.dot(v, ysyn[b])) for b, v in central])
+    for name in PREC_NAMES:
+        nzb, yv, xb = gpu["proj"][name]
+        ymap = dict(zip(nzb.tolist(), yv.tolist()))
+        yg = np.array([ymap.get(int(b), 0.0) for b in bins])
+        outside = float(sum(abs(v) for b, v in ymap.items() if b not in yo))
+        d = yg - yref
+        res[name]["fwd_sparse_image_16cube"] = {
+            "bins": int(len(bins)), "max_rel_entry": float(np.max(np.abs(d) / yref)),
+            "max_abs_over_max": float(np.abs(d).max() / yref.max()),
+            "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(yref)), "mass_outside_oracle_bins": outside}
+        res[name]["adj_sampled_voxels_16cube"] = {"voxels": int(len(loc)),
+                                                  "max_rel": float(np.max(np.abs(xb - xref) / np.abs(xref)))}
+        log(f"{name} vs FP64: rows {res[name]['matrix_rows']['max_rel']:.2e}, fwd entry "
+            f"{res[name]['fwd_sparse_image_16cube']['max_rel_entry']:.2e}, adj "
+            f"{res[name]['adj_sampled_voxels_16cube']['max_rel']:.2e}")
+    return res
 
 
 if __name__ == "__main__":
