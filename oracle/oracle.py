@@ -262,6 +262,64 @@ def csr_from_columns(cols: np.ndarray, threshold: float):
     return row_ptr, c.astype(np.int32), cols[r, c]
 
 
+def sinogram_view(i, j, n: int):
+    """Sinogram angle of the crystal pair (i, j) of a ring of n crystals (Table 1:
+    a histogram of n/2 angles for n crystals per ring).  Chords with the same
+    i + j (mod n) are parallel on a circular ring; the two parities of i + j
+    interleave in one view: view ((i + j) mod n) // 2."""
+    return ((np.asarray(i) + np.asarray(j)) % n) // 2
+
+
+def truncate_top_n(cols: np.ndarray, n_crystals: int, top_n: int) -> np.ndarray:
+    """Sec 3.3: for every voxel (row of cols, columns = 2D bins) and every
+    sinogram angle, keep the top_n largest bins and drop the others (ties keep
+    the lower bin).  Returns a new dense array."""
+    nb = cols.shape[1]
+    i = np.zeros(nb, np.int64)
+    j = np.zeros(nb, np.int64)
+    for a in range(n_crystals):          # the unordered pairs in bin order
+        lo = a * n_crystals - a * (a + 1) // 2
+        i[lo:lo + n_crystals - a - 1] = a
+        j[lo:lo + n_crystals - a - 1] = np.arange(a + 1, n_crystals)
+    view = sinogram_view(i, j, n_crystals)
+    out = np.zeros_like(cols)
+    for v in range(n_crystals // 2):
+        idx = np.nonzero(view == v)[0]   # ascending bins
+        sub = cols[:, idx]
+        order = np.argsort(-sub, axis=1, kind="stable")[:, :top_n]   # largest first, lower bin first on ties
+        rows = np.arange(cols.shape[0])[:, None]
+        keep = idx[order]
+        out[rows, keep] = cols[rows, keep]
+    return out
+
+
+def subset_mask(n_bins: int, n_crystals: int, n_rings: int, n_subsets: int, subset: int) -> np.ndarray:
+    """Bins of OSEM subset k (Sec 3: OSEM over the sinogram of Table 1): the
+    bins whose sinogram angle v (of their transaxial crystal pair) has
+    v mod n_subsets = k.  Bins: transaxial pair major, then the ring pair."""
+    tb = np.arange(n_bins, dtype=np.int64) // (n_rings * n_rings)
+    starts = np.array([a * n_crystals - a * (a + 1) // 2 for a in range(n_crystals)], dtype=np.int64)
+    gi = np.searchsorted(starts, tb, side="right") - 1
+    gj = tb - starts[gi] + gi + 1
+    return (sinogram_view(gi, gj, n_crystals) % n_subsets == subset).astype(np.float64)
+
+
+def osem_update(cols: np.ndarray, y: np.ndarray, x: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """One OSEM subset update (Sec 3): x <- x / s_k * A^T (m_k y / A x),
+    s_k = A^T m_k; bins with A x = 0 add nothing, voxels with s_k = 0 get 0.
+    cols[voxels, bins] holds A^T."""
+    yhat = cols.T @ x
+    ratio = np.zeros_like(yhat)
+    ok = (mask > 0) & (yhat > 0)
+    ratio[ok] = y[ok] / yhat[ok]
+    back = cols.dot(ratio)
+    sens = cols.dot(mask)
+    out = np.zeros_like(x)
+    nz = sens > 0
+    out[nz] = x[nz] * back[nz] / sens[nz]
+    return out
+
+
 def project_fwd(cols: np.ndarray, x: np.ndarray) -> np.ndarray:
     """y[B, bins] = A x for x[B, voxels]; cols[voxels, bins] holds A^T."""
     return np.atleast_2d(x) @ cols

@@ -339,3 +339,82 @@ def test_table_gradient_exact_fd(oracle):
         tm = tdata.copy().reshape(-1); tm[e] -= h
         fd = (loss(tp.reshape(tdata.shape)) - loss(tm.reshape(tdata.shape))) / (2 * h)
         assert abs(fd - grad.reshape(-1)[e]) <= 1e-9 * max(1.0, abs(fd)), (e, fd, grad.reshape(-1)[e])
+
+
+def test_sinogram_views_are_parallel_chords(oracle):
+    """Table 1's histogram organisation: the view of a crystal pair groups
+    parallel chords.  On a circular ring of n crystals at angles 2 pi g / n, the
+    chords of one view have directions within pi / n of each other (the two
+    interleaved parities), and every view holds the same number of pairs."""
+    n = 128
+    ang = 2 * np.pi * np.arange(n) / n
+    i, j = np.triu_indices(n, 1)
+    view = oracle.sinogram_view(i, j, n)
+    d = np.mod(np.arctan2(np.sin(ang[j]) - np.sin(ang[i]), np.cos(ang[j]) - np.cos(ang[i])), np.pi)
+    counts = np.bincount(view, minlength=n // 2)
+    assert counts.min() == counts.max() == n - 1
+    for v in range(n // 2):
+        dv = d[view == v]
+        spread = np.angle(np.exp(2j * dv) / np.exp(2j * dv[0])) / 2   # directions mod pi, relative
+        assert np.ptp(spread) <= np.pi / n + 1e-12
+
+
+def test_truncate_top_n_properties(oracle):
+    """Sec 3.3 truncation: at most N bins per view and voxel, the kept ones are
+    the largest, N = 1 keeps each view's maximum, a large N keeps everything,
+    and the kept sets grow with N."""
+    n = 16
+    rng = np.random.default_rng(9)
+    nb = n * (n - 1) // 2
+    cols = rng.random((5, nb)) * (rng.random((5, nb)) < 0.4)
+    cols[0, :4] = 0.5   # ties
+    i, j = np.triu_indices(n, 1)
+    view = oracle.sinogram_view(i, j, n)
+    prev = None
+    for N in (1, 2, 3, 5, 7):
+        t = oracle.truncate_top_n(cols, n, N)
+        for v in range(n // 2):
+            m = view == v
+            for r in range(cols.shape[0]):
+                kept = np.nonzero(t[r, m])[0]
+                assert len(kept) == min(N, np.count_nonzero(cols[r, m]))
+                if len(kept) < np.count_nonzero(cols[r, m]):
+                    dropped = np.setdiff1d(np.nonzero(cols[r, m])[0], kept)
+                    assert cols[r, m][kept].min() >= cols[r, m][dropped].max()
+                if N == 1 and len(kept):
+                    assert t[r, m][kept[0]] == cols[r, m].max()
+        assert np.all((t == 0) | (t == cols))
+        if prev is not None:
+            assert np.all((prev == 0) | (t == prev))   # kept at N-1 stays kept at N
+        prev = t
+    assert np.array_equal(oracle.truncate_top_n(cols, n, n), cols)
+    # ties keep the lower bin: row 0 has four equal values in view 0 and 1 and 1 ...
+    t1 = oracle.truncate_top_n(np.full((1, nb), 0.5), n, 1)
+    for v in range(n // 2):
+        assert np.nonzero(t1[0, view == v])[0].tolist() == [0]
+
+
+def test_osem_update_pins(oracle):
+    """Sec 3 OSEM: the subsets partition the bins; consistent data (y = A x)
+    is a fixed point of every subset update; an update keeps the subset's
+    counts: sum_j s_kj x_new_j = sum of y over the subset's bins with A x > 0."""
+    cfg = dict(CFG, nx=24, ny=24)
+    tab = oracle.table_2d(cfg)
+    n = cfg["nx"] * cfg["ny"]
+    cols, _ = oracle.columns_2d(cfg, tab, np.arange(n))
+    Nc = oracle.n_crystals_ring(cfg)
+    nb = oracle.n_bins_2d(cfg)
+    masks = [oracle.subset_mask(nb, Nc, 1, 8, k) for k in range(8)]
+    assert np.array_equal(sum(masks), np.ones(nb))
+    rng = np.random.default_rng(13)
+    x = rng.random(n) + 0.1
+    y = cols.T @ x
+    for k in (0, 5):
+        xk = oracle.osem_update(cols, y, x, masks[k])
+        sk = cols @ masks[k]
+        np.testing.assert_allclose(xk[sk > 0], x[sk > 0], rtol=1e-12)
+    yn = rng.poisson(1000 * y).astype(np.float64)
+    xk = oracle.osem_update(cols, yn, x * 1000, masks[3])
+    yhat = cols.T @ (x * 1000)
+    sel = (masks[3] > 0) & (yhat > 0)
+    np.testing.assert_allclose((cols @ masks[3]) @ xk, yn[sel].sum(), rtol=1e-12)
