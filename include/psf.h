@@ -44,7 +44,8 @@ enum {
     PSF_OK = 0,
     PSF_EINVAL = -1,       /* a NULL pointer, a negative size or a bad option */
     PSF_EGEOM = -2,        /* inconsistent geometry (e.g. a voxel outside the ring) */
-    PSF_ERANGE = -3,       /* an incidence angle beyond the table's last row, or table shape mismatch */
+    PSF_ERANGE = -3,       /* an incidence angle beyond the table's last row, a table shape mismatch, or
+                            * (PSF_OPT_DETERMINISTIC) a tile entry outside [0, 1) */
     PSF_ESIZE = -4,        /* a buffer is too small; the required size is written back */
     PSF_EHIP = -5,         /* a HIP runtime error (see psf_last_hip_error) */
     PSF_EOVERFLOW = -6,    /* fill phase produced more entries than the count phase allotted */
@@ -106,6 +107,15 @@ typedef struct {
     int64_t vox_end;        /* vox_end <= 0 means all voxels */
     int32_t accumulate;     /* 1: add into the output instead of overwriting */
     int32_t flags;          /* PSF_OPT_* bits */
+    int32_t top_n;          /* 0: every bin; n > 0 (2D, n <= 16): the matrix keeps, for each voxel and
+                             * each sinogram angle, only its n largest bins (paper Sec 3.3, Table 3).
+                             * The angle of crystal pair (i, j) of an N-crystal ring is view
+                             * ((i + j) mod N) / 2 of N / 2: pairs of one view are parallel chords
+                             * of a circular ring, the two parities interleaved (Table 1: 192 angles
+                             * for 384 crystals per ring).  Ties keep the lower bin.  Applies to every
+                             * 2D call (matrix, projections, sensitivity, list mode); not with the
+                             * table gradient, nor in 3D (PSF_EUNSUPPORTED). */
+    int32_t reserved;       /* 0 */
 } psf_opts;
 
 /* psf_opts.flags: project_adj will be asked for the table gradient (3D: the
@@ -135,6 +145,23 @@ typedef struct {
  * image.  A range may cut a group; its voxels inside the range are then built
  * one by one.  2D: the order is the linear one. */
 #define PSF_OPT_CLASS_ORDER 8
+/* psf_opts.flags: the workspace will serve psf_osem_update and
+ * psf_subset_sensitivity (psf_workspace_size adds their sinogram buffers). */
+#define PSF_OPT_OSEM 16
+/* psf_opts.flags (build_psf_sysmat): a deterministic build.  Each voxel's
+ * entries are summed as 64-bit integers in units of 2^-62 (each tile entry
+ * rounded to that unit once) instead of FP32 / FP64 floating-point atomics,
+ * whose order of arrival varies; integer sums do not depend on that order, so
+ * the CSR (pattern and values) is bitwise the same from run to run, on any
+ * GPU of the same architecture.  An element's error against the exact sum of
+ * its tile entries is at most (number of entries) x 2^-63 in absolute value,
+ * so elements far below 1e-12 lose relative precision and those below about
+ * 1e-19 may round to zero.  Tile entries must lie in [0, 1) and elements
+ * below 2 (true for response tables of probabilities); a tile entry outside
+ * that range returns PSF_ERANGE.  3D: the accumulators take 8 bytes per cell
+ * instead of 4 (psf_workspace_size must be asked with the flag).  Projections
+ * refuse the flag (PSF_EUNSUPPORTED). */
+#define PSF_OPT_DETERMINISTIC 32
 
 /* CSR of A^T: one row per voxel of the range, columns are bins, ascending. */
 typedef struct {
@@ -164,6 +191,14 @@ int psf_sizes(const psf_handle* h, int64_t* n_crystals, int64_t* n_bins, int64_t
  * table_dev (layout of psf_table, 2D or 3D by the handle's mode). */
 int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, float* table_dev,
                     void* stream);
+
+/* The same analytic table computed in FP64 on the host (the table builder
+ * of Sec 2.1.1 and Eq.6-7 as the device call above, kept in double precision
+ * and written to host memory, layout of psf_table for mode3d 0 or 1).  Needs no
+ * handle and no GPU; runs on the calling thread (the 3D table of 61 x 61 rows
+ * and 4 x 4 sub-positions takes a few seconds). */
+int psf_build_table_host(const psf_geometry* geom, int32_t mode3d, int32_t n_rows, int32_t n_sub, double step_deg,
+                         double* table_host);
 
 /* Device workspace in bytes needed by the calls below for these options,
  * batch size and number of events. */
@@ -239,6 +274,25 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
                        int64_t n_events, float randoms, const float* sens_dev, int32_t n_subsets,
                        const float* x_in_dev, float* x_out_dev, void* workspace_dev, size_t workspace_bytes,
                        void* stream);
+
+/* One histogram-mode OSEM subset update (paper Sec 3: the reconstructions of
+ * Fig. 9-12 and Table 2-3 run OSEM, 24 subsets of a 192-angle sinogram):
+ *   x_out = x_in / s_k * A^T (m_k y / A x_in),
+ * with y_dev the measured sinogram [n_bins] (FP32, bin layout of project_fwd),
+ * m_k the bins whose sinogram angle lies in subset k (angle of crystal pair
+ * (g_i, g_j) on an Nc-crystal ring: view ((g_i + g_j) mod Nc) / 2 of Nc / 2;
+ * subset k: the views v with v mod n_subsets = k; in 3D the transaxial pair
+ * decides), and s_k = A^T m_k from psf_subset_sensitivity.  Bins whose
+ * estimate A x_in is 0 contribute 0; voxels with s_k = 0 get 0.  One image;
+ * the workspace is sized with PSF_OPT_OSEM.  2D: asynchronous; 3D: blocks
+ * (see project_fwd). */
+int psf_osem_update(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y_dev,
+                    int32_t n_subsets, int32_t subset, const float* sens_dev, const float* x_in_dev, float* x_out_dev,
+                    void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* s_k = A^T m_k: the sensitivity of subset k of psf_osem_update, FP32 [n_voxels]. */
+int psf_subset_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t n_subsets,
+                           int32_t subset, float* s_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /* Wait for `stream` and report the status word the kernels keep in the
  * workspace (PSF_ERANGE if an incidence angle fell beyond the table). */

@@ -107,9 +107,10 @@ class Scanner:
             pass
 
     # -- helpers -----------------------------------------------------------
-    def opts(self, precision=PSF_FP32, threshold=0.0, vox_begin=0, vox_end=-1, accumulate=0, homog_k=0, flags=0):
+    def opts(self, precision=PSF_FP32, threshold=0.0, vox_begin=0, vox_end=-1, accumulate=0, homog_k=0, flags=0,
+             top_n=0):
         return _lib.psf_opts(int(precision), int(homog_k), float(threshold), int(vox_begin), int(vox_end),
-                             int(accumulate), int(flags))
+                             int(accumulate), int(flags), int(top_n), 0)
 
     def workspace(self, table: Table, batch: int = 1, n_events: int = 0, opts=None):
         torch = _torch()
@@ -136,6 +137,16 @@ class Scanner:
               "psf_build_table")
         return Table(data, n_rows, n_sub, step_deg)
 
+    def build_table_host(self, n_rows: int = 61, n_sub: int = 4, step_deg: float = 1.0):
+        """The same analytic table in FP64 on the host (psf_build_table_host):
+        numpy float64 in the layout of psf_table."""
+        import numpy as np
+        numel = n_rows * n_rows * n_sub * n_sub * 25 if self.mode3d else n_rows * n_sub * 5
+        out = np.zeros(numel, dtype=np.float64)
+        check(self.L.psf_build_table_host(C.byref(self.geom), int(self.mode3d), int(n_rows), int(n_sub),
+                                          float(step_deg), C.c_void_p(out.ctypes.data)), "psf_build_table_host")
+        return out
+
     def table_from(self, data, n_rows: int, n_sub: int, step_deg: float = 1.0) -> Table:
         """Wrap a caller-provided table (any shape with the right number of entries)."""
         torch = _torch()
@@ -152,15 +163,20 @@ class Scanner:
 
     def build_psf_sysmat(self, table: Table, threshold: float = 0.0, vox_begin: int = 0, vox_end: int = -1,
                          precision: int = PSF_FP32, stage: bool = True, counters: list | None = None,
-                         class_order: bool = False):
+                         class_order: bool = False, homog_k: int = 0, top_n: int = 0, deterministic: bool = False):
         """CSR of A^T for voxels [vox_begin, vox_end): (row_ptr int64, col int32, val float32).
         stage: the count phase keeps its rows in the workspace for the fill phase (3D).
         counters: if a list, each phase appends its header_counters() snapshot (3D).
         class_order: the range counts positions of voxel_order() (row k is voxel
-        voxel_order()[vox_begin + k])."""
+        voxel_order()[vox_begin + k]).
+        homog_k: 0 for the k -> infinity homogenization weights, k > 0 for k lines (2D).
+        top_n: n > 0 keeps each voxel's n largest bins per sinogram angle (2D).
+        deterministic: integer sums of the tile entries (PSF_OPT_DETERMINISTIC): the
+        same CSR, bit for bit, on every run."""
         torch = _torch()
         flags = (_lib.PSF_OPT_STAGE_CSR if stage else 0) | (_lib.PSF_OPT_CLASS_ORDER if class_order else 0)
-        o = self.opts(precision, threshold, vox_begin, vox_end, flags=flags)
+        flags |= _lib.PSF_OPT_DETERMINISTIC if deterministic else 0
+        o = self.opts(precision, threshold, vox_begin, vox_end, flags=flags, homog_k=homog_k, top_n=top_n)
         ve = self.n_voxels if vox_end is None or vox_end < 0 else vox_end
         n = ve - vox_begin
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=self.device)
@@ -185,7 +201,8 @@ class Scanner:
             counters.append(self.header_counters())
         return row_ptr, col[:nnz], val[:nnz]
 
-    def project_fwd(self, table: Table, x, events=None, precision: int = PSF_FP32, y=None, accumulate: int = 0):
+    def project_fwd(self, table: Table, x, events=None, precision: int = PSF_FP32, y=None, accumulate: int = 0,
+                    homog_k: int = 0, top_n: int = 0):
         """y = A x (x: [batch, n_voxels] float32); with ``events`` (int32 [n, 2]
         crystal pairs) the list-mode rows y[batch, n]."""
         torch = _torch()
@@ -196,7 +213,7 @@ class Scanner:
         nout = self.n_bins if events is None else ne
         if y is None:
             y = torch.empty(batch, nout, dtype=torch.float32, device=self.device)
-        o = self.opts(precision, accumulate=accumulate)
+        o = self.opts(precision, accumulate=accumulate, homog_k=homog_k, top_n=top_n)
         ws = self.workspace(table, batch, ne, o)
         tc = table.c()
         check(self.L.project_fwd(self.h, C.byref(tc), C.byref(o), _ptr(x2), batch, _events_ptr(events), ne, _ptr(y),
@@ -204,7 +221,7 @@ class Scanner:
         return y
 
     def project_adj(self, table: Table, y, events=None, xt=None, want_table_grad=False, precision: int = PSF_FP32,
-                    x=None, accumulate: int = 0):
+                    x=None, accumulate: int = 0, top_n: int = 0):
         """x = A^T y; optionally also d<y, A xt>/d table.  Returns x or (x, grad)."""
         torch = _torch()
         y = _dev_f32(y, "y")
@@ -218,7 +235,8 @@ class Scanner:
         if want_table_grad:
             xt = _dev_f32(xt, "xt").reshape(batch, self.n_voxels)
             grad = torch.zeros_like(table.data)
-        o = self.opts(precision, accumulate=accumulate, flags=_lib.PSF_OPT_TABLE_GRAD if want_table_grad else 0)
+        o = self.opts(precision, accumulate=accumulate, flags=_lib.PSF_OPT_TABLE_GRAD if want_table_grad else 0,
+                      top_n=top_n)
         ws = self.workspace(table, batch, ne, o)
         tc = table.c()
         check(self.L.project_adj(self.h, C.byref(tc), C.byref(o), _ptr(y2), batch, _events_ptr(events), ne, _ptr(x),
@@ -226,10 +244,10 @@ class Scanner:
                                  _stream()), "project_adj")
         return (x, grad) if want_table_grad else x
 
-    def sensitivity(self, table: Table, precision: int = PSF_FP32):
+    def sensitivity(self, table: Table, precision: int = PSF_FP32, top_n: int = 0):
         torch = _torch()
         s = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)
-        o = self.opts(precision)
+        o = self.opts(precision, top_n=top_n)
         ws = self.workspace(table, 1, 0, o)
         tc = table.c()
         check(self.L.psf_sensitivity(self.h, C.byref(tc), C.byref(o), _ptr(s), _ptr(ws), ws.numel(), _stream()),
@@ -249,6 +267,34 @@ class Scanner:
         check(self.L.psf_lm_osem_update(self.h, C.byref(tc), C.byref(o), _ptr(events), ne, float(randoms),
                                         _ptr(sens), int(n_subsets), _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
                                         _stream()), "psf_lm_osem_update")
+        return out
+
+    def subset_sensitivity(self, table: Table, n_subsets: int, subset: int, precision: int = PSF_FP32,
+                           top_n: int = 0):
+        """s_k = A^T m_k for OSEM subset k of n_subsets (psf_subset_sensitivity)."""
+        torch = _torch()
+        s = torch.empty(self.n_voxels, dtype=torch.float32, device=self.device)
+        o = self.opts(precision, flags=_lib.PSF_OPT_OSEM, top_n=top_n)
+        ws = self.workspace(table, 1, 0, o)
+        tc = table.c()
+        check(self.L.psf_subset_sensitivity(self.h, C.byref(tc), C.byref(o), int(n_subsets), int(subset), _ptr(s),
+                                            _ptr(ws), ws.numel(), _stream()), "psf_subset_sensitivity")
+        return s
+
+    def osem_update(self, table: Table, y, x, sens_k, n_subsets: int, subset: int, precision: int = PSF_FP32,
+                    top_n: int = 0):
+        """One histogram OSEM subset update (psf_osem_update); returns x_out."""
+        torch = _torch()
+        y = _dev_f32(y, "y").reshape(-1)
+        x = _dev_f32(x, "x").reshape(-1)
+        sens_k = _dev_f32(sens_k, "sens_k").reshape(-1)
+        out = torch.empty_like(x)
+        o = self.opts(precision, flags=_lib.PSF_OPT_OSEM, top_n=top_n)
+        ws = self.workspace(table, 1, 0, o)
+        tc = table.c()
+        check(self.L.psf_osem_update(self.h, C.byref(tc), C.byref(o), _ptr(y), int(n_subsets), int(subset),
+                                     _ptr(sens_k), _ptr(x), _ptr(out), _ptr(ws), ws.numel(), _stream()),
+              "psf_osem_update")
         return out
 
     def profile_start(self):

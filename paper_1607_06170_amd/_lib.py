@@ -26,6 +26,8 @@ PSF_OPT_TABLE_GRAD = 1
 PSF_OPT_STAGE_CSR = 2
 PSF_OPT_WS_CLEAN = 4
 PSF_OPT_CLASS_ORDER = 8
+PSF_OPT_OSEM = 16
+PSF_OPT_DETERMINISTIC = 32
 
 PSF_FP32 = 0
 PSF_BF16 = 1
@@ -51,7 +53,8 @@ class psf_table(C.Structure):
 
 class psf_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("homog_k", C.c_int32), ("threshold", C.c_double),
-                ("vox_begin", C.c_int64), ("vox_end", C.c_int64), ("accumulate", C.c_int32), ("flags", C.c_int32)]
+                ("vox_begin", C.c_int64), ("vox_end", C.c_int64), ("accumulate", C.c_int32), ("flags", C.c_int32),
+                ("top_n", C.c_int32), ("reserved", C.c_int32)]
 
 
 class psf_csr(C.Structure):
@@ -67,6 +70,7 @@ SIGNATURES = {
     "psf_destroy": (None, [_H]),
     "psf_sizes": (C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "psf_build_table": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double, _P, _P]),
+    "psf_build_table_host": (C.c_int, [C.POINTER(psf_geometry), C.c_int32, C.c_int32, C.c_int32, C.c_double, _P]),
     "psf_workspace_size": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), C.c_int32, C.c_int64,
                                      C.POINTER(C.c_size_t)]),
     "build_psf_sysmat": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_size_t,
@@ -81,6 +85,10 @@ SIGNATURES = {
     "psf_lm_osem_update": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int64, C.c_float, _P,
                                      C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "psf_voxel_order": (C.c_int, [_H, _P]),
+    "psf_osem_update": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), _P, C.c_int32, C.c_int32, _P, _P,
+                                  _P, _P, C.c_size_t, _P]),
+    "psf_subset_sensitivity": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), C.c_int32, C.c_int32, _P, _P,
+                                         C.c_size_t, _P]),
     "psf_check": (C.c_int, [_H, _P, _P]),
     "psf_profile": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_void_p]),
     "psf_status_string": (C.c_char_p, [C.c_int]),

@@ -186,10 +186,14 @@ static Ring2D make_ring2d(const psf_handle* h, const psf_table* t, const psf_opt
     G.frames = h->frames_dev;
     G.table = t->data;
     G.precision = o ? o->precision : PSF_FP32;
+    G.homog_k = o ? o->homog_k : 0;
+    G.top_n = o ? o->top_n : 0;
+    G.det = 0;  // set by the matrix build
     return G;
 }
 
 static int check_2d_support(const psf_handle* h, const Ring2D& G, int mode) {
+    if (G.top_n > 0 && (G.Nc % 2 != 0 || mode == kModeAdjGrad)) return PSF_EUNSUPPORTED;
     int dev = 0, maxsm = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSF_EHIP;
     if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PSF_EHIP;
@@ -197,11 +201,12 @@ static int check_2d_support(const psf_handle* h, const Ring2D& G, int mode) {
     return PSF_OK;
 }
 
-int check_opts(const psf_opts* o) {
+int check_opts(const psf_opts* o, bool build) {
     if (!o) return PSF_EINVAL;
     if (o->precision < PSF_FP32 || o->precision > PSF_BF16X2) return PSF_EINVAL;
     if (o->homog_k < 0) return PSF_EINVAL;
-    if (o->homog_k > 0) return PSF_EUNSUPPORTED;  // finite-k sampling is an oracle test mode
+    if (o->top_n < 0 || o->top_n > kTopNMax) return PSF_EINVAL;
+    if (!build && (o->flags & PSF_OPT_DETERMINISTIC)) return PSF_EUNSUPPORTED;  // matrix builds only
     return PSF_OK;
 }
 
@@ -270,6 +275,7 @@ extern "C" {
 int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
                        int64_t n_events, size_t* bytes) {
     if (!h || !table || !bytes || batch < 0 || n_events < 0) return PSF_EINVAL;
+    if (opts && (opts->flags & PSF_OPT_OSEM) && n_events == 0) n_events = 1;  // the OSEM sinogram buffers
     *bytes = h->mode3d ? ws3_total(h, table, batch, n_events, opts) : ws_layout(h, table, batch, n_events).total;
     return PSF_OK;
 }
@@ -284,12 +290,23 @@ int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_de
     return PSF_OK;
 }
 
+int psf_build_table_host(const psf_geometry* geom, int32_t mode3d, int32_t n_rows, int32_t n_sub, double step_deg,
+                         double* out) {
+    if (!geom || !out || n_rows < 1 || n_sub < 1 || !(step_deg > 0) || (mode3d != 0 && mode3d != 1)) return PSF_EINVAL;
+    if (!(geom->pitch_t > 0) || !(geom->pitch_z > 0) || !(geom->depth > 0) || !(geom->mu > 0)) return PSF_EINVAL;
+    if (mode3d)
+        table_3d_host(*geom, n_rows, n_sub, step_deg, out);
+    else
+        table_2d_host(*geom, n_rows, n_sub, step_deg, out);
+    return PSF_OK;
+}
+
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* ws, size_t ws_bytes,
                      psf_csr* csr, void* stream) {
     if (!h || !csr || !ws) return PSF_EINVAL;
     int st = check_table(h, table);
     if (st) return st;
-    if ((st = check_opts(opts))) return st;
+    if ((st = check_opts(opts, true))) return st;
     if (h->mode3d) return build_sysmat_3d(h, table, opts, ws, ws_bytes, csr, (hipStream_t)stream);
     if (ws_bytes < kWsHeader) return PSF_ESIZE;
     const int64_t vb = opts->vox_begin, ve = opts->vox_end > 0 ? opts->vox_end : h->n_vox;
@@ -297,6 +314,7 @@ int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts
     if (!csr->row_ptr) return PSF_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     Ring2D G = make_ring2d(h, table, opts);
+    G.det = (opts->flags & PSF_OPT_DETERMINISTIC) != 0;
     VoxArgs2D a;
     memset(&a, 0, sizeof(a));
     a.vox_begin = vb;
@@ -531,6 +549,55 @@ int psf_lm_osem_update(psf_handle* h, const psf_table* table, const psf_opts* op
     if ((st = adj_bins(h, table, opts, h32, 0, 1, back, nullptr, nullptr, 0, ws, s))) return st;
     HIP_TRY(launch_lm_update(x_in, back, sens, n_subsets, h->n_vox, x_out, s));
     return PSF_OK;
+}
+
+static int check_subsets(const psf_handle* h, int n_subsets, int subset) {
+    const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
+    if (n_subsets < 1 || subset < 0 || subset >= n_subsets || n_subsets > Nc / 2) return PSF_EINVAL;
+    return PSF_OK;
+}
+
+int psf_osem_update(psf_handle* h, const psf_table* table, const psf_opts* opts, const float* y, int32_t n_subsets,
+                    int32_t subset, const float* sens, const float* x_in, float* x_out, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!h || !y || !sens || !x_in || !x_out || !ws) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if ((st = check_subsets(h, n_subsets, subset))) return st;
+    if (h->mode3d)
+        return osem_3d(h, table, opts, y, n_subsets, subset, sens, x_in, x_out, ws, ws_bytes, (hipStream_t)stream);
+    const WsLayout L = ws_layout(h, table, 1, 1);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    double* y64 = at<double>(ws, L.y64);
+    float* r = at<float>(ws, L.h32);
+    float* back = at<float>(ws, L.back);
+    const int64_t Nc = h->n_crystals;
+    if ((st = fwd_bins(h, table, opts, x_in, 1, y64, ws, s))) return st;
+    HIP_TRY(launch_osem_ratio(y64, nullptr, y, h->n_bins, Nc, 1, n_subsets, subset, r, s));
+    if ((st = adj_bins(h, table, opts, r, 0, 1, back, nullptr, nullptr, 0, ws, s))) return st;
+    HIP_TRY(launch_osem_update(x_in, back, sens, h->n_vox, x_out, s));
+    return PSF_OK;
+}
+
+int psf_subset_sensitivity(psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t n_subsets,
+                           int32_t subset, float* s_dev, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !s_dev || !ws) return PSF_EINVAL;
+    int st = check_table(h, table);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if ((st = check_subsets(h, n_subsets, subset))) return st;
+    if (h->mode3d)
+        return subset_sensitivity_3d(h, table, opts, n_subsets, subset, s_dev, ws, ws_bytes, (hipStream_t)stream);
+    const WsLayout L = ws_layout(h, table, 1, 1);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((st = zero_header(ws, s))) return st;
+    float* m = at<float>(ws, L.h32);
+    HIP_TRY(launch_subset_mask(h->n_bins, h->n_crystals, 1, n_subsets, subset, m, s));
+    return adj_bins(h, table, opts, m, 0, 1, s_dev, nullptr, nullptr, 0, ws, s);
 }
 
 int psf_profile(psf_handle* h, int32_t enable, double* ms, int64_t* launches) {

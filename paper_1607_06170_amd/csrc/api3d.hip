@@ -16,6 +16,7 @@ constexpr int kBatchCsr = 1024;   // voxels per batch of the matrix build (dense
 constexpr int kShareCsr = 8;      // voxels of one column in a class of the matrix build (interleaved accumulators)
 constexpr int kBatchProj = 4096;  // voxels per batch of the projections (fewer, fuller launches)
 constexpr int kClsBatch = 2047;   // classes per batch: a tile record's header holds the class index in 11 bits
+constexpr int kMaxMemProj = 256;  // voxels of a projection class with images or the axial mirror (16 z-shifts x 8 images x 2)
 constexpr int kCapSamples = 4096;
 constexpr int kCapPairs = 1024;
 constexpr int kCapSlots = 4096;
@@ -74,7 +75,9 @@ Cyl3D make_cyl3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
     return G;
 }
 
-int check3d(const psf_handle* h, const psf_table* t) {
+int check3d(const psf_handle* h, const psf_table* t, const psf_opts* o) {
+    if (o && o->homog_k > 0) return PSF_EUNSUPPORTED;  // the 3D weights are the k -> infinity solid angles
+    if (o && o->top_n > 0) return PSF_EUNSUPPORTED;    // the truncation per sinogram angle is built for the 2D ring
     if (t->n_sub > 4) return PSF_EUNSUPPORTED;  // tiles hold P^2 <= 16 sub-patches
     const int64_t nseg = (int64_t)h->g.n_blocks * h->g.n_cryst_t * t->n_sub;
     if (nseg >= 32768) return PSF_EUNSUPPORTED;
@@ -90,14 +93,17 @@ struct Ws3 {
         g64, plan, stage_cb, stage_cn, stage_nch, stage_cnt, stage_col, stage_val, x64, ydiag, y32, h64, h32, back, total;
     int64_t table_elems, cap_stage, stage_rows;  // stage: entries; rows with a region of kStagePerVoxel
     int bmax, bcsr, cap_slots, band_rows;
-    int64_t dense_slab;  // floats of one member's share of the build accumulators
+    int64_t dense_slab;  // cells of one member's share of the build accumulators
+    int det;             // deterministic build: 64-bit integer cells (fix62) instead of FP32
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
 };
 
-Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad, int64_t stage_rows) {
+Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad, int64_t stage_rows,
+               int det = 0) {
     Ws3 L;
+    L.det = det;
     const int64_t Nc = (int64_t)h->g.n_blocks * h->g.n_cryst_t;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
     const int64_t ntbins = Nc * (Nc - 1) / 2;
@@ -122,7 +128,7 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
     off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
     L.dense = off;  // a class of n members takes n slabs: [slot][NR + n - 1][NR + n - 1][n]
     L.dense_slab = (int64_t)L.cap_slots * (NR + kShareCsr - 1) * (NR + kShareCsr - 1);
-    off += align256(sizeof(float) * (size_t)L.bcsr * L.dense_slab);
+    off += align256((det ? sizeof(unsigned long long) : sizeof(float)) * (size_t)L.bcsr * L.dense_slab);
     L.band = off;  // a build class's s_max is below kShareCsr
     L.band_rows = (int)NR + kShareCsr + 3;
     off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
@@ -224,6 +230,7 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.slot_order = at3<int>(ws, L.slot_order);
     S.dense = at3<float>(ws, L.dense);
     S.dense_slab = L.dense_slab;
+    S.det = L.det;
     S.chunk_counts = at3<int>(ws, L.chunks);
     S.max_chunks = L.max_chunks;
     S.recs = at3<float>(ws, L.recs);
@@ -293,7 +300,8 @@ static int64_t column_image(int code, int64_t n, int64_t ixy) {
 // zmir: a class may also take the axial mirror image of its z-run (z -> -z
 // about the scanner's centre), when the image grid is centred axially.
 // share: most voxels of one column in a class.
-Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share, bool zmir) {
+Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax, bool sym, int share, bool zmir,
+            int max_mem = 128) {
     Plan3 pl;
     const int64_t nx = h->im.nx, ny = h->im.ny, nz = h->im.nz, nxy = nx * ny;
     const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
@@ -348,10 +356,11 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
             for (int64_t iz = zlo; iz <= zhi; ++iz) add_class(cols[0] + iz * nxy, 0, 1, cols, codes, ni, 0);
             return;
         }
-        // the contraction gives each member of a class a lane in one of two passes
-        // of 64: at most 64 members with images, 128 with the mirror half too
+        // classes with images or the axial mirror hold at most max_mem members
+        // (the contraction's emission keeps a class's member values in LDS): half
+        // of them in the reference half
         int run = cmax;
-        if (ni > 1 && run * ni > 64) run = 64 / ni;
+        if (ni > 1 && run * ni > max_mem / 2) run = max_mem / 2 / ni;
         std::vector<int64_t> rs, rn;  // runs: first z, voxels
         for (int64_t c = 0; c < m && zlo + c <= zhi; ++c) {
             const int64_t n_all = (zhi - (zlo + c)) / m + 1;
@@ -365,7 +374,7 @@ Plan3 plan3(const psf_handle* h, const Ws3& L, int64_t vb, int64_t ve, int bmax,
             if (used[i]) continue;
             used[i] = 1;
             int mir = 0;
-            if (zmir && rn[i] * ni * 2 <= 128) {  // the run whose voxels are this run's mirror images, if it is one
+            if (zmir && rn[i] * ni * 2 <= max_mem) {  // the run whose voxels are this run's mirror images, if it is one
                 const int64_t s2 = nz - 1 - (rs[i] + (rn[i] - 1) * m);
                 for (size_t j = i + 1; j < rs.size(); ++j)
                     if (!used[j] && rs[j] == s2 && rn[j] == rn[i]) {
@@ -546,7 +555,7 @@ int batch_geometry(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Args
 // into a diagonal-layout copy (FP32 atomics), permuted into y at the end
 int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* x, int batch, float* y,
              int accumulate, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true, kMaxMemProj);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -580,7 +589,7 @@ int fwd3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
 // g64, also d <y, A xt> / d table summed over the batch
 int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, const float* y, int ones, int batch,
              double* x64, const float* xt, double* g64, void* ws, hipStream_t s) {
-    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true);
+    const Plan3 pl = plan3(h, L, 0, h->n_vox, L.bmax, true, L.bmax, true, kMaxMemProj);
     PlanDev pd;
     int st = upload_plan(pl, ws, L, s, &pd);
     if (st) return st;
@@ -625,14 +634,16 @@ static int64_t stage_rows(const psf_handle* h, const psf_opts* o) {
 }
 
 size_t ws3_total(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, const psf_opts* o) {
-    return ws3_layout(h, t, batch, n_events, o && (o->flags & PSF_OPT_TABLE_GRAD), stage_rows(h, o)).total;
+    return ws3_layout(h, t, batch, n_events, o && (o->flags & PSF_OPT_TABLE_GRAD), stage_rows(h, o),
+                      o && (o->flags & PSF_OPT_DETERMINISTIC)).total;
 }
 
 int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* ws, size_t ws_bytes, psf_csr* csr,
                     hipStream_t s) {
-    int st = check3d(h, t);
+    int st = check3d(h, t, o);
     if (st) return st;
-    const Ws3 L = ws3_layout(h, t, 1, 0, o->flags & PSF_OPT_TABLE_GRAD, stage_rows(h, o));
+    const Ws3 L = ws3_layout(h, t, 1, 0, o->flags & PSF_OPT_TABLE_GRAD, stage_rows(h, o),
+                             (o->flags & PSF_OPT_DETERMINISTIC) != 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
     if (L.dense_slab * kShareCsr >= ((int64_t)1 << 31)) return PSF_EUNSUPPORTED;  // a group's cells index in 32 bits
     const int64_t vb = o->vox_begin, ve = o->vox_end > 0 ? o->vox_end : h->n_vox;
@@ -670,11 +681,12 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     // the accumulators start clean (cleared, or known clean from the last build
     // on this workspace); the compaction leaves them clean
     const bool use_dense = !(phase_fill && staged == (int)pl.batches.size());
+    const int64_t dense_floats = L.bcsr * L.dense_slab * (L.det ? 2 : 1);  // FP32 cells, or 64-bit integer ones
     const unsigned long long dsig[3] = {(unsigned long long)(uintptr_t)h, (unsigned long long)L.dense,
-                                        (unsigned long long)(L.bcsr * L.dense_slab)};
+                                        (unsigned long long)dense_floats};
     unsigned long long* dstate = (unsigned long long*)((char*)ws + kWsDense);
     if (use_dense)
-        HIP_TRY(launch_dense_clear(S.dense, L.bcsr * L.dense_slab, dstate, dsig, (o->flags & PSF_OPT_WS_CLEAN) != 0, s));
+        HIP_TRY(launch_dense_clear(S.dense, dense_floats, dstate, dsig, (o->flags & PSF_OPT_WS_CLEAN) != 0, s));
     // the count phase writes each row's count into row_ptr[row + 1]
     if (!phase_fill) HIP_TRY(launch_zero_f64((double*)csr->row_ptr, ve - vb + 1, s));
     PlanDev pd;
@@ -752,7 +764,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
 
 int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* x, int batch,
                    const int32_t* events, int64_t n_events, float* y, void* ws, size_t ws_bytes, hipStream_t s) {
-    int st = check3d(h, t);
+    int st = check3d(h, t, o);
     if (st) return st;
     const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
@@ -774,7 +786,7 @@ int project_fwd_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
 int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int ones, int batch,
                    const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
                    size_t ws_bytes, hipStream_t s) {
-    int st = check3d(h, t);
+    int st = check3d(h, t, o);
     if (st) return st;
     const Ws3 L = ws3_layout(h, t, batch, events ? n_events : 0, grad != nullptr, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
@@ -808,7 +820,7 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
 int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
                float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
                size_t ws_bytes, hipStream_t s) {
-    int st = check3d(h, t);
+    int st = check3d(h, t, o);
     if (st) return st;
     const Ws3 L = ws3_layout(h, t, 1, n_events, 0, 0);
     if (ws_bytes < L.total) return PSF_ESIZE;
@@ -844,4 +856,47 @@ int voxel_order_3d(psf_handle* h, int64_t* order) {
     if ((int64_t)C.mem.size() != h->n_vox) return PSF_EINVAL;
     for (int64_t k = 0; k < h->n_vox; ++k) order[k] = C.mem[k].x;
     return PSF_OK;
+}
+
+int osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int n_subsets, int subset,
+            const float* sens, const float* x_in, float* x_out, void* ws, size_t ws_bytes, hipStream_t s) {
+    int st = check3d(h, t, o);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, 1, 1, 0, 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    if ((st = zero_header(ws, s))) return st;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    float* yh = at3<float>(ws, L.y32);
+    float* r = at3<float>(ws, L.h32);
+    float* back = at3<float>(ws, L.back);
+    double* x64 = at3<double>(ws, L.x64);
+    // yhat = A x -> r = m_k y / yhat -> back = A^T r -> update
+    if ((st = fwd3_all(h, G, S, L, x_in, 1, yh, 0, ws, s))) return st;
+    HIP_TRY(launch_osem_ratio(nullptr, yh, y, h->n_bins, G.Nc, NR, n_subsets, subset, r, s));
+    HIP_TRY(launch_zero_f64(x64, h->n_vox, s));
+    if ((st = adj3_all(h, G, S, L, r, 0, 1, x64, nullptr, nullptr, ws, s))) return st;
+    HIP_TRY(launch_finalize(x64, back, h->n_vox, 0, s));
+    HIP_TRY(launch_osem_update(x_in, back, sens, h->n_vox, x_out, s));
+    return read_status(ws, s);
+}
+
+int subset_sensitivity_3d(psf_handle* h, const psf_table* t, const psf_opts* o, int n_subsets, int subset, float* s_dev,
+                          void* ws, size_t ws_bytes, hipStream_t s) {
+    int st = check3d(h, t, o);
+    if (st) return st;
+    const Ws3 L = ws3_layout(h, t, 1, 1, 0, 0);
+    if (ws_bytes < L.total) return PSF_ESIZE;
+    const Cyl3D G = make_cyl3d(h, t, o);
+    const Scratch3D S = make_scratch(ws, L);
+    if ((st = zero_header(ws, s))) return st;
+    const int64_t NR = (int64_t)h->g.n_cryst_z * h->g.n_block_rings;
+    float* m = at3<float>(ws, L.h32);
+    double* x64 = at3<double>(ws, L.x64);
+    HIP_TRY(launch_subset_mask(h->n_bins, G.Nc, NR, n_subsets, subset, m, s));
+    HIP_TRY(launch_zero_f64(x64, h->n_vox, s));
+    if ((st = adj3_all(h, G, S, L, m, 0, 1, x64, nullptr, nullptr, ws, s))) return st;
+    HIP_TRY(launch_finalize(x64, s_dev, h->n_vox, 0, s));
+    return read_status(ws, s);
 }

@@ -74,7 +74,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int64_t table_elems(const psf_handle* h, const psf_table* t);
 int check_table(const psf_handle* h, const psf_table* t);
-int check_opts(const psf_opts* o);
+int check_opts(const psf_opts* o, bool build = false);  // build: a matrix build (the only call taking PSF_OPT_DETERMINISTIC)
 int zero_header(void* ws, hipStream_t st);
 int read_status(void* ws, hipStream_t st);
 
@@ -88,6 +88,10 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
                    const int32_t* events, int64_t n_events, float* x, const float* xt, float* grad, void* ws,
                    size_t ws_bytes, hipStream_t s);
 int voxel_order_3d(psf_handle* h, int64_t* order);
+int osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const float* y, int n_subsets, int subset,
+            const float* sens, const float* x_in, float* x_out, void* ws, size_t ws_bytes, hipStream_t s);
+int subset_sensitivity_3d(psf_handle* h, const psf_table* t, const psf_opts* o, int n_subsets, int subset, float* s_dev,
+                          void* ws, size_t ws_bytes, hipStream_t s);
 int lm_osem_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const int32_t* events, int64_t n_events,
                float randoms, const float* sens, int n_subsets, const float* x_in, float* x_out, void* ws,
                size_t ws_bytes, hipStream_t s);

@@ -13,6 +13,7 @@ constexpr double kPi = 3.14159265358979323846;
 // of zero measure (it guards exact antipodal coincidences against rounding).
 constexpr double kEpsOverlap = 1e-12;
 constexpr int kNb = 5;  // neighbour crystals per axis: offsets -2..2
+constexpr int kTopNMax = 16;  // largest top_n (bins kept per voxel and sinogram view)
 
 // status bits kept in the first word of the workspace
 constexpr int kStatRange = 1;     // an incidence angle beyond the last table row was used
@@ -43,6 +44,9 @@ struct Ring2D {
     const double* frames;  // [R][2]: cos, sin of the block's outward normal
     const float* table;    // [n_rows][P][5]
     int precision;
+    int homog_k;           // 0: the k -> infinity sweep; k > 0: k lines at theta_i = pi i / k (Eq.11)
+    int top_n;             // 0: every bin; n > 0: each sinogram view keeps its n largest bins
+    int det;               // matrix build: integer sums of the tile entries (fix62)
 };
 
 // Everything a 3D-scanner kernel needs, passed by value.  Crystal (g, r):
@@ -71,12 +75,14 @@ struct Scratch3D {
     int* slotmap;      // [B_mem][ntbins]  transaxial bin -> slot (-1: none), reference columns
     int* slot_tbin;    // [B_mem][cap_slots]  the column's bins in ascending order
     int* slot_order;   // [B_mem][cap_slots]  their reference slots (bit 30: photons swapped)
-    // matrix build: FP32 sums of the FP32 tile entries.  A column of n members
+    // matrix build: FP32 sums of the FP32 tile entries (deterministic builds:
+    // exact integer sums in units of 2^-62, see fix62).  A column of n members
     // (s_max = n - 1) from batch member mi0 on holds [slot][i][j][s] from slab
     // mi0: member s's ring pair (r_i, r_j) at i = r_i - s + s_max, j = r_j - s +
     // s_max (both < NR + s_max), so an entry's members lie side by side
-    float* dense;      // [B_mem][dense_slab]
+    float* dense;      // [B_mem][dense_slab] (deterministic builds: 64-bit integer cells, fix62)
     int64_t dense_slab;
+    int det;
     int* chunk_counts; // [B_mem][max_chunks]  kept entries per compaction chunk
     int64_t max_chunks;
     float* recs;       // [cap_recs][kRecFloats]  tile records (header, sample blocks of W)
@@ -204,10 +210,19 @@ hipError_t launch_lm_ratio(const double* y64, const float* y32, const int32_t* e
 hipError_t launch_lm_update(const float* x_in, const float* back, const float* sens, int n_subsets, int64_t nvox,
                             float* x_out, hipStream_t st);
 
+hipError_t launch_osem_ratio(const double* yh64, const float* yh32, const float* y, int64_t nbins, int64_t Nc,
+                             int64_t NR, int n_subsets, int subset, float* r, hipStream_t st);
+hipError_t launch_subset_mask(int64_t nbins, int64_t Nc, int64_t NR, int n_subsets, int subset, float* m,
+                              hipStream_t st);
+hipError_t launch_osem_update(const float* x_in, const float* back, const float* sens, int64_t nvox, float* x_out,
+                              hipStream_t st);
+
 enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad = 4 };
 
 // 3D launchers (cyl3d.hip, table3d.hip)
 hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st);
+void table_2d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out);
+void table_3d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out);
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
                                    hipStream_t st);
 hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
@@ -231,5 +246,15 @@ hipError_t launch_diag_perm(const float* src, float* dst, int64_t nbins, int NR,
                             hipStream_t st);
 int64_t cyl3d_max_chunks(int cap_slots, int NR);
 constexpr int kStatScratch = 16;  // a per-voxel scratch capacity was exceeded
+
+// Deterministic matrix builds: a tile entry t in [0, 1) is rounded once to the
+// nearest multiple of 2^-62 and summed as a 64-bit integer.  Integer sums are
+// exact, so a bin's sum does not depend on the order in which its entries
+// arrive; an element (below 2) is read back as q * 2^-62, rounded to FP64.
+__device__ __forceinline__ bool fix62_ok(float t) { return t >= 0.0f && t < 1.0f; }
+__device__ __forceinline__ unsigned long long fix62(float t) {
+    return fix62_ok(t) ? (unsigned long long)__builtin_rint((double)t * 0x1p62) : 0ull;
+}
+__host__ __device__ inline double unfix62(unsigned long long q) { return (double)q * 0x1p-62; }
 
 }  // namespace psf

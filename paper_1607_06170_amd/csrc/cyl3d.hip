@@ -107,6 +107,28 @@ __device__ __forceinline__ int diag32(int ri, int rj, int NR) {
     return ((NR * (NR - 1)) >> 1) + k * NR - ((k * (k - 1)) >> 1) + ri;
 }
 
+// the matrix build's accumulator cell i (an index into S.dense counted in
+// cells): add a tile entry, or take the sum (read it, and clear the cell)
+__device__ __forceinline__ void acc_add(const Scratch3D& S, int64_t i, float v, int& flag) {
+    if (S.det) {
+        if (!fix62_ok(v)) flag |= kStatRange;
+        atomicAdd((unsigned long long*)S.dense + i, fix62(v));
+    } else {
+        atomicAdd(S.dense + i, v);
+    }
+}
+__device__ __forceinline__ float acc_take(const Scratch3D& S, int64_t i, bool clear) {
+    if (S.det) {
+        unsigned long long* p = (unsigned long long*)S.dense + i;
+        const unsigned long long q = *p;
+        if (clear) *p = 0ull;
+        return (float)unfix62(q);
+    }
+    const float a = S.dense[i];
+    if (clear) S.dense[i] = 0.0f;
+    return a;
+}
+
 __device__ __forceinline__ int64_t diag_index(int ri, int rj, int NR) {
     const int d = rj - ri + NR - 1;
     if (d < NR - 1) return (int64_t)d * (d + 1) / 2 + (ri - (NR - 1 - d));
@@ -1196,35 +1218,55 @@ struct MmaList {
     unsigned short ab[640]; // a | b << 8: the entry's place in the tile
 };
 
+// The forward's emission by runs: a tile's entries grouped by transaxial
+// neighbour pair p and axial diagonal bz - az.  Along such a group the bins of
+// consecutive az lie on one ring-pair diagonal, one ring apart, and so do the
+// class's z-members of one column and half (one ring shift apart), so the
+// group reaches, for each column and half, one run of consecutive floats of
+// the diagonal sinogram: float u = s + az sums the products of the entries
+// with the member of shift s.  The runs of a chunk of (group, column-half)
+// pairs are laid out one float per lane, and each float is added once.
+constexpr int kFwdGroups = 225;   // 25 transaxial pairs x 9 axial diagonals
+constexpr int kXsPad = 4;         // zero guards on both sides of a column-half's member values
+constexpr int kFwdSlots = 1536;   // floats of the runs of one chunk of pairs
+struct MmaFwdRuns {
+    float gt[1152];                     // [group][az + 2]: the tile's entries (1125 used; cleared as float4)
+    float xs[384];                      // [column-half][kXsPad + ring shift]: the members' values, 0 if the tile misses them
+    unsigned short gl[kFwdGroups + 3];  // groups present in the tile
+    unsigned int gmask[8];
+    int mpos[64];                       // per pair of the chunk: the bin of its run's first valid float
+    int minfo[64];                      // group | column-half << 8 | (u + 2) << 12 | mirror << 22
+    int mstart[65];                     // exclusive prefix of the runs' valid lengths
+    unsigned char mmap[kFwdSlots];      // float slot -> pair of the chunk
+};
+
 // classes with images: for each transaxial neighbour pair p = a_t * 5 + b_t
 // of the tile and column ci of the class, entry p * 8 + ci holds the pair's
 // transaxial bin seen from the column times NR^2 (the bin's first ring pair),
 // with bit 31 set when the column's image puts photon 2's crystal first.
 // The projections also keep, per list entry, the start of its ring-pair
 // diagonal for both photon orders (see the emission).
-// The forward's emission by runs: a tile's entries grouped by transaxial
-// neighbour pair p and axial diagonal bz - az.  Along such a group the bins of
-// consecutive az lie on one ring-pair diagonal, one ring apart, and so do the
-// class's members of one column and half (one ring shift apart), so the group
-// reaches, for each column and half, one run of consecutive floats of the
-// diagonal sinogram: float u = s + az - az_lo sums the entries' products with
-// the member of shift s.  One atomic add per float of the run.
-constexpr int kFwdGroups = 225;   // 25 transaxial pairs x 9 axial diagonals
-struct MmaFwdRuns {
-    float gt[1152];                 // [group][az + 2]: the tile's entries (1125 used; cleared as float4)
-    float xs[128];                  // [column and half][ring shift]: the members' image values, 0 if the tile misses them
-    unsigned short gl[kFwdGroups + 3];  // groups present in the tile
-    unsigned int gmask[8];
-};
-
 struct MmaLds {
     union {
         MmaOps o;
         MmaList e;
-        MmaFwdRuns f;
     };
     int ptab[200];
     unsigned int dd[640];
+};
+
+// the forward: the runs over the spent operands (the list and its diagonal
+// starts serve classes too large for the runs)
+struct MmaLdsFwd {
+    union {
+        MmaOps o;
+        struct {
+            MmaList e;
+            unsigned int dd[640];
+        };
+        MmaFwdRuns f;
+    };
+    int ptab[200];
 };
 
 // the adjoint with the table gradient keeps the operands past the emission
@@ -1251,6 +1293,11 @@ struct MmaLdsBuild {
     int2 bndc[125];  // by column: the r_i range (classes with images)
     int bslot[25];
     int ptab[200];
+    // the emission: per (entry, column-half) pair of a chunk, its accumulator
+    // cell, group, valid ring shifts and value
+    int mcell[64];
+    int minfo[64];   // group | mirror << 5 | first valid shift << 8 | end << 16
+    float mt[64];
 };
 
 template <int MODE>
@@ -1262,7 +1309,15 @@ struct MmaLdsOf<kModeAdjGrad> {
     typedef MmaLdsGrad type;
 };
 template <>
+struct MmaLdsOf<kModeFwd> {
+    typedef MmaLdsFwd type;
+};
+template <>
 struct MmaLdsOf<kModeCount> {
+    typedef MmaLdsBuild type;
+};
+template <>
+struct MmaLdsOf<kModeFill> {
     typedef MmaLdsBuild type;
 };
 
@@ -1404,9 +1459,10 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
         }
         __builtin_amdgcn_wave_barrier();
         if constexpr (MODE == kModeFwd) {
-          if (cl.z <= 128) {
+          if (cl.z <= 256 && cl.z / nzc <= 16) {
             // the forward: emission by runs (see MmaFwdRuns); the operands are spent
-            const int nhg = cl.z / nzc;  // columns x halves
+            const int nhg = cl.z / nzc;          // columns x halves
+            const int XS = nzc + 2 * kXsPad;     // a column-half's row of member values
             float4* g4 = (float4*)L.f.gt;
             for (int i = lane; i < 288; i += 64) g4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (lane < 8) L.f.gmask[lane] = 0u;
@@ -1448,7 +1504,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             __builtin_amdgcn_wave_barrier();
             if (lane < 8) {  // list the present groups
                 const unsigned int w = L.f.gmask[lane];
-                int pre = __popc(w), incl = pre;
+                const int pre = __popc(w);
+                int incl = pre;
                 for (int off = 1; off < 8; off <<= 1) {
                     const int o = __shfl_up(incl, off, 8);
                     if (lane >= off) incl += o;
@@ -1461,61 +1518,89 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                                                            __popc(L.f.gmask[3]) + __popc(L.f.gmask[4]) + __popc(L.f.gmask[5]) +
                                                            __popc(L.f.gmask[6]) + __popc(L.f.gmask[7]));
             const int npair = ngr * nhg;
-            const int NR = G.NR, o = lane & 15;
+            const int NR = G.NR;
+            // pairs per chunk: their runs (at most nzc + 4 floats each) fit the slot map
+            const int cp = kFwdSlots / (nzc + 4) < 64 ? kFwdSlots / (nzc + 4) : 64;
             for (int bb = 0; bb < nb; ++bb) {
-                // the members' values by (column and half, ring shift)
-                for (int sm = lane; sm < 128; sm += 64) {
-                    float xv = 0.0f;
+                // the members' values by (column-half, ring shift), zero guards around
+                for (int i = lane; i < nhg * XS; i += 64) L.f.xs[i] = 0.0f;
+                __builtin_amdgcn_wave_barrier();
+                for (int sm0 = 0; sm0 < cl.z; sm0 += 64) {
+                    const int sm = sm0 + lane;
                     bool ok = false;
                     if (sm < cl.z) {
                         const int hg = sm / nzc, s2 = sm - hg * nzc;
-                        const bool mh = mir && (hg & 1);
-                        const int sh = mh ? nzc - 1 - s2 : s2;
+                        const int sh = (mir && (hg & 1)) ? nzc - 1 - s2 : s2;
                         ok = r1 + sh >= 0 && r1 + sh < NR && r2 + sh >= 0 && r2 + sh < NR;
-                        if (ok) xv = S.xm[(int64_t)(cl.y + sm) * 8 + bb];
-                        L.f.xs[hg * nzc + sh] = xv;
+                        if (ok) L.f.xs[hg * XS + kXsPad + sh] = S.xm[(int64_t)(cl.y + sm) * 8 + bb];
                     }
                     if (bb == 0) n_vt += __popcll(__ballot(ok)) * (lane == 0);
                 }
-                __builtin_amdgcn_wave_barrier();
                 float* ob = A.y + (int64_t)bb * G.nbins;
-                for (int base = 0; base < npair; base += 4) {
-                    const int pi = base + (lane >> 4);
-                    if (pi >= npair) continue;
-                    const int gq = pi / nhg, hg = pi - gq * nhg;
-                    const int g = L.f.gl[gq];
-                    const int p = g / 9, dz = g - p * 9 - 4;
-                    const int azlo = dz > 0 ? -2 : -2 - dz, azhi = dz > 0 ? 2 - dz : 2;
-                    if (o >= nzc + azhi - azlo) continue;
-                    const int u = o + azlo;  // ring shift plus az
-                    const int ri = r1 + u, rj = r2 + dz + u;
-                    if ((unsigned)ri >= (unsigned)NR || (unsigned)rj >= (unsigned)NR) continue;
-                    float val = 0.0f;
-                    for (int az = azlo; az <= azhi; ++az) {
-                        const int sh = u - az;
-                        if (sh >= 0 && sh < nzc) val += L.f.gt[g * 5 + az + 2] * L.f.xs[hg * nzc + sh];
+                for (int c0 = 0; c0 < npair; c0 += cp) {
+                    __builtin_amdgcn_wave_barrier();
+                    // one lane per pair of the chunk: its run's valid part, first bin and direction
+                    int cnt = 0;
+                    if (lane < cp && c0 + lane < npair) {
+                        const int pi = c0 + lane;
+                        const int gq = pi / nhg, hg = pi - gq * nhg;
+                        const int g = L.f.gl[gq];
+                        const int p = g / 9, dz = g - p * 9 - 4;
+                        const int azlo = dz > 0 ? -2 : -2 - dz;
+                        const int len = nzc + 4 - (dz < 0 ? -dz : dz);
+                        // float o of the run is u = o + azlo = shift + az: rings r1 + u and r2 + dz + u
+                        int ulo = -r1 > -r2 - dz ? -r1 : -r2 - dz;
+                        int uhi = NR - r1 < NR - r2 - dz ? NR - r1 : NR - r2 - dz;
+                        ulo = ulo > azlo ? ulo : azlo;
+                        uhi = uhi < azlo + len ? uhi : azlo + len;
+                        cnt = uhi > ulo ? uhi - ulo : 0;
+                        const bool mh = mir && (hg & 1);
+                        int tb;
+                        bool sw;
+                        if (imgs) {
+                            const int v = L.ptab[(p << 3) + (mir ? hg >> 1 : hg)];
+                            sw = v < 0;
+                            tb = v & 0x7fffffff;
+                        } else {
+                            int ga = g1 + p / 5 - 2, gb = g2 + p % 5 - 2;
+                            ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
+                            gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
+                            sw = ga > gb;
+                            tb = (sw ? tbin32(gb, ga, G.Nc) : tbin32(ga, gb, G.Nc)) * (NR * NR);
+                        }
+                        const int ri = r1 + ulo, rj = r2 + dz + ulo;
+                        int rb = sw ? rj : ri, rc = sw ? ri : rj;  // the bin's rings, photon order of the bin
+                        if (mh) {
+                            rb = NR - 1 - rb;
+                            rc = NR - 1 - rc;
+                        }
+                        L.f.mpos[lane] = cnt > 0 ? tb + diag32(rb, rc, NR) : 0;
+                        L.f.minfo[lane] = g | (hg << 8) | ((ulo + 2) << 12) | (mh ? 1 << 22 : 0);
                     }
-                    if (val == 0.0f) continue;
-                    const bool mh = mir && (hg & 1);
-                    int tb;
-                    bool sw;
-                    if (imgs) {
-                        const int v = L.ptab[(p << 3) + (mir ? hg >> 1 : hg)];
-                        sw = v < 0;
-                        tb = v & 0x7fffffff;
-                    } else {
-                        int ga = g1 + p / 5 - 2, gb = g2 + p % 5 - 2;
-                        ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
-                        gb = gb < 0 ? gb + G.Nc : (gb >= G.Nc ? gb - G.Nc : gb);
-                        sw = ga > gb;
-                        tb = (sw ? tbin32(gb, ga, G.Nc) : tbin32(ga, gb, G.Nc)) * (NR * NR);
+                    int incl = cnt;
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const int o = __shfl_up(incl, off, 64);
+                        if (lane >= off) incl += o;
                     }
-                    int rb = sw ? rj : ri, rc = sw ? ri : rj;  // the bin's rings, photon order of the bin
-                    if (mh) {
-                        rb = NR - 1 - rb;
-                        rc = NR - 1 - rc;
+                    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+                    const int st0 = incl - cnt;
+                    L.f.mstart[lane] = st0;
+                    for (int t = 0; t < cnt; ++t) L.f.mmap[st0 + t] = (unsigned char)lane;
+                    __builtin_amdgcn_wave_barrier();
+                    for (int k = lane; k < total; k += 64) {
+                        const int j = L.f.mmap[k];
+                        const int info = L.f.minfo[j];
+                        const int t = k - L.f.mstart[j];
+                        const int g = info & 0xff, hg = (info >> 8) & 0xf;
+                        const int u = ((info >> 12) & 0x3ff) - 2 + t;
+                        const float* gv = &L.f.gt[g * 5];
+                        const float* xv = &L.f.xs[hg * XS + kXsPad + u + 2];   // shift u - az at az = a - 2
+                        float val = 0.0f;
+#pragma unroll
+                        for (int a = 0; a < 5; ++a) val += gv[a] * xv[-a];
+                        if (val != 0.0f) atomicAdd(&ob[L.f.mpos[j] + ((info >> 22) ? -t : t)], val);
                     }
-                    atomicAdd(&ob[tb + diag32(rb, rc, NR)], val);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -1523,7 +1608,21 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
           }
         }
         // live entries (crystals distinct, inside the 25 x 25 tile, non-zero) and
-        // the transaxial part of their bins
+        // the transaxial part of their bins.  The table gradient also needs the
+        // zero entries in a row a of a non-zero column of U or a column b of a
+        // non-zero column of X: dU = X dT^T and dV = W^T U dT read d loss / d T
+        // there (a zero table entry still has a gradient).
+        unsigned int uzm = 0u, xzm = 0u;
+        if constexpr (kGrad) {
+            bool nu = false, nx = false;
+            if (lane < 25)
+                for (int p = 0; p < 16; ++p) {
+                    nu |= L.o.U[p][lane] != 0.0f;
+                    nx |= L.o.X[p][lane] != 0.0f;
+                }
+            uzm = (unsigned int)__ballot(nu);
+            xzm = (unsigned int)__ballot(nx);
+        }
         const int bq = m;
         const int bt = bq / 5 - 2, bz = bq % 5 - 2;
         int gb = g2 + bt;
@@ -1539,7 +1638,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             key[j] = 0;
             int ga = g1 + a / 5 - 2;
             ga = ga < 0 ? ga + G.Nc : (ga >= G.Nc ? ga - G.Nc : ga);
-            if (bq >= 25 || a >= 25 || ct[j] == 0.0f || ga == gb) continue;
+            if (bq >= 25 || a >= 25 || ga == gb) continue;
+            if (ct[j] == 0.0f && !(kGrad && (((uzm >> a) | (xzm >> bq)) & 1u))) continue;
             const bool sw = ga > gb;
             const int tb_ = (int)tbin_of(sw ? gb : ga, sw ? ga : gb, G.Nc);
             if (MODE == kModeCount || MODE == kModeFill) {
@@ -1664,13 +1764,74 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
             }
         }
-        // emission.  With at most 128 members, in passes of up to 64: lane =
+        if constexpr (MODE == kModeCount || MODE == kModeFill) {
+          if (cl.z <= 128 && nzc <= 8) {
+            // the build: each (entry, column-half) pair reaches one accumulator
+            // cell, whose nzc members (one per ring shift) are adjacent floats.
+            // Chunks of 64 pairs: one lane per pair finds the cell and the ring
+            // shifts for which the entry's rings exist; then eight lanes per pair
+            // add the entry to its members' floats.
+            const int ngrp = cl.z / nzc;
+            const int NRr = G.NR + nzc - 1, NR = G.NR;
+            const int npair = total * ngrp;
+            // members' shifts whose central rings exist: counted (voxel, tile) pairs
+            {
+                const int lo = (-r1 > -r2 ? -r1 : -r2) > 0 ? (-r1 > -r2 ? -r1 : -r2) : 0;
+                const int hi = (NR - r1 < NR - r2 ? NR - r1 : NR - r2) < nzc ? (NR - r1 < NR - r2 ? NR - r1 : NR - r2) : nzc;
+                n_vt += (unsigned long long)(hi > lo ? (hi - lo) * ngrp : 0) * (lane == 0);
+            }
+            for (int c0 = 0; c0 < npair; c0 += 64) {
+                __builtin_amdgcn_wave_barrier();
+                const int pi = c0 + lane;
+                if (pi < npair) {
+                    const int e = pi / ngrp, g = pi - e * ngrp;
+                    const int mm = L.e.m[e], key = L.e.key[e];
+                    const bool mh = mir && (g & 1);
+                    const int ai = r1 + (mm & 7) - 2, bj = r2 + ((mm >> 3) & 7) - 2;
+                    bool sw = (mm >> 6) & 1;
+                    if (imgs) {  // the pair's photon order seen from the group's column
+                        const int ab = L.e.ab[e];
+                        const int v = L.ptab[((ab & 0xff) * 13 >> 6) * 40 + ((ab >> 8) * 13 >> 6) * 8 + (mir ? g >> 1 : g)];
+                        sw = v < 0;
+                    }
+                    const int u = sw ? bj : ai, w = sw ? ai : bj;  // (r_i, r_j) for the reference voxel
+                    const int i = mh ? NR - 1 - u : u + nzc - 1, j = mh ? NR - 1 - w : w + nzc - 1;
+                    // shifts s with r1 + s, r2 + s, ai + s, bj + s inside the scanner
+                    int lo = -r1 > -r2 ? -r1 : -r2;
+                    lo = lo > -ai ? lo : -ai;
+                    lo = lo > -bj ? lo : -bj;
+                    lo = lo > 0 ? lo : 0;
+                    int hi = NR - r1 < NR - r2 ? NR - r1 : NR - r2;
+                    hi = hi < NR - ai ? hi : NR - ai;
+                    hi = hi < NR - bj ? hi : NR - bj;
+                    hi = hi < nzc ? hi : nzc;
+                    L.mcell[lane] = (key * NRr + i) * NRr + j;
+                    L.minfo[lane] = g | (mh ? 32 : 0) | ((lo > hi ? hi : lo) << 8) | (hi << 16);
+                    L.mt[lane] = L.e.t[e];
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int nq = npair - c0 < 64 ? npair - c0 : 64;
+                for (int q0 = 0; q0 < nq; q0 += 8) {
+                    const int q = q0 + (lane >> 3), s2 = lane & 7;
+                    if (q >= nq || s2 >= nzc) continue;
+                    const int info = L.minfo[q];
+                    const int g = info & 31;
+                    const int sh = (info & 32) ? nzc - 1 - s2 : s2;  // the reference-half voxel's shift
+                    if (sh < ((info >> 8) & 0xff) || sh >= (info >> 16)) continue;
+                    acc_add(S, (int64_t)(cl.y + g * nzc) * S.dense_slab + L.mcell[q] * nzc + s2, L.mt[q], flag);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            continue;
+          }
+        }
+        // emission.  With at most 256 members, in passes of up to 64: lane =
         // (entry, member), the member fixed per lane (lane mod the pass's member
         // count rounded up to a power of two); projection sinograms in the
         // diagonal layout, so a lane group touches consecutive floats.
         // Otherwise member by member.
         const int npass = (cl.z + 63) >> 6;
-        if (npass <= 2) {
+        if (npass <= 4) {
             int lg = 0;
             while ((1 << lg) < (cl.z < 64 ? cl.z : 64)) ++lg;
             const int msk = (1 << lg) - 1;
@@ -1702,8 +1863,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             }
             n_vt += __popcll(__ballot(mok && lane <= msk));
             // build: the lane's group's accumulators, [slot][i][j][s2] (members interleaved)
-            float* dense = (MODE == kModeCount || MODE == kModeFill) && mok
-                               ? S.dense + (int64_t)(cl.y + g * nzc) * S.dense_slab : nullptr;
+            const int64_t dbase = (int64_t)(cl.y + g * nzc) * S.dense_slab;
             const int NRr = G.NR + nzc - 1;
             // one list entry (code, value, key, place): forward atomics, or the
             // adjoint (and gradient) products
@@ -1862,7 +2022,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                     const float cv = t;
                     if (e + step < total) ld(e + step, mm, t, key, ab);
                     const int c = locate(cm, ck, ca);
-                    if (c >= 0) atomicAdd(&dense[c], cv);
+                    if (c >= 0) acc_add(S, dbase + c, cv, flag);
                 }
             }
             if constexpr (kGrad) {
@@ -1877,7 +2037,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             }
             }
         } else if (imgs || mir) {
-            flag |= kStatGeom;  // classes with images have at most 128 members (the plan keeps them so)
+            flag |= kStatGeom;  // classes with images have at most 256 members (the plan keeps them so)
         } else {
         if constexpr (kGrad)
             for (int e = lane; e < total; e += 64) L.Gl[e] = 0.0f;
@@ -1893,7 +2053,7 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 acc[bb] = 0.0;
                 xv[bb] = ((MODE == kModeFwd || kGrad) && bb < nb) ? (double)(kGrad ? A.xt : A.x)[(int64_t)bb * G.nvox + v] : 0.0;
             }
-            float* dense = (MODE == kModeCount || MODE == kModeFill) ? S.dense + (int64_t)cl.y * S.dense_slab : nullptr;
+            const int64_t dbase = (int64_t)cl.y * S.dense_slab;
             const int NRr = G.NR + nzc - 1;
             for (int e = lane; e < total; e += 64) {
                 const int mm = L.e.m[e];
@@ -1920,9 +2080,10 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if constexpr (kGrad) L.Gl[e] += (float)gv;
                     }
                 } else {
-                    atomicAdd(&dense[(((int64_t)L.e.key[e] * NRr + ri - me.y + nzc - 1) * NRr + rj - me.y + nzc - 1) * nzc +
-                                     me.y],
-                              t);
+                    acc_add(S,
+                            dbase + (((int64_t)L.e.key[e] * NRr + ri - me.y + nzc - 1) * NRr + rj - me.y + nzc - 1) * nzc +
+                                me.y,
+                            t, flag);
                 }
             }
             if (kAdj) {
@@ -2112,7 +2273,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
     const int64_t nrr = (int64_t)NR * NR;
     const int nzc = A.cls[vb].w + 1, NRr = NR + nzc - 1;  // the group's members, interleaved
-    float* dense = S.dense + (int64_t)grp * S.dense_slab;
+    const int64_t dbase = (int64_t)grp * S.dense_slab;   // the group's cells in S.dense
     const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
     // the column's slots in its bin order: the reference slot, and whether the
     // image swaps the photons (the ring pair then reads the reference transposed)
@@ -2205,8 +2366,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
             }
             col = rlo[lo] + (f - rpre[lo]);
             const int di = rbase[lo] + col * nzc;
-            a = dense[di];
-            if (MODE != kCompactChunks) dense[di] = 0.0f;  // leave the accumulator clean
+            a = acc_take(S, dbase + di, MODE != kCompactChunks);  // leave the accumulator clean
         }
         const bool keep = a > 0.0f && (double)a >= A.threshold;
         const unsigned long long m = __ballot(keep);
@@ -2275,7 +2435,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
     if (chunk == 0 && tid < nzc) A.stage_nch[A.mem[grp + tid].w] = (int)((nrows + kRowsC - 1) / kRowsC);
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
-    float* dense = S.dense + (int64_t)grp * S.dense_slab;
+    const int64_t dbase = (int64_t)grp * S.dense_slab;  // the group's cells in S.dense
     const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
     const int* order = S.slot_order + (int64_t)grp * S.cap_slots;
     const int64_t bref = (int64_t)A.cls[vb].y * S.cap_slots * S.band_rows;
@@ -2386,13 +2546,12 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
             }
             j = rlo[lo] + (f - rpre[lo]);
             const int i = (int)((q0 + lo) % NRr);
-            float* cell = dense + rcell[lo] + j * nzc;
+            const int64_t cell = dbase + rcell[lo] + j * nzc;
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 a[s] = 0.0f;
                 if (s < nzc) {
-                    a[s] = cell[s];
-                    cell[s] = 0.0f;  // leave the accumulator clean
+                    a[s] = acc_take(S, cell + s, true);  // leave the accumulator clean
                     const bool ok = i >= c - s && i <= NR - 1 + c - s && j >= c - s && j <= NR - 1 + c - s;
                     if (ok && a[s] > 0.0f && (double)a[s] >= A.threshold) keep |= 1u << s;
                 }

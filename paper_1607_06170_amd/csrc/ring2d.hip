@@ -250,9 +250,84 @@ __global__ void __launch_bounds__(kBlock2D) k_voxel2d(Ring2D G, VoxArgs2D A) {
         for (int bb = 0; bb < A.batch && bb < 8; ++bb) xt_b[bb] = (double)A.x[(int64_t)bb * G.nvox + v];
     }
 
+    int range_hit = 0;
+    // the lines (s1, s2) of weight w spread into the bins (g1 + a, g2 + b)
+    auto spread = [&](int s1, int s2, double w) {
+        const float wf = (float)w;
+        range_hit |= L.uflag[s1] | L.uflag[s2];
+        const float* U1 = L.U + kNb * s1;
+        const float* U2 = L.U + kNb * s2;
+        const int g1 = s1 / G.P, g2 = s2 / G.P;
+#pragma unroll
+        for (int a = 0; a < kNb; ++a) {
+            const float u = U1[a];
+            if (MODE != kModeAdjGrad && u == 0.0f) continue;
+            int i = g1 + a - 2;
+            i = i < 0 ? i + G.Nc : (i >= G.Nc ? i - G.Nc : i);
+#pragma unroll
+            for (int bq = 0; bq < kNb; ++bq) {
+                const float vv = U2[bq];
+                if (MODE != kModeAdjGrad && vv == 0.0f) continue;
+                int j = g2 + bq - 2;
+                j = j < 0 ? j + G.Nc : (j >= G.Nc ? j - G.Nc : j);
+                if (i == j) continue;
+                const int64_t bin = pair_bin(i, j, G.Nc);
+                const float t = tile_product(G.precision, wf, u, vv);
+                if (t != 0.0f) {
+                    if (G.det) {  // exact integer sums: independent of the order of arrival
+                        range_hit |= fix62_ok(t) ? 0 : 1;
+                        atomicAdd((unsigned long long*)&L.acc[bin], fix62(t));
+                    } else {
+                        atomicAdd(&L.acc[bin], (double)t);
+                    }
+                }
+                if (MODE == kModeAdjGrad) {
+                    double gsum = 0.0;
+                    for (int bb = 0; bb < A.batch && bb < 8; ++bb)
+                        gsum += xt_b[bb] * (double)A.y[(int64_t)bb * G.nbins + bin];
+                    const double gw = gsum * w;
+                    const int su = L.src[kNb * s1 + a], sv = L.src[kNb * s2 + bq];
+                    if (su >= 0 && gw != 0.0) atomicAdd(&L.gpart[su], gw * (double)vv);
+                    if (sv >= 0 && gw != 0.0) atomicAdd(&L.gpart[sv], gw * (double)u);
+                }
+            }
+        }
+    };
+    if (G.homog_k > 0) {
+        // Eq.11 with finite k: line i at direction theta_i = pi i / k, weight 1 / k,
+        // ends on the sub-segments whose direction intervals hold theta_i and
+        // theta_i + pi (none through a gap).  The interval is found by bisection
+        // on the unwrapped starts; of the candidates around it the last one (in
+        // sub-segment order) whose half-open interval holds the direction wins.
+        const double w = 1.0 / G.homog_k;
+        auto hit = [&](double th) -> int {
+            const double x = lo0 + wrap_2pi(th - lo0);
+            int lo = 0, hi = G.nseg;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (L.unw[mid] <= x) lo = mid + 1;
+                else hi = mid;
+            }
+            int found = -1;
+            for (int d = -1; d <= 1; ++d) {
+                int s = lo - 1 + d;
+                s = s < 0 ? s + G.nseg : (s >= G.nseg ? s - G.nseg : s);
+                const int b = s / segs_per_block, k = s - b * segs_per_block;
+                const double lo_s = L.th[b * M1 + k];
+                const double len_s = wrap_2pi(L.th[b * M1 + k + 1] - lo_s);
+                if (wrap_2pi(th - lo_s) < len_s && s > found) found = s;
+            }
+            return found;
+        };
+        for (int i = tid; i < G.homog_k; i += bs) {
+            const double th = kPi * i / G.homog_k;
+            const int h1 = hit(th), h2 = hit(th + kPi);
+            if (h1 < 0 || h2 < 0) continue;
+            spread(h1 < h2 ? h1 : h2, h1 < h2 ? h2 : h1, w);
+        }
+    } else
     // homogenization sweep: thread per s1, candidates s2 found by bisection on
     // the unwrapped interval starts
-    int range_hit = 0;
     for (int s1 = tid; s1 < G.nseg; s1 += bs) {
         const int b1 = s1 / segs_per_block, k1 = s1 - b1 * segs_per_block;
         const double lo1 = L.th[b1 * M1 + k1];
@@ -267,8 +342,6 @@ __global__ void __launch_bounds__(kBlock2D) k_voxel2d(Ring2D G, VoxArgs2D A) {
         }
         // x can sit an ulp below the first start after the wrap: start at segment 0
         const int j0 = lo > 0 ? lo - 1 : 0;
-        const float* U1 = L.U + kNb * s1;
-        const int g1 = s1 / G.P;
         for (int c = 0; c < G.nseg; ++c) {
             const int jj = j0 + c;
             const int s2 = jj >= G.nseg ? jj - G.nseg : jj;
@@ -280,42 +353,58 @@ __global__ void __launch_bounds__(kBlock2D) k_voxel2d(Ring2D G, VoxArgs2D A) {
             const double len2 = wrap_2pi(L.th[b2 * M1 + k2 + 1] - lo2);
             const double ov = overlap_opposite(lo1, len1, lo2, len2);
             if (!(ov > kEpsOverlap)) continue;
-            const double w = ov / kPi;
-            const float wf = (float)w;
-            range_hit |= L.uflag[s1] | L.uflag[s2];
-            const float* U2 = L.U + kNb * s2;
-            const int g2 = s2 / G.P;
-#pragma unroll
-            for (int a = 0; a < kNb; ++a) {
-                const float u = U1[a];
-                if (MODE != kModeAdjGrad && u == 0.0f) continue;
-                int i = g1 + a - 2;
-                i = i < 0 ? i + G.Nc : (i >= G.Nc ? i - G.Nc : i);
-#pragma unroll
-                for (int bq = 0; bq < kNb; ++bq) {
-                    const float vv = U2[bq];
-                    if (MODE != kModeAdjGrad && vv == 0.0f) continue;
-                    int j = g2 + bq - 2;
-                    j = j < 0 ? j + G.Nc : (j >= G.Nc ? j - G.Nc : j);
-                    if (i == j) continue;
-                    const int64_t bin = pair_bin(i, j, G.Nc);
-                    const float t = tile_product(G.precision, wf, u, vv);
-                    if (t != 0.0f) atomicAdd(&L.acc[bin], (double)t);
-                    if (MODE == kModeAdjGrad) {
-                        double gsum = 0.0;
-                        for (int bb = 0; bb < A.batch && bb < 8; ++bb)
-                            gsum += xt_b[bb] * (double)A.y[(int64_t)bb * G.nbins + bin];
-                        const double gw = gsum * w;
-                        const int su = L.src[kNb * s1 + a], sv = L.src[kNb * s2 + bq];
-                        if (su >= 0 && gw != 0.0) atomicAdd(&L.gpart[su], gw * (double)vv);
-                        if (sv >= 0 && gw != 0.0) atomicAdd(&L.gpart[sv], gw * (double)u);
-                    }
-                }
-            }
+            spread(s1, s2, ov / kPi);
         }
     }
     if (range_hit) atomicOr(A.status, kStatRange);
     __syncthreads();
+    if (G.det) {  // the integer sums back to FP64, in place
+        for (int64_t i = tid; i < G.nbins; i += bs) L.acc[i] = unfix62(((const unsigned long long*)L.acc)[i]);
+        __syncthreads();
+    }
+
+    if (G.top_n > 0) {
+        // truncation of the extended bins (Sec 3.3): in every sinogram view, the
+        // voxel keeps its top_n largest bins (ties: the lower bin).  View v holds
+        // the pairs i < j with (i + j) mod Nc in {2v, 2v + 1}: one thread per view
+        // finds the cut (the top_n-th largest) in one pass, then clears the rest.
+        const int nview = G.Nc / 2;
+        for (int v = tid; v < nview; v += bs) {
+            double cv[kTopNMax];
+            int cb[kTopNMax];
+            int n = 0;
+            for (int q = 0; q < 4; ++q) {  // i + j = s, s in {2v, 2v+1, 2v+Nc, 2v+1+Nc}
+                const int s = 2 * v + (q & 1) + (q >> 1) * G.Nc;
+                for (int i = s - (G.Nc - 1) > 0 ? s - (G.Nc - 1) : 0; 2 * i < s; ++i) {
+                    const int64_t bin = pair_bin(i, s - i, G.Nc);
+                    const double a = L.acc[bin];
+                    if (!(a > 0.0)) continue;
+                    // insert (a, bin) into the descending list of at most top_n
+                    if (n == G.top_n && !(a > cv[n - 1] || (a == cv[n - 1] && bin < cb[n - 1]))) continue;
+                    int k = n < G.top_n ? n++ : n - 1;
+                    while (k > 0 && (a > cv[k - 1] || (a == cv[k - 1] && bin < cb[k - 1]))) {
+                        cv[k] = cv[k - 1];
+                        cb[k] = cb[k - 1];
+                        --k;
+                    }
+                    cv[k] = a;
+                    cb[k] = (int)bin;
+                }
+            }
+            if (n < G.top_n) continue;  // the view has at most top_n bins
+            const double cut = cv[n - 1];
+            const int cutb = cb[n - 1];
+            for (int q = 0; q < 4; ++q) {
+                const int s = 2 * v + (q & 1) + (q >> 1) * G.Nc;
+                for (int i = s - (G.Nc - 1) > 0 ? s - (G.Nc - 1) : 0; 2 * i < s; ++i) {
+                    const int64_t bin = pair_bin(i, s - i, G.Nc);
+                    const double a = L.acc[bin];
+                    if (a < cut || (a == cut && bin > cutb)) L.acc[bin] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
 
     if (MODE == kModeCount) {
         double cnt = 0.0;

@@ -16,7 +16,7 @@
 namespace psf {
 
 // integral over [u0, u1] of exp(-mu * clip((c - u) / sa, 0, smax)) du
-__device__ static double edge_integral(double c, double u0, double u1, double sa, double smax, double mu) {
+__host__ __device__ static double edge_integral(double c, double u0, double u1, double sa, double smax, double mu) {
     const double reach = smax * sa;  // lateral travel over the full depth
     double tot = 0.0;
     double lo = fmax(u0, c), hi = u1;  // photon already past the edge c: factor 1
@@ -31,7 +31,7 @@ __device__ static double edge_integral(double c, double u0, double u1, double sa
 }
 
 // mean first-interaction probability in crystal a over sub-position [u0, u1)
-__device__ static double sub_response(double alpha, double u0, double u1, int a, double lam, double L, double mu) {
+__host__ __device__ static double sub_response(double alpha, double u0, double u1, int a, double lam, double L, double mu) {
     if (a < 0) return 0.0;
     if (alpha == 0.0) return a == 0 ? 1.0 - exp(-mu * L) : 0.0;
     const double sa = sin(alpha), smax = L / cos(alpha);
@@ -49,6 +49,18 @@ __global__ void k_table_2d(int n_rows, int P, double step_deg, double lam, doubl
         const double alpha = row * step_deg * kPi / 180.0;
         const double u0 = p * lam / P, u1 = (p + 1) * lam / P;
         out[i] = (float)sub_response(alpha, u0, u1, a, lam, L, mu);
+    }
+}
+
+// the same entries in FP64 on the host, one after the other
+void table_2d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out) {
+    const int n = n_rows * P * kNb;
+    for (int i = 0; i < n; ++i) {
+        const int a = i % kNb - 2;
+        const int p = (i / kNb) % P;
+        const int row = i / (kNb * P);
+        const double alpha = row * step_deg * kPi / 180.0;
+        out[i] = sub_response(alpha, p * g.pitch_t / P, (p + 1) * g.pitch_t / P, a, g.pitch_t, g.depth, g.mu);
     }
 }
 

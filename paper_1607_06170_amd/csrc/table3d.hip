@@ -20,7 +20,7 @@ struct GL16 {
 };
 
 // integral over uz in [uz0, uz1] at fixed ut
-__device__ static double inner_uz3(double tt, double tz, double ut, double uz0, double uz1, int at, int az,
+__host__ __device__ static double inner_uz3(double tt, double tz, double ut, double uz0, double uz1, int at, int az,
                                    double lt, double lz, double L, double mu) {
     double ta, tb;
     if (tt == 0.0) {
@@ -62,20 +62,17 @@ __device__ static double inner_uz3(double tt, double tz, double ut, double uz0, 
     return i1 - i2;
 }
 
-__global__ void k_table_3d(int n_rows, int P, double step_deg, double lt, double lz, double L, double mu, GL16 gl,
-                           float* out) {
-    const int64_t n = (int64_t)n_rows * n_rows * P * P * kNb * kNb;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// entry i of the table (layout of psf_table, 3D), FP64
+__host__ __device__ static double table3_entry(int64_t i, int n_rows, int P, double step_deg, double lt, double lz,
+                                               double L, double mu, const GL16& gl) {
+    {
         const int az = (int)(i % kNb) - 2;
         const int at = (int)((i / kNb) % kNb) - 2;
         const int pz = (int)((i / (kNb * kNb)) % P);
         const int pt = (int)((i / (kNb * kNb * P)) % P);
         const int rz = (int)((i / ((int64_t)kNb * kNb * P * P)) % n_rows);
         const int rt = (int)(i / ((int64_t)kNb * kNb * P * P * n_rows));
-        if (at < 0 || az < 0) {
-            out[i] = 0.0f;
-            continue;
-        }
+        if (at < 0 || az < 0) return 0.0;
         const double alt = rt * step_deg * kPi / 180.0, alz = rz * step_deg * kPi / 180.0;
         const double tt = rt == 0 ? 0.0 : tan(alt), tz = rz == 0 ? 0.0 : tan(alz);
         const double ut0 = pt * lt / P, ut1 = (pt + 1) * lt / P;
@@ -119,8 +116,15 @@ __global__ void k_table_3d(int n_rows, int P, double step_deg, double lt, double
             for (int q = 0; q < 16; ++q) s += gl.w[q] * inner_uz3(tt, tz, m + h * gl.x[q], uz0, uz1, at, az, lt, lz, L, mu);
             tot += h * s;
         }
-        out[i] = (float)(tot / ((ut1 - ut0) * (uz1 - uz0)));
+        return tot / ((ut1 - ut0) * (uz1 - uz0));
     }
+}
+
+__global__ void k_table_3d(int n_rows, int P, double step_deg, double lt, double lz, double L, double mu, GL16 gl,
+                           float* out) {
+    const int64_t n = (int64_t)n_rows * n_rows * P * P * kNb * kNb;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)table3_entry(i, n_rows, P, step_deg, lt, lz, L, mu, gl);
 }
 
 // Gauss-Legendre nodes on [-1, 1]: Newton's method on the Legendre recurrence
@@ -152,6 +156,12 @@ static GL16 gauss_legendre16() {
         g.w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
     return g;
+}
+
+void table_3d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out) {
+    const int64_t n = (int64_t)n_rows * n_rows * P * P * kNb * kNb;
+    const GL16 gl = gauss_legendre16();
+    for (int64_t i = 0; i < n; ++i) out[i] = table3_entry(i, n_rows, P, step_deg, g.pitch_t, g.pitch_z, g.depth, g.mu, gl);
 }
 
 hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st) {

@@ -58,7 +58,10 @@ def test_table_parity(torch, oracle, cfg):
 
 
 def _compare_csr(oracle, rp, col, val, cols, flags, thr, vox):
-    """CSR from the GPU vs the oracle's thresholded columns for voxels vox."""
+    """CSR from the GPU vs the oracle's thresholded columns for voxels vox.
+    Patterns are compared both ways.  A row may differ only where the oracle
+    allows a second reading: in its bins within 1e-4 of the threshold, or, in
+    a row whose decisions the oracle flags as ties, in at most 1% of its bins."""
     rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
     sub = cols[vox]
     rpo, colo, valo = oracle.csr_from_columns(sub, thr)
@@ -70,6 +73,12 @@ def _compare_csr(oracle, rp, col, val, cols, flags, thr, vox):
         o = colo[rpo[r]:rpo[r + 1]]
         if exact_rows[r]:
             assert np.array_equal(g, o), f"row {vox[r]}: pattern differs"
+        else:
+            diff = np.setxor1d(g, o)
+            if ties[r]:
+                assert len(diff) <= 0.01 * max(len(np.union1d(g, o)), 1), f"row {vox[r]}: {len(diff)} bins differ"
+            else:
+                assert near[r, diff].all(), f"row {vox[r]}: bins away from the threshold differ"
         gv = val[rp[r]:rp[r + 1]]
         # every GPU entry's value against the oracle's dense column
         np.testing.assert_allclose(gv, sub[r, g], rtol=RTOL, atol=0, err_msg=f"row {vox[r]}")
@@ -85,6 +94,36 @@ def test_sysmat_full_config(torch, oracle, ref1):
     torch.cuda.synchronize()
     nnz = _compare_csr(oracle, rp, col, val, cols, flags, CFG["threshold"], np.arange(64 * 64))
     assert nnz == int(oracle.csr_from_columns(cols, CFG["threshold"])[0][-1])
+
+
+def test_deterministic_build(torch, oracle, ref1, refn):
+    """PSF_OPT_DETERMINISTIC: the tile entries summed as integers in units of
+    2^-62.  Two builds give the same CSR bit for bit, it meets the oracle as
+    the default build does (with the threshold, and without one down to
+    1e-9, far above the integer sums' rounding of at most 2^-63 per tile
+    entry), and the default build (FP64 atomics in LDS, summed in arrival
+    order) rounds to the same FP32 values within one ulp."""
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    thr = CFG["threshold"]
+    first = sc.build_psf_sysmat(t, threshold=thr, deterministic=True)
+    again = sc.build_psf_sysmat(t, threshold=thr, deterministic=True)
+    for a, b in zip(first, again):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    rp, col, val = first
+    nnz = _compare_csr(oracle, rp, col, val, cols, flags, thr, np.arange(64 * 64))
+    assert nnz == int(oracle.csr_from_columns(cols, thr)[0][-1])
+    rpf, colf, valf = (a.cpu().numpy() for a in sc.build_psf_sysmat(t, threshold=thr))
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    assert np.array_equal(rp, rpf) and np.array_equal(col, colf)
+    np.testing.assert_allclose(val, valf, rtol=1.2e-7, atol=0)
+    tab_n, cols_n, flags_n = refn
+    scn = _scanner(NARROW)
+    tn = scn.build_table(61, 4, 1.0)
+    rp, col, val = scn.build_psf_sysmat(tn, threshold=1e-9, deterministic=True)
+    _compare_csr(oracle, rp, col, val, cols_n, flags_n, 1e-9, np.arange(NARROW["nx"] * NARROW["ny"]))
 
 
 @pytest.mark.parametrize("vb,ve", [(0, 1), (5, 6), (1000, 1337), (4000, 4096)])
@@ -347,3 +386,184 @@ def test_degenerate_inputs(torch, oracle, ref1):
     assert tuple(q.shape) == (2, 0)
     xe = sc.project_adj(t, torch.zeros(2, 0, device="cuda"), events=ev)
     assert tuple(xe.shape) == (2, sc.n_voxels) and int((xe != 0).sum().item()) == 0
+
+
+def test_host_table_parity(torch, oracle):
+    """psf_build_table_host (FP64, host) against the oracle's table, 2D and 3D
+    (sampled rows), and against the device table rounded to FP32."""
+    from paper_1607_06170_amd import Scanner
+    sc = Scanner(S.CFG_2D)
+    host = sc.build_table_host(61, 4, 1.0).reshape(61, 4, 5)
+    ref = oracle.table_2d(S.CFG_2D).data
+    np.testing.assert_allclose(host, ref, rtol=1e-12, atol=1e-15)
+    dev = sc.build_table(61, 4, 1.0).data.cpu().numpy().reshape(61, 4, 5)
+    np.testing.assert_allclose(dev, host.astype(np.float32), rtol=1.2e-7, atol=0)   # one FP32 rounding apart at most
+    s3 = Scanner(S.CFG_3D_SMALL, mode3d=True)
+    h3 = s3.build_table_host(91, 4, 1.0).reshape(91, 91, 4, 4, 5, 5)
+    rng = np.random.default_rng(4)
+    rt, rz = rng.integers(0, 91, 30), rng.integers(0, 91, 30)
+    np.testing.assert_allclose(h3[rt, rz], oracle.table3_rows(S.CFG_3D_SMALL, rt, rz), rtol=1e-9, atol=1e-13)
+    d3 = s3.build_table(91, 4, 1.0).data.cpu().numpy().reshape(h3.shape)
+    # one FP32 rounding apart, but for entries below 1e-12 (differences of nearly equal exponentials, where
+    # the device's and the host's exp differ in the last FP64 bits)
+    np.testing.assert_allclose(d3, h3.astype(np.float32), rtol=1.2e-7, atol=1e-15)
+
+
+@pytest.mark.parametrize("k", [360, 5000])
+def test_finite_k_homogenization(torch, oracle, k):
+    """Eq.11 with k lines per voxel (homog_k = k): the CSR and the forward
+    projection against the oracle's finite-k mode, on the narrow-gap ring."""
+    cfg = NARROW
+    n = cfg["nx"] * cfg["ny"]
+    vox = np.arange(0, n, 7)
+    tab = oracle.table_2d(cfg)
+    cols, flags = oracle.columns_2d(cfg, tab, vox, homog_k=k)
+    full = np.zeros((n, cols.shape[1]))
+    full[vox] = cols
+    sc = _scanner(cfg)
+    t = sc.table_from(tab.data.astype(np.float32), 61, 4, 1.0)
+    rp, col, val = sc.build_psf_sysmat(t, threshold=0.0, homog_k=k)
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    for r, v in enumerate(vox):
+        g, gv = col[rp[v]:rp[v + 1]], val[rp[v]:rp[v + 1]]
+        assert np.array_equal(g, np.nonzero(cols[r])[0]), f"voxel {v}: pattern differs"
+        np.testing.assert_allclose(gv, cols[r, g], rtol=RTOL, atol=0)
+    x = np.zeros((1, n))
+    x[0, vox] = S.phantom_uniform(cfg, seed=3)[0, vox]
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda"), homog_k=k).cpu().numpy()
+    yo = x.astype(np.float32).astype(np.float64) @ full
+    np.testing.assert_allclose(y, yo, rtol=RTOL, atol=RTOL * 1e-2 * np.abs(yo).max())
+    # the finite-k matrix approaches the k -> infinity one: per voxel the line
+    # sets differ only near the 32 face-end directions of each half-turn
+    rp0, col0, val0 = sc.build_psf_sysmat(t, threshold=0.0)
+    assert abs(float(val.sum()) - float(val0.sum().item())) <= 100.0 / k * n
+
+
+def test_finite_k_unsupported_in_3d(torch):
+    from paper_1607_06170_amd import PsfError, Scanner, _lib
+    sc = Scanner(S.CFG_3D_SMALL, mode3d=True)
+    t = sc.build_table(91, 4, 1.0)
+    with pytest.raises(PsfError) as ei:
+        sc.build_psf_sysmat(t, homog_k=100)
+    assert ei.value.code == _lib.PSF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_top_n_truncation(torch, oracle, ref1, N):
+    """Sec 3.3 / Table 3: each voxel keeps its N largest bins per sinogram
+    angle.  The CSR (threshold 1e-6 after the truncation) and the forward
+    projection against the oracle's truncated matrix.  Where the oracle's N-th
+    and (N+1)-th values of a view are within 1e-5 of each other the two sides
+    may keep different bins (their sums differ in the last bits), so those
+    views' bins are excused from the pattern check only."""
+    tab_o, cols, flags = ref1
+    Nc = oracle.n_crystals_ring(CFG)
+    trunc = oracle.truncate_top_n(cols, Nc, N)
+    i, j = np.triu_indices(Nc, 1)
+    view = oracle.sinogram_view(i, j, Nc)
+    excuse = np.zeros_like(cols, dtype=bool)
+    for v in range(Nc // 2):
+        m = np.nonzero(view == v)[0]
+        srt = -np.sort(-cols[:, m], axis=1)
+        if srt.shape[1] > N:
+            close = (srt[:, N - 1] > 0) & (srt[:, N] >= srt[:, N - 1] * (1 - 1e-5))
+            excuse[np.ix_(close, m)] = True
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    thr = CFG["threshold"]
+    rp, col, val = sc.build_psf_sysmat(t, threshold=thr, top_n=N)
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    rpo, colo, _ = oracle.csr_from_columns(trunc, thr)
+    ties = (flags & oracle.F_TIES) != 0
+    n_exact = 0
+    for v in range(cols.shape[0]):
+        g, o = col[rp[v]:rp[v + 1]], colo[rpo[v]:rpo[v + 1]]
+        diff = np.setxor1d(g, o)
+        near = np.abs(cols[v, diff] - thr) <= 1e-4 * thr
+        if not ties[v]:
+            assert np.all(excuse[v, diff] | near), f"voxel {v}: {len(diff)} bins differ"
+            n_exact += len(diff) == 0
+        np.testing.assert_allclose(val[rp[v]:rp[v + 1]], cols[v, g], rtol=RTOL, atol=0)
+    assert n_exact >= 0.9 * cols.shape[0]
+    # at most N entries per view; fewer entries than the untruncated matrix
+    # exactly when the oracle's truncation drops some (at N = 7 no view of a
+    # voxel of this ring holds more than 7 bins above the threshold)
+    per_view = np.stack([np.bincount(view[col[rp[v]:rp[v + 1]]], minlength=Nc // 2) for v in range(cols.shape[0])])
+    assert per_view.max() <= N
+    full_nnz = int(oracle.csr_from_columns(cols, thr)[0][-1])
+    assert (rp[-1] < full_nnz) == (rpo[-1] < full_nnz)
+    assert rp[-1] <= full_nnz
+    x = S.phantom_uniform(CFG, seed=1)
+    y = sc.project_fwd(t, torch.tensor(x, dtype=torch.float32, device="cuda"), top_n=N).cpu().numpy()
+    yo = x.astype(np.float32).astype(np.float64) @ trunc
+    # bins whose truncation decision the two sides may take differently
+    tol = RTOL * np.abs(yo).max() + (excuse * cols).T @ np.abs(x[0])
+    assert np.all(np.abs(y[0] - yo[0]) <= tol)
+
+
+def test_osem_subset_update(torch, oracle, ref1):
+    """Histogram OSEM (Sec 3), 8 subsets of the 64 sinogram angles: the subset
+    sensitivity and one update from a uniform image against the oracle."""
+    tab_o, cols, flags = ref1
+    sc = _scanner(CFG)
+    t = sc.build_table(61, 4, 1.0)
+    Nc, nb = oracle.n_crystals_ring(CFG), oracle.n_bins_2d(CFG)
+    x_true = S.phantom_uniform(CFG, seed=1)[0]
+    y = S.poisson_counts(1e3 * (x_true @ cols), seed=200).astype(np.float32)
+    x0 = np.ones(cols.shape[0], np.float32)
+    for k in (0, 3, 7):
+        m = oracle.subset_mask(nb, Nc, 1, 8, k)
+        s_gpu = sc.subset_sensitivity(t, 8, k).cpu().numpy()
+        np.testing.assert_allclose(s_gpu, cols @ m, rtol=RTOL, atol=RTOL * 1e-2 * float((cols @ m).max()))
+        xk = sc.osem_update(t, torch.tensor(y, device="cuda"), torch.tensor(x0, device="cuda"),
+                            torch.tensor(s_gpu, device="cuda"), 8, k).cpu().numpy()
+        xo = oracle.osem_update(cols, y.astype(np.float64), x0.astype(np.float64), m)
+        np.testing.assert_allclose(xk, xo, rtol=2e-5, atol=2e-5 * float(xo.max()))
+
+
+def _fwhm(profile):
+    """Full width at half maximum of a 1D profile (linear interpolation)."""
+    p = np.asarray(profile, dtype=np.float64)
+    k = int(np.argmax(p))
+    h = p[k] / 2
+    lo = k
+    while lo > 0 and p[lo - 1] > h:
+        lo -= 1
+    hi = k
+    while hi < len(p) - 1 and p[hi + 1] > h:
+        hi += 1
+    left = lo - 1 + (p[lo - 1] - h) / (p[lo - 1] - p[lo]) if lo > 0 else lo
+    right = hi + (p[hi] - h) / (p[hi] - p[hi + 1]) if hi < len(p) - 1 else hi
+    return right - left
+
+
+def test_osem_point_sources_psf_sharper(torch):
+    """Sec 3.1, Fig. 9 (reproduced qualitatively on the 65 mm ring): point
+    sources along a radius, data from the PSF matrix, 10 iterations of OSEM
+    with 8 subsets.  Reconstructed with the PSF matrix the points are sharper
+    (smaller radial FWHM) than with the geometric matrix (each photon detected
+    in its entry crystal only), and the gap grows towards the edge."""
+    cfg = CFG
+    sc = _scanner(cfg)
+    t_psf = sc.build_table(61, 4, 1.0)
+    geo = np.zeros((61, 4, 5), np.float32)
+    geo[:, :, 2] = t_psf.data.cpu().numpy().reshape(61, 4, 5).sum(axis=2)   # all of it in the entry crystal
+    t_geo = sc.table_from(geo, 61, 4, 1.0)
+    n = cfg["nx"]
+    radii = [2, 10, 20, 28]   # mm from the centre along +x (voxel centres at +0.5 mm)
+    x_true = np.zeros((n, n), np.float32)
+    for r in radii:
+        x_true[n // 2, n // 2 + r] = 1.0
+    xt = torch.tensor(x_true.reshape(1, -1), device="cuda")
+    y = sc.project_fwd(t_psf, xt)[0] * 1e4
+    fw = {}
+    for name, t in (("psf", t_psf), ("geo", t_geo)):
+        sens = [sc.subset_sensitivity(t, 8, k) for k in range(8)]
+        x = torch.ones(n * n, device="cuda")
+        for it in range(10):
+            for k in range(8):
+                x = sc.osem_update(t, y, x, sens[k], 8, k)
+        img = x.reshape(n, n).cpu().numpy()
+        fw[name] = [_fwhm(img[n // 2, n // 2 + r - 4:n // 2 + r + 5]) for r in radii]
+    assert all(p < g for p, g in zip(fw["psf"], fw["geo"])), fw
+    assert fw["geo"][-1] - fw["psf"][-1] > fw["geo"][0] - fw["psf"][0] - 0.05, fw
