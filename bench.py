@@ -288,6 +288,7 @@ def main():
             s16 = _S(c16, mode3d=True)
         if not args.no_extra_rows:
             out["forms"] = forms_rows(s16, skipped)
+            out["table_grad"] = table_grad_row(s16, skipped)
         if gpu is not None and loc is not None:
             gpu.update(gpu_projections_16(s16, loc))
         del s16
@@ -305,26 +306,13 @@ def _left():
 
 
 def extra_rows_3d(sc, tab, x, y, xt, cfg, prec, per_step_s, skipped):
-    """The hot path's other two rows on the same workload, each timed once
-    after the timed steps:
-      - the adjoint with the table gradient d <y, A xt> / d table;
-      - one list-mode OSEM subset update of 1e6 events (9e5 drawn from the
-        forward projection of the phantom, 1e5 uniform over the LORs, seeded).
-    Each runs only while the whole run stays within its wall-clock budget."""
+    """One list-mode OSEM subset update of 1e6 events (9e5 drawn from the
+    forward projection of the phantom, 1e5 uniform over the LORs, seeded) on
+    the same workload, timed once after the timed steps, while the whole run
+    stays within its wall-clock budget."""
     import torch
     ev = lambda: torch.cuda.Event(enable_timing=True)
     res = {}
-    if _left() > 2.0 * per_step_s:
-        e0, e1 = ev(), ev()
-        e0.record()
-        sc.project_adj(tab, y, xt=xt, want_table_grad=True, precision=prec)
-        e1.record()
-        torch.cuda.synchronize()
-        res["table_grad"] = {"ms": e0.elapsed_time(e1), "table_entries": int(tab.data.numel()),
-                             "what": "x = A^T y and d<y, A xt>/d table, one image"}
-        log(f"adjoint with table gradient: {res['table_grad']['ms']:.1f} ms")
-    else:
-        skipped.append("table_grad (wall-clock budget)")
     if _left() > 2.0 * per_step_s:
         # events: bins drawn on the device from the expected counts, then crystal pairs
         g = torch.Generator(device="cuda").manual_seed(300)
@@ -361,6 +349,36 @@ def extra_rows_3d(sc, tab, x, y, xt, cfg, prec, per_step_s, skipped):
     else:
         skipped.append("listmode (wall-clock budget)")
     return res
+
+
+def table_grad_row(s16, skipped):
+    """The adjoint with the table gradient, x = A^T y and d <y, A x> / d table,
+    on the central 16^3 voxels (their own image grid, one image of the
+    phantom, y its forward projection): timed once after a warm-up call."""
+    import torch
+    if _left() < 30.0:
+        skipped.append("table_grad (wall-clock budget)")
+        return None
+    c16, m16 = workload("cyl3d_sub16")
+    t16 = s16.build_table(c16["n_rows"], c16["n_sub"], c16["step_deg"])
+    x = torch.tensor(phantom(c16, m16), dtype=torch.float32, device="cuda")
+    y = s16.project_fwd(t16, x)
+    s16.project_adj(t16, y, xt=x, want_table_grad=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s16.project_adj(t16, y, xt=x, want_table_grad=True)
+    e1.record()
+    torch.cuda.synchronize()
+    e0b, e1b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0b.record()
+    s16.project_adj(t16, y)
+    e1b.record()
+    torch.cuda.synchronize()
+    ms, ms_adj = e0.elapsed_time(e1), e0b.elapsed_time(e1b)
+    log(f"adjoint with table gradient (16^3): {ms:.1f} ms (adjoint alone {ms_adj:.1f} ms)")
+    return {"ms": ms, "adjoint_alone_ms": ms_adj, "table_entries": int(t16.data.numel()),
+            "what": "x = A^T y and d<y, A x>/d table, one image, the central 16^3 voxels on their own grid"}
 
 
 def forms_rows(sc, skipped):
@@ -533,17 +551,33 @@ def rel_errors(meta, vox, loc, cols, flags, gpu, O):
             res[name] = {"matrix_max_rel": worst}
         return res
     for name in PREC_NAMES:
-        worst, same, n = 0.0, True, 0
+        worst, worst_big, same, n = 0.0, 0.0, True, 0
+        tie_n, tie_common, tie_worst = 0, 1.0, 0.0
         for k, (g, gv) in enumerate(gpu[name]["rows"]):
-            if flags[k] & O.F_TIES:
-                continue
             ob, ov = cols[k]
+            if flags[k] & O.F_TIES:
+                # a decision within a hair of a boundary: compare the common entries
+                _, ia, ib = np.intersect1d(g, ob, assume_unique=True, return_indices=True)
+                tie_n += 1
+                tie_common = min(tie_common, len(ia) / max(len(np.union1d(g, ob)), 1))
+                if len(ia):
+                    tie_worst = max(tie_worst, float(np.max(np.abs(gv[ia] - ov[ib]) / ov[ib])))
+                continue
             n += 1
             if not np.array_equal(g, ob):
                 same = False
                 continue
-            worst = max(worst, float(np.max(np.abs(gv - ov) / ov)))
-        res[name] = {"matrix_rows": {"voxels": n, "same_pattern": same, "max_rel": worst}}
+            rel = np.abs(gv - ov) / ov
+            worst = max(worst, float(np.max(rel)))
+            big = ov >= 1e-9 * ov.max()
+            worst_big = max(worst_big, float(np.max(rel[big])))
+        res[name] = {"matrix_rows": {
+            "voxels": n, "same_pattern": same, "max_rel": worst, "max_rel_above_1e-9_of_row_max": worst_big,
+            "note": "the largest relative errors sit on elements 1e-12 or more below their row's largest, whose "
+                    "homogenization weights are sets of about 1e-14 of the sphere (the empty-set threshold), "
+                    "where the FP64 closed form and the oracle's quadrature differ relatively",
+            "voxels_with_flagged_ties": {"n": tie_n, "min_common_fraction": tie_common,
+                                         "max_rel_on_common": tie_worst}}}
     if loc is None or "proj" not in gpu:
         return res
     central = cols[len(vox) - len(loc):]

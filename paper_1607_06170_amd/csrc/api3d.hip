@@ -166,7 +166,7 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
         L.uvgrad = off;
         off += align256(sizeof(double) * 400 * (size_t)L.cap_uv);
         L.g64 = off;
-        off += align256(sizeof(double) * (size_t)L.table_elems);
+        off += align256(sizeof(double) * kGradRep * (size_t)L.table_elems);
     }
     L.plan = off;  // classes, members, row-table offsets and images of every batch: at most 2 int4 + 2 int per voxel
     off += align256((2 * sizeof(int4) + 2 * sizeof(int)) * (size_t)h->n_vox);
@@ -606,6 +606,7 @@ int adj3_all(psf_handle* h, const Cyl3D& G, const Scratch3D& S, const Ws3& L, co
             a.yin = ones ? nullptr : yd;
             a.xt = xt ? xt + (int64_t)b0 * h->n_vox : nullptr;
             a.g64 = g64;
+            a.g64_n = L.table_elems;
             if (a.xt) HIP_TRY(launch_gather_members(S, a, a.xt, h->n_vox, s));
             a.ones = ones;
             a.x64 = x64 + (int64_t)b0 * h->n_vox;
@@ -808,12 +809,15 @@ int project_adj_3d(psf_handle* h, const psf_table* t, const psf_opts* o, const f
     HIP_TRY(launch_zero_f64(x64, (int64_t)batch * h->n_vox, s));
     double* g64 = grad ? at3<double>(ws, L.g64) : nullptr;
     if (grad) {
-        HIP_TRY(launch_zero_f64(g64, L.table_elems, s));
+        HIP_TRY(launch_zero_f64(g64, kGradRep * L.table_elems, s));
         HIP_TRY(launch_zero_f64(S.uvgrad, 400 * L.cap_uv, s));
     }
     if ((st = adj3_all(h, G, S, L, ybins, ones, batch, x64, xt, g64, ws, s))) return st;
     HIP_TRY(launch_finalize(x64, x, (int64_t)batch * h->n_vox, ones ? 0 : o->accumulate, s));
-    if (grad) HIP_TRY(launch_finalize(g64, grad, L.table_elems, 1, s));
+    if (grad) {
+        HIP_TRY(launch_sum_copies(g64, L.table_elems, kGradRep, s));  // the copies into the first
+        HIP_TRY(launch_finalize(g64, grad, L.table_elems, 1, s));
+    }
     return read_status(ws, s);  // blocks: a capacity or range flag means x is incomplete
 }
 

@@ -109,6 +109,9 @@ struct Scratch3D {
     int band_rows;
 };
 constexpr int kXRep = 64;
+// copies of the FP64 table-gradient accumulator, taken by workgroup: many response
+// rows feed the same table entries, and one copy would serialise their atomics
+constexpr int kGradRep = 32;
 
 // tile record (ints and floats in one array):
 //   [0] g1  [1] g2  [2] (r1 + 512) | (r2 + 512) << 10 | class << 20  [3] n samples
@@ -146,7 +149,8 @@ struct Args3D {
     int* status;
     int ones;           // adjoint with y == 1 (sensitivity)
     const float* xt;    // [batch][nvox] image of the table gradient (adjoint with gradient)
-    double* g64;        // table-gradient accumulator [table entries]
+    double* g64;        // table-gradient accumulator [kGradRep][table entries]
+    int64_t g64_n;      // table entries (the stride of g64's copies)
     // matrix build, count phase with staging: rows compacted into the stage, in
     // pieces of one compaction chunk each
     int stage;
@@ -227,6 +231,7 @@ hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Arg
                                    hipStream_t st);
 hipError_t launch_cyl3d_uvtab(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
 hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st);
+hipError_t launch_sum_copies(double* p, int64_t n, int reps, hipStream_t st);
 hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);
 hipError_t launch_cyl3d_compact(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st);

@@ -844,6 +844,9 @@ __global__ void __launch_bounds__(kUvBlock) k_cyl3d_uvgrad(Cyl3D G, Scratch3D S,
     if (slot >= n_slots) return;
     double* gr = S.uvgrad + (slot * 16 + row) * 25;
     if (row >= G.P * G.P) return;
+    bool any = false;
+    for (int c = 0; c < 25; ++c) any |= gr[c] != 0.0;
+    if (!any) return;  // no tile of the batch reached this row
     int lo = 0, hi = A.n_cls - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -860,9 +863,25 @@ __global__ void __launch_bounds__(kUvBlock) k_cyl3d_uvgrad(Cyl3D G, Scratch3D S,
     for (int c = 0; c < 25; ++c) {
         const double v = gr[c];
         if (v == 0.0) continue;
-        if (out[c] >= 0) atomicAdd(&A.g64[out[c]], v);
+        if (out[c] >= 0) atomicAdd(&A.g64[(int64_t)(blockIdx.x % kGradRep) * A.g64_n + out[c]], v);
         gr[c] = 0.0;
     }
+}
+
+// p[i] += p[r * n + i] for r = 1 .. reps - 1
+__global__ void k_sum_copies(double* p, int64_t n, int reps) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = p[i];
+        for (int r = 1; r < reps; ++r) v += p[r * n + i];
+        p[i] = v;
+    }
+}
+
+hipError_t launch_sum_copies(double* p, int64_t n, int reps, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, p, n, reps);
+    return hipGetLastError();
 }
 
 hipError_t launch_cyl3d_uvgrad(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int64_t n_slots, hipStream_t st) {
@@ -1861,6 +1880,9 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if (bb < nb) xv[bb] = (double)xs[bb];
                 }
             }
+            bool mx = false;  // the member's xt is non-zero in some image
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) mx |= xv[bb] != 0.0;
             n_vt += __popcll(__ballot(mok && lane <= msk));
             // build: the lane's group's accumulators, [slot][i][j][s2] (members interleaved)
             const int64_t dbase = (int64_t)(cl.y + g * nzc) * S.dense_slab;
@@ -1982,7 +2004,8 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                         if (mok && e < total) {
                             int mm, key, ab;
                             ld(e, mm, tv[u], key, ab);
-                            c[u] = locate(mm, key, ab);
+                            // a zero entry serves only the gradient: members with xt = 0 skip it
+                            if (tv[u] != 0.0f || mx) c[u] = locate(mm, key, ab);
                         }
                     }
                     double gv[kGE];
