@@ -12,8 +12,8 @@ using namespace psf;
 
 namespace {
 
-constexpr int kBatchCsr = 1024;   // voxels per batch of the matrix build (dense accumulators, FP32: about 50 GB)
-constexpr int kShareCsr = 8;      // voxels of one column in a class of the matrix build (interleaved accumulators)
+constexpr int kBatchCsr = 1024;   // voxels per batch of the matrix build (dense accumulators, FP32: about 67 GB)
+constexpr int kShareCsr = 16;     // voxels of one column in a class of the matrix build (interleaved accumulators)
 constexpr int kBatchProj = 4096;  // voxels per batch of the projections (fewer, fuller launches)
 constexpr int kClsBatch = 2047;   // classes per batch: a tile record's header holds the class index in 11 bits
 constexpr int kMaxMemProj = 256;  // voxels of a projection class with images or the axial mirror (16 z-shifts x 8 images x 2)
@@ -431,7 +431,7 @@ const ClassOrderCache& class_order(psf_handle* h, const Ws3& L) {
     ClassOrderCache& C = h->order;
     const int64_t key[3] = {L.bcsr, L.cap_recs, L.cap_uv_rings};
     if (C.valid && C.key[0] == key[0] && C.key[1] == key[1] && C.key[2] == key[2]) return C;
-    const Plan3 all = plan3(h, L, 0, h->n_vox, L.bcsr, true, kShareCsr, true);
+    const Plan3 all = plan3(h, L, 0, h->n_vox, L.bcsr, true, kShareCsr, true, kMaxMemProj);
     C.cls.clear();
     C.sym.clear();
     C.first.clear();
@@ -656,7 +656,7 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
     const int stage = L.cap_stage > 0;
     csr->n_rows = ve - vb;
     const Plan3 pl = (o->flags & PSF_OPT_CLASS_ORDER) ? plan3_order(h, L, vb, ve, L.bcsr)
-                                                       : plan3(h, L, vb, ve, L.bcsr, true, kShareCsr, true);
+                                                       : plan3(h, L, vb, ve, L.bcsr, true, kShareCsr, true, kMaxMemProj);
     // what a count phase on this workspace staged for us (read before the header is cleared)
     int staged = 0;
     StageState ss;

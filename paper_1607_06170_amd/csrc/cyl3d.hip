@@ -1784,12 +1784,12 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
             }
         }
         if constexpr (MODE == kModeCount || MODE == kModeFill) {
-          if (cl.z <= 128 && nzc <= 8) {
+          if (cl.z <= 256 && nzc <= 16) {
             // the build: each (entry, column-half) pair reaches one accumulator
             // cell, whose nzc members (one per ring shift) are adjacent floats.
             // Chunks of 64 pairs: one lane per pair finds the cell and the ring
-            // shifts for which the entry's rings exist; then eight lanes per pair
-            // add the entry to its members' floats.
+            // shifts for which the entry's rings exist; then eight (nzc <= 8) or
+            // sixteen lanes per pair add the entry to its members' floats.
             const int ngrp = cl.z / nzc;
             const int NRr = G.NR + nzc - 1, NR = G.NR;
             const int npair = total * ngrp;
@@ -1830,8 +1830,9 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                 }
                 __builtin_amdgcn_wave_barrier();
                 const int nq = npair - c0 < 64 ? npair - c0 : 64;
-                for (int q0 = 0; q0 < nq; q0 += 8) {
-                    const int q = q0 + (lane >> 3), s2 = lane & 7;
+                const int lsh = nzc <= 8 ? 3 : 4;  // lanes per pair: 8 or 16
+                for (int q0 = 0; q0 < nq; q0 += 64 >> lsh) {
+                    const int q = q0 + (lane >> lsh), s2 = lane & ((1 << lsh) - 1);
                     if (q >= nq || s2 >= nzc) continue;
                     const int info = L.minfo[q];
                     const int g = info & 31;
@@ -2445,24 +2446,28 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
     __shared__ int rcell[kRowsC], rbin[kRowsC];  // a row's cell (j = 0), its bin for member 0 at j = n - 1
     __shared__ unsigned short rowof[kMapC];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kBlockC / 64;
-    const int grp = blockIdx.y;  // the member index of the group's first voxel
+    // a column group of up to 16 members is compacted in halves of up to 8:
+    // the block of its member 0 takes members 0-7, that of member 8 takes 8-15
+    const int grp = blockIdx.y;  // the member index of the half's first voxel
     const int4 me = A.mem[grp];
-    if (me.y != 0) return;  // not the first voxel of its column group
+    if (me.y & 7) return;  // not the first voxel of a half of its column group
     const int vb = me.z;
     const int NR = G.NR;
     const int nzc = A.cls[vb].w + 1, c = nzc - 1, NRr = NR + c;
-    const int nsl = S.n_slots[grp];
+    const int s0 = me.y, g0 = grp - s0;        // the half's first member; the group's first voxel
+    const int nh = nzc - s0 < 8 ? nzc - s0 : 8;  // the half's members
+    const int nsl = S.n_slots[g0];
     const int64_t nrows = (int64_t)nsl * NRr;
     const int64_t chunk = blockIdx.x;
     const int64_t q0 = chunk * kRowsC;
-    if (chunk == 0 && tid < nzc) A.stage_nch[A.mem[grp + tid].w] = (int)((nrows + kRowsC - 1) / kRowsC);
+    if (chunk == 0 && tid < nh) A.stage_nch[A.mem[grp + tid].w] = (int)((nrows + kRowsC - 1) / kRowsC);
     if (q0 >= nrows) return;
     const int nq = nrows - q0 < kRowsC ? (int)(nrows - q0) : kRowsC;
-    const int64_t dbase = (int64_t)grp * S.dense_slab;  // the group's cells in S.dense
-    const int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
-    const int* order = S.slot_order + (int64_t)grp * S.cap_slots;
+    const int64_t dbase = (int64_t)g0 * S.dense_slab;  // the group's cells in S.dense
+    const int* stb = S.slot_tbin + (int64_t)g0 * S.cap_slots;
+    const int* order = S.slot_order + (int64_t)g0 * S.cap_slots;
     const int64_t bref = (int64_t)A.cls[vb].y * S.cap_slots * S.band_rows;
-    const bool mh = (A.sym[vb] & 0x100) && (((grp - A.cls[vb].y) / nzc) & 1);
+    const bool mh = (A.sym[vb] & 0x100) && (((g0 - A.cls[vb].y) / nzc) & 1);
     const int C = NR - 1 - c;
     int tot_s[8];  // the chunk's cells of each member (its stage reservation)
     {
@@ -2486,9 +2491,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
                     len = h - l + 1;
 #pragma unroll
                     for (int s = 0; s < 8; ++s) {
-                        // member s: rows and columns c - s .. NR - 1 + c - s
-                        if (s < nzc && i >= c - s && i <= NR - 1 + c - s) {
-                            const int l2 = max(l, c - s), h2 = min(h, NR - 1 + c - s);
+                        // member sg = s0 + s: rows and columns c - sg .. NR - 1 + c - sg
+                        const int sg = s0 + s;
+                        if (s < nh && i >= c - sg && i <= NR - 1 + c - sg) {
+                            const int l2 = max(l, c - sg), h2 = min(h, NR - 1 + c - sg);
                             ls[s] = h2 >= l2 ? h2 - l2 + 1 : 0;
                         }
                     }
@@ -2532,7 +2538,7 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
         __syncthreads();
     }
     // each member's reservation in its stage region
-    if (tid < nzc) {
+    if (tid < nh) {
         const int s = tid;
         int64_t b = -1;
         int ts = 0;
@@ -2573,9 +2579,10 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 a[s] = 0.0f;
-                if (s < nzc) {
-                    a[s] = acc_take(S, cell + s, true);  // leave the accumulator clean
-                    const bool ok = i >= c - s && i <= NR - 1 + c - s && j >= c - s && j <= NR - 1 + c - s;
+                if (s < nh) {
+                    const int sg = s0 + s;
+                    a[s] = acc_take(S, cell + sg, true);  // leave the accumulator clean
+                    const bool ok = i >= c - sg && i <= NR - 1 + c - sg && j >= c - sg && j <= NR - 1 + c - sg;
                     if (ok && a[s] > 0.0f && (double)a[s] >= A.threshold) keep |= 1u << s;
                 }
             }
@@ -2596,18 +2603,18 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
             int off = 0;
             for (int w = 0; w < wid; ++w) off += wave_tot[s][w];
             const int64_t pos = s_run[s] + off + pre[s];  // below the member's reservation
-            A.stage_col[start + pos] = rbin[lo] + j + s * (NR + 1);
+            A.stage_col[start + pos] = rbin[lo] + j + (s0 + s) * (NR + 1);
             A.stage_val[start + pos] = a[s];
         }
         __syncthreads();
-        if (tid < nzc) {
+        if (tid < nh) {
             int t = 0;
             for (int w = 0; w < nw; ++w) t += wave_tot[tid][w];
             s_run[tid] += t;
         }
         __syncthreads();
     }
-    if (tid < nzc) {
+    if (tid < nh) {
         const int64_t row = A.mem[grp + tid].w;
         const int n = s_run[tid];
         atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
