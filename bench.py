@@ -258,6 +258,12 @@ def main():
                     "symmetry class (below), whose work a voxel-by-voxel method would repeat",
             "voxel_tiles_per_launch": vtiles_per_launch,
             "symmetry_amortised_tflops": amortised}
+        if traffic is not None:
+            # what bounds the kernel instead: its emission (FP32 atomics into the build's
+            # accumulators and the sinogram, gathers in the adjoint), measured as HBM bytes
+            hbm = traffic / (avg_ms * 1e-3) / 1e9
+            out["roofline"]["hbm_traffic_gbps"] = hbm
+            out["roofline"]["hbm_traffic_frac"] = hbm / HBM_PEAK_GBS
         out["geometry_kernel"] = {"kernel": "k_cyl3d_geom (FP64 homogenization weights and response rows)",
                                   "total_ms_per_step": g_ms / steps, "launches": g_launches,
                                   "contraction_total_ms_per_step": k_ms / steps}

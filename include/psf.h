@@ -133,7 +133,8 @@ typedef struct {
  * skips clearing its accumulators (every build leaves them clear; the last
  * 32 bytes of the workspace header record the handle and layout that did, and
  * the clear is skipped only when they match).  A wrong assertion gives wrong
- * matrices; without the flag every build clears them (about 50 GB). */
+ * matrices; without the flag every build clears them (about 67 GB, twice that
+ * for deterministic builds). */
 #define PSF_OPT_WS_CLEAN 4
 /* psf_opts.flags (build_psf_sysmat): [vox_begin, vox_end) counts positions in
  * the library's voxel order (psf_voxel_order) instead of linear voxel indices;
