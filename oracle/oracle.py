@@ -24,7 +24,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "_psf_oracle.so")
-SOURCES = [os.path.join(HERE, "psf_oracle.c"), os.path.join(HERE, "psf_oracle3d.c")]
+SOURCES = [os.path.join(HERE, "psf_oracle.c"), os.path.join(HERE, "psf_oracle3d.c"),
+           os.path.join(HERE, "psf_oracle_mc.c")]
 
 # flag bits (see psf_oracle.c)
 F_MIRROR_TIE = 1
@@ -108,6 +109,17 @@ def lib():
             L.og_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
             if hasattr(L, "og_table3_rows"):
                 _bind3d(L, G, I, T)
+            _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+            L.og_philox4x32_10.restype = None
+            L.og_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+            L.og_kn_sigma.restype = C.c_double
+            L.og_kn_sigma.argtypes = [C.c_double]
+            L.og_kn_cos_samples.restype = None
+            L.og_kn_cos_samples.argtypes = [C.c_double, C.c_int64, C.c_uint64, _dp]
+            L.og_table_mc.restype = None
+            L.og_table_mc.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_int64, C.c_uint64, C.c_int, C.c_int64, C.c_int64, _i64p,
+                                      C.c_int]
             _lib = L
     return _lib
 
@@ -452,3 +464,35 @@ def n_bins_3d(cfg: dict) -> int:
 def pair_bin(i, j, n):
     i, j = np.minimum(i, j), np.maximum(i, j)
     return i * n - i * (i + 1) // 2 + (j - i - 1)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC 2011) of a 4-word counter and 2-word key."""
+    out = np.zeros(4, np.uint32)
+    lib().og_philox4x32_10(np.ascontiguousarray(ctr, np.uint32), np.ascontiguousarray(key, np.uint32), out)
+    return out
+
+
+def table_mc_counts(cfg: dict, mode3d: bool, photons: int, seed: int, scatter: bool, cells,
+                    n_rows: int = 61, n_sub: int = 4, step_deg: float = 1.0, nthreads: int = 8) -> np.ndarray:
+    """Photon-transport Monte Carlo of the response table (Sec 2.1.1, Eq.1): for
+    table cells [cells[0], cells[1]) the counts of detected photons, shape
+    [cells, 5 (a_t + 2), 5 (a_z + 2)] (2D: a_z = 0).  See psf_oracle_mc.c."""
+    c0, c1 = int(cells[0]), int(cells[1])
+    out = np.zeros((c1 - c0) * 25, np.int64)
+    lib().og_table_mc(int(mode3d), int(n_rows), int(n_sub), float(step_deg), float(cfg["pitch_t"]),
+                      float(cfg["pitch_z"]), float(cfg["depth"]), float(cfg["mu"]), int(photons), int(seed),
+                      int(scatter), c0, c1, out, int(nthreads))
+    return out.reshape(c1 - c0, 5, 5)
+
+
+def kn_cos_samples(k: float, n: int, seed: int) -> np.ndarray:
+    """n Compton scattering cosines at k = E / 511 keV from the MC's sampler."""
+    out = np.zeros(int(n))
+    lib().og_kn_cos_samples(float(k), int(n), int(seed), out)
+    return out
+
+
+def kn_sigma(k: float) -> float:
+    """The MC's Klein-Nishina total cross section (units of 2 pi r_e^2) at k = E / 511 keV."""
+    return float(lib().og_kn_sigma(float(k)))
