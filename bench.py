@@ -296,6 +296,7 @@ def main():
             out["forms"] = forms_rows(s16, skipped)
             out["table_grad"] = table_grad_row(s16, skipped)
             out["top_n"] = top_n_rows(skipped)
+            out["mc_tables"] = mc_table_rows(skipped)
         if gpu is not None and loc is not None:
             gpu.update(gpu_projections_16(s16, loc))
         del s16
@@ -386,6 +387,38 @@ def table_grad_row(s16, skipped):
     log(f"adjoint with table gradient (16^3): {ms:.1f} ms (adjoint alone {ms_adj:.1f} ms)")
     return {"ms": ms, "adjoint_alone_ms": ms_adj, "table_entries": int(t16.data.numel()),
             "what": "x = A^T y and d<y, A x>/d table, one image, the central 16^3 voxels on their own grid"}
+
+
+def mc_table_rows(skipped):
+    """The response tables by photon-transport Monte Carlo (Sec 2.1.1, Eq.1;
+    psf_build_table_mc), timed once each after a warm-up: the 2D table (61
+    rows x 4 sub-positions, 1e6 photons per cell) and the 3D table (61 x 61
+    rows x 4 x 4 sub-positions, 1e4 photons per cell), first interaction
+    only and with Compton scatter."""
+    import torch
+    if _left() < 30.0:
+        skipped.append("mc_tables (wall-clock budget)")
+        return None
+    from paper_1607_06170_amd import Scanner
+    from paper_1607_06170_amd import synth
+    res = {}
+    for name, cfg, mode3d, n in (("2d", synth.CFG_2D, False, 1_000_000), ("3d", synth.CFG_3D, True, 10_000)):
+        sc = Scanner(cfg, mode3d=mode3d)
+        cells = 61 * 61 * 16 if mode3d else 61 * 4
+        for scatter in (False, True):
+            sc.build_table_mc(61, 4, 1.0, photons=1000, seed=2, scatter=scatter)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sc.build_table_mc(61, 4, 1.0, photons=n, seed=3, scatter=scatter)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            res[f"{name}_{'scatter' if scatter else 'first_interaction'}"] = {
+                "ms": ms, "cells": cells, "photons_per_cell": n, "photons_per_s": cells * n / (ms * 1e-3)}
+        del sc
+    log("MC tables: " + ", ".join(f"{k} {v['ms']:.0f} ms" for k, v in res.items()))
+    return res
 
 
 def top_n_rows(skipped):

@@ -201,6 +201,27 @@ int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_de
 int psf_build_table_host(const psf_geometry* geom, int32_t mode3d, int32_t n_rows, int32_t n_sub, double step_deg,
                          double* table_host);
 
+/* Response table by photon-transport Monte Carlo (paper Sec 2.1.1, Eq.1:
+ * the response of the crystal array to photons entering at each sub-position
+ * and incidence angle is simulated; indexed as Sec 2.1.3, Eq.6-7), in the
+ * layout of psf_build_table, for this handle's crystals (pitches, depth,
+ * attenuation mu) and its mode (2D or 3D).  Each of the table's cells (2D:
+ * n_rows x n_sub; 3D: n_rows^2 x n_sub^2) follows `photons` photons entering
+ * uniformly over its sub-position; an entry is the fraction detected in that
+ * neighbour crystal.
+ *   scatter 0: first interaction only (the path length is exponential with
+ *     attenuation mu); its expectation is psf_build_table's analytic table.
+ *   scatter 1: photoelectric absorption (0.32 of mu at 511 keV, scaled by
+ *     (511/E)^3) and Compton scatter (Klein-Nishina cross section and angles);
+ *     a photon counts when 350 keV or more is deposited, in the crystal of the
+ *     energy-weighted centroid of its deposits.
+ * Photon k of cell c draws from Philox4x32-10 with counter (k, c, draw) and
+ * key `seed`, so results do not depend on the launch and are reproducible.
+ * counts_dev (optional, may be NULL): int64 [cells][5][5] detected photons
+ * (2D: entries [a + 2][2]).  photons in [1, 2^32).  Asynchronous. */
+int psf_build_table_mc(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, int64_t photons,
+                       uint64_t seed, int32_t scatter, float* table_dev, int64_t* counts_dev, void* stream);
+
 /* Device workspace in bytes needed by the calls below for these options,
  * batch size and number of events. */
 int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_opts* opts, int32_t batch,
@@ -215,8 +236,8 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
  *   phase 2: fills col/val (capacity csr->nnz); BLOCKS; PSF_EOVERFLOW if a
  *   row would exceed what phase 1 allotted.
  * 3D: PSF_EUNSUPPORTED when a class's accumulator cells (4096 transaxial
- * slots x (NR + 7)^2 ring pairs x 8 voxels) would not index in 32 bits, that
- * is for more than about 180 crystal rings. */
+ * slots x (NR + 15)^2 ring pairs x 16 voxels) would not index in 32 bits, that
+ * is for more than about 165 crystal rings. */
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
                      size_t workspace_bytes, psf_csr* csr, void* stream);
 

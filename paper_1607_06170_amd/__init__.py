@@ -147,6 +147,20 @@ class Scanner:
                                           float(step_deg), C.c_void_p(out.ctypes.data)), "psf_build_table_host")
         return out
 
+    def build_table_mc(self, n_rows: int = 61, n_sub: int = 4, step_deg: float = 1.0, photons: int = 100_000,
+                       seed: int = 1, scatter: bool = False, counts: bool = False):
+        """Response table by photon-transport Monte Carlo on the device
+        (psf_build_table_mc): a Table, and with counts=True also the int64
+        detected-photon counts [cells, 5, 5]."""
+        torch = _torch()
+        cells = n_rows * n_rows * n_sub * n_sub if self.mode3d else n_rows * n_sub
+        data = torch.empty(cells * (25 if self.mode3d else 5), dtype=torch.float32, device=self.device)
+        cnt = torch.empty(cells * 25, dtype=torch.int64, device=self.device) if counts else None
+        check(self.L.psf_build_table_mc(self.h, int(n_rows), int(n_sub), float(step_deg), int(photons), int(seed),
+                                        int(bool(scatter)), _ptr(data), _ptr(cnt), _stream()), "psf_build_table_mc")
+        t = Table(data, n_rows, n_sub, step_deg)
+        return (t, cnt.reshape(cells, 5, 5)) if counts else t
+
     def table_from(self, data, n_rows: int, n_sub: int, step_deg: float = 1.0) -> Table:
         """Wrap a caller-provided table (any shape with the right number of entries)."""
         torch = _torch()

@@ -70,6 +70,8 @@ SIGNATURES = {
     "psf_destroy": (None, [_H]),
     "psf_sizes": (C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "psf_build_table": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double, _P, _P]),
+    "psf_build_table_mc": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double, C.c_int64, C.c_uint64, C.c_int32, _P, _P,
+                                     _P]),
     "psf_build_table_host": (C.c_int, [C.POINTER(psf_geometry), C.c_int32, C.c_int32, C.c_int32, C.c_double, _P]),
     "psf_workspace_size": (C.c_int, [_H, C.POINTER(psf_table), C.POINTER(psf_opts), C.c_int32, C.c_int64,
                                      C.POINTER(C.c_size_t)]),

@@ -290,6 +290,17 @@ int psf_build_table(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_de
     return PSF_OK;
 }
 
+int psf_build_table_mc(psf_handle* h, int32_t n_rows, int32_t n_sub, double step_deg, int64_t photons, uint64_t seed,
+                       int32_t scatter, float* table_dev, int64_t* counts_dev, void* stream) {
+    if (!h || !table_dev || n_rows < 1 || n_sub < 1 || !(step_deg > 0)) return PSF_EINVAL;
+    if (photons < 1 || photons >= ((int64_t)1 << 32) || (scatter != 0 && scatter != 1)) return PSF_EINVAL;
+    const int64_t cells = h->mode3d ? (int64_t)n_rows * n_rows * n_sub * n_sub : (int64_t)n_rows * n_sub;
+    if (cells >= ((int64_t)1 << 31)) return PSF_ESIZE;
+    HIP_TRY(launch_table_mc(h->g, h->mode3d, n_rows, n_sub, step_deg, photons, seed, scatter, table_dev,
+                            (long long*)counts_dev, (hipStream_t)stream));
+    return PSF_OK;
+}
+
 int psf_build_table_host(const psf_geometry* geom, int32_t mode3d, int32_t n_rows, int32_t n_sub, double step_deg,
                          double* out) {
     if (!geom || !out || n_rows < 1 || n_sub < 1 || !(step_deg > 0) || (mode3d != 0 && mode3d != 1)) return PSF_EINVAL;

@@ -225,6 +225,8 @@ enum { kModeCount = 0, kModeFill = 1, kModeFwd = 2, kModeAdj = 3, kModeAdjGrad =
 
 // 3D launchers (cyl3d.hip, table3d.hip)
 hipError_t launch_table_3d(const psf_geometry& g, int n_rows, int P, double step_deg, float* out, hipStream_t st);
+hipError_t launch_table_mc(const psf_geometry& g, int mode3d, int n_rows, int P, double step_deg, long long photons,
+                           unsigned long long seed, int scatter, float* table, long long* counts, hipStream_t st);
 void table_2d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out);
 void table_3d_host(const psf_geometry& g, int n_rows, int P, double step_deg, double* out);
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
