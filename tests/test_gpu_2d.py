@@ -241,8 +241,10 @@ def test_table_gradient(torch, oracle):
 
 
 def test_autograd_fd_on_gpu(torch):
-    """Central differences of the GPU forward in x and in table entries
-    (float64 sums of the float32 outputs) agree with the hand-written adjoint."""
+    """Central differences of the GPU forward in table entries (float64 sums
+    of the float32 outputs) agree with the hand-written gradient.  f is
+    exactly quadratic in the table (reading 5), so central differences are
+    exact up to rounding: the tolerance is the forward's FP32 output rounding."""
     from paper_1607_06170_amd import PsfProject
     cfg = NARROW
     n = cfg["nx"] * cfg["ny"]
@@ -264,7 +266,7 @@ def test_autograd_fd_on_gpu(torch):
         yp = sc.project_fwd(Table(tp, 61, 4, 1.0), x).double()
         ym = sc.project_fwd(Table(tm, 61, 4, 1.0), x).double()
         fd = float(((yp - ym) * g.double()).sum()) / (2 * h)
-        assert abs(fd - gt[e]) <= 2e-3 * abs(gt[e]) + 1e-3 * np.abs(gt).max(), (e, fd, gt[e])
+        assert abs(fd - gt[e]) <= 1e-4 * abs(gt[e]) + 1e-5 * np.abs(gt).max(), (e, fd, gt[e])
 
 
 @pytest.mark.parametrize("prec,elem_tol,proj_tol", [(1, 1e-2, 1e-2), (2, 1e-4, 1e-4)])

@@ -67,11 +67,9 @@ def test_table3_parity(torch, oracle):
     sc = _scanner(CFG3)
     t = sc.build_table(61, 4, 1.0)
     got = t.data.cpu().numpy().reshape(61, 61, 4, 4, 5, 5).astype(np.float64)
-    rng = np.random.default_rng(3)
-    rt = np.concatenate([[0, 0, 60, 60, 45, 1], rng.integers(0, 61, 40)])
-    rz = np.concatenate([[0, 60, 0, 60, 45, 0], rng.integers(0, 61, 40)])
-    ref = oracle.table3_rows(CFG3, rt, rz)
-    np.testing.assert_allclose(got[rt, rz], ref, rtol=1e-6, atol=1e-9)
+    rt, rz = np.meshgrid(np.arange(61), np.arange(61), indexing="ij")   # every one of the 3721 row pairs
+    ref = oracle.table3_rows(CFG3, rt.ravel(), rz.ravel(), 4, 1.0, 16).reshape(61, 61, 4, 4, 5, 5)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9)
 
 
 def _check_rows(oracle, rp, col, val, cols, flags, vox):
