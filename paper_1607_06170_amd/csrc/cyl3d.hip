@@ -1977,9 +1977,11 @@ k_cyl3d_mma(Cyl3D G, Scratch3D S, Args3D A) {
                                 float yv[kGE];
 #pragma unroll
                                 for (int u = 0; u < kGE; ++u) yv[u] = c[u] < 0 ? 0.0f : (A.ones ? 1.0f : yb[c[u]]);
+                                float part = 0.0f;
 #pragma unroll
                                 for (int u = 0; u < kGE; ++u)
-                                    if (c[u] >= 0) acc1 += (double)tv[u] * (double)yv[u];
+                                    if (c[u] >= 0) part += tv[u] * yv[u];
+                                acc1 += (double)part;
                             }
                         }
                     }
@@ -2576,12 +2578,22 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
             j = rlo[lo] + (f - rpre[lo]);
             const int i = (int)((q0 + lo) % NRr);
             const int64_t cell = dbase + rcell[lo] + j * nzc;
+            if (!S.det && nh == 8 && ((uintptr_t)(S.dense + cell + s0) & 15) == 0) {
+                // the half's eight floats: two 16-byte loads and stores
+                float4* q = (float4*)(S.dense + cell + s0);
+                const float4 v0 = q[0], v1 = q[1];
+                q[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                q[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                a[0] = v0.x; a[1] = v0.y; a[2] = v0.z; a[3] = v0.w;
+                a[4] = v1.x; a[5] = v1.y; a[6] = v1.z; a[7] = v1.w;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 8; ++s) a[s] = s < nh ? acc_take(S, cell + s0 + s, true) : 0.0f;
+            }
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                a[s] = 0.0f;
                 if (s < nh) {
                     const int sg = s0 + s;
-                    a[s] = acc_take(S, cell + sg, true);  // leave the accumulator clean
                     const bool ok = i >= c - sg && i <= NR - 1 + c - sg && j >= c - sg && j <= NR - 1 + c - sg;
                     if (ok && a[s] > 0.0f && (double)a[s] >= A.threshold) keep |= 1u << s;
                 }
