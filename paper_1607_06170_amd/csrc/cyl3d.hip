@@ -2253,8 +2253,8 @@ hipError_t launch_xrep_fold(const Scratch3D& S, const Args3D& a, int64_t nvox, h
 // phase with staging: one pass per column group (k_cyl3d_compact_group
 // below); the fill phase copies each row's chunks in order (k_stage_copy).
 
-constexpr int kBlockC = 512;
-constexpr int kRowsC = 512;  // rows per chunk (one per thread for the row scan)
+constexpr int kBlockC = 256;
+constexpr int kRowsC = 256;  // rows per chunk (one per thread for the row scan)
 constexpr int kMapC = 8192;  // flat entries of a chunk mapped to their rows in LDS
 
 enum { kCompactCount = 0, kCompactChunks = 1, kCompactFill = 2 };
@@ -2440,10 +2440,11 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact(Cyl3D G, Scratch3D S,
 // bin is the cell's plus s (NR + 1).  Each member's entries come out in its
 // bin order, as in the member-by-member kernel, into its own stage region.
 // Chunks are kRowsC accumulator rows (slot, i) of the group.
+static_assert(kBlockC == 256, "the group compaction's pass totals hold four waves");
 __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratch3D S, Args3D A) {
     __shared__ int wave_tot[8][kBlockC / 64];
+    __shared__ __align__(16) int pass_tot[2][8][4];  // a pass's kept entries per member and wave (two passes alternate)
     __shared__ int64_t s_base[8];
-    __shared__ int s_run[8];
     __shared__ int rlo[kRowsC], rpre[kRowsC + 1], wave_len[kBlockC / 64];
     __shared__ int rcell[kRowsC], rbin[kRowsC];  // a row's cell (j = 0), its bin for member 0 at j = n - 1
     __shared__ unsigned short rowof[kMapC];
@@ -2556,9 +2557,11 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
             if (b < 0) atomicOr(A.stage_full, 1);
         }
         s_base[s] = b;
-        s_run[s] = 0;
     }
     __syncthreads();
+    int run[8];  // each member's kept entries so far (the same in every thread)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) run[s] = 0;
     for (int f0 = 0; f0 < T; f0 += kBlockC) {
         const int f = f0 + tid;
         float a[8];
@@ -2600,35 +2603,35 @@ __global__ void __launch_bounds__(kBlockC) k_cyl3d_compact_group(Cyl3D G, Scratc
             }
         }
         int pre[8];
+        const int pb = (f0 / kBlockC) & 1;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const unsigned long long m = __ballot((keep >> s) & 1u);
             pre[s] = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) wave_tot[s][wid] = __popcll(m);
+            if (lane == 0) pass_tot[pb][s][wid] = __popcll(m);
         }
+        // one barrier a pass: the totals written two passes on are behind the next one
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            if (!((keep >> s) & 1u)) continue;
-            const int64_t start = s_base[s];
-            if (start < 0) continue;
-            int off = 0;
-            for (int w = 0; w < wid; ++w) off += wave_tot[s][w];
-            const int64_t pos = s_run[s] + off + pre[s];  // below the member's reservation
-            A.stage_col[start + pos] = rbin[lo] + j + (s0 + s) * (NR + 1);
-            A.stage_val[start + pos] = a[s];
+            const int4 wt = *(const int4*)pass_tot[pb][s];
+            const int off = (wid > 0 ? wt.x : 0) + (wid > 1 ? wt.y : 0) + (wid > 2 ? wt.z : 0);
+            if ((keep >> s) & 1u) {
+                const int64_t start = s_base[s];
+                if (start >= 0) {
+                    const int64_t pos = run[s] + off + pre[s];  // below the member's reservation
+                    A.stage_col[start + pos] = rbin[lo] + j + (s0 + s) * (NR + 1);
+                    A.stage_val[start + pos] = a[s];
+                }
+            }
+            run[s] += wt.x + wt.y + wt.z + wt.w;
         }
-        __syncthreads();
-        if (tid < nh) {
-            int t = 0;
-            for (int w = 0; w < nw; ++w) t += wave_tot[tid][w];
-            s_run[tid] += t;
-        }
-        __syncthreads();
     }
     if (tid < nh) {
         const int64_t row = A.mem[grp + tid].w;
-        const int n = s_run[tid];
+        int n = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) n = s == tid ? run[s] : n;
         atomicAdd((unsigned long long*)&A.row_ptr[row + 1], (unsigned long long)n);
         A.stage_cb[row * S.max_chunks + chunk] = s_base[tid];
         A.stage_cn[row * S.max_chunks + chunk] = n;
