@@ -2176,23 +2176,45 @@ hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a
     return hipGetLastError();
 }
 
+// Blocks of a k_cyl3d_mma launch: twice as many as the GPU holds at once (the
+// kernel's blocks per compute unit times the compute units), so that every
+// block runs in one of two full rounds.  Each block's share of the records is
+// fixed at launch; a partial last round would leave compute units idle.
+template <int MODE>
+dim3 mma_grid() {
+    constexpr int kDevs = 64;
+    static int cached[kDevs];  // per device; 0 until queried
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kDevs) {
+        if (cached[dev] <= 0) {
+            int cus = 0, per = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cyl3d_mma<MODE>, 64 * kWavesM, 0) == hipSuccess &&
+                cus > 0 && per > 0)
+                cached[dev] = 2 * cus * per;
+        }
+        if (cached[dev] > 0) return dim3((unsigned)cached[dev]);
+    }
+    return dim3(2048);
+}
+
 hipError_t launch_cyl3d_mma(int mode, const Cyl3D& G, const Scratch3D& S, const Args3D& a, hipStream_t st) {
     if (a.n_cls <= 0) return hipSuccess;
-    const dim3 grid(2048), block(64 * kWavesM);
+    const dim3 block(64 * kWavesM);
     switch (mode) {
         case kModeCount:
         case kModeFill:
-            hipLaunchKernelGGL(k_cyl3d_mma<kModeCount>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeCount>, mma_grid<kModeCount>(), block, 0, st, G, S, a);
             break;
         case kModeFwd:
-            hipLaunchKernelGGL(k_cyl3d_mma<kModeFwd>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeFwd>, mma_grid<kModeFwd>(), block, 0, st, G, S, a);
             break;
         case kModeAdj:
-            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdj>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdj>, mma_grid<kModeAdj>(), block, 0, st, G, S, a);
             break;
         case kModeAdjGrad:
             if (!S.uvgrad || !a.xt) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdjGrad>, grid, block, 0, st, G, S, a);
+            hipLaunchKernelGGL(k_cyl3d_mma<kModeAdjGrad>, mma_grid<kModeAdjGrad>(), block, 0, st, G, S, a);
             break;
         default:
             return hipErrorInvalidValue;
