@@ -34,6 +34,8 @@
 // and S(A cos u) has the antiderivative asin(A sin u / sqrt(1 + A^2)); the
 // integral is exact once the interval is cut where the binding limits switch
 // (roots of p cos theta + q sin theta = 0).
+#include <atomic>
+
 #include "common.hpp"
 
 namespace psf {
@@ -2183,17 +2185,20 @@ hipError_t launch_cyl3d_geom(const Cyl3D& G, const Scratch3D& S, const Args3D& a
 template <int MODE>
 dim3 mma_grid() {
     constexpr int kDevs = 64;
-    static int cached[kDevs];  // per device; 0 until queried
+    static std::atomic<int> cached[kDevs];  // per device; 0 until queried (host threads may race: same value)
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kDevs) {
-        if (cached[dev] <= 0) {
+        int n = cached[dev].load(std::memory_order_relaxed);
+        if (n <= 0) {
             int cus = 0, per = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
                 hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cyl3d_mma<MODE>, 64 * kWavesM, 0) == hipSuccess &&
-                cus > 0 && per > 0)
-                cached[dev] = 2 * cus * per;
+                cus > 0 && per > 0) {
+                n = 2 * cus * per;
+                cached[dev].store(n, std::memory_order_relaxed);
+            }
         }
-        if (cached[dev] > 0) return dim3((unsigned)cached[dev]);
+        if (n > 0) return dim3((unsigned)n);
     }
     return dim3(2048);
 }
