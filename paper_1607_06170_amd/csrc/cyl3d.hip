@@ -472,6 +472,15 @@ __device__ void clear_slot_counts(const Scratch3D& S, const Args3D& A, int cb) {
     for (int i = 0; i < c.z; i += nzc) S.n_slots[c.y + i] = 0;
 }
 
+// The build's slot numbering keeps a bitmap of the transaxial bins and a word
+// prefix in the kernel's dynamic LDS (over the spent sweep arrays) when they
+// fit in kSlotBitsMax bytes; else it scans the slot map in global memory.
+constexpr size_t kSlotBitsMax = 48 * 1024;
+__host__ __device__ inline size_t slot_bitmap_bytes(const Cyl3D& G) {
+    const size_t b = 2 * sizeof(unsigned int) * (size_t)((G.ntbins + 31) / 32);
+    return b <= kSlotBitsMax ? b : 0;
+}
+
 __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D S, Args3D A, int want_slots) {
     extern __shared__ __align__(16) unsigned char smem3[];
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -638,6 +647,73 @@ __global__ void __launch_bounds__(kBlockT) k_cyl3d_transaxial(Cyl3D G, Scratch3D
     __shared__ int s_run;
     const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
     int* smap = S.slotmap + (int64_t)grp * G.ntbins;
+    if (slot_bitmap_bytes(G) > 0) {
+        // marks as bits in LDS (the sweep arrays are spent), a prefix count per
+        // word, then every bin's slot (or -1) written with consecutive threads
+        // on consecutive bins
+        const int nwd = (int)((G.ntbins + 31) / 32);
+        unsigned int* bits = (unsigned int*)smem3;
+        int* wpre = (int*)(bits + nwd);
+        __syncthreads();
+        for (int w = tid; w < nwd; w += bs) bits[w] = 0u;
+        __syncthreads();
+        for (int p = tid; p < np; p += bs) {
+            const int4 pr = pairs[p];
+            for (int at = -2; at <= 2; ++at)
+                for (int bt = -2; bt <= 2; ++bt) {
+                    int gi = pr.x + at, gj = pr.y + bt;
+                    gi = gi < 0 ? gi + G.Nc : (gi >= G.Nc ? gi - G.Nc : gi);
+                    gj = gj < 0 ? gj + G.Nc : (gj >= G.Nc ? gj - G.Nc : gj);
+                    if (gi == gj) continue;
+                    const int64_t tb = tbin_of(gi < gj ? gi : gj, gi < gj ? gj : gi, G.Nc);
+                    atomicOr(&bits[tb >> 5], 1u << (tb & 31));
+                }
+        }
+        __syncthreads();
+        // words in contiguous runs per thread: counts, one block scan, prefixes
+        const int per = (nwd + bs - 1) / bs, w0 = tid * per, w1 = w0 + per < nwd ? w0 + per : nwd;
+        int mine = 0;
+        for (int w = w0; w < w1; ++w) mine += __popc(bits[w]);
+        int inc = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) red[wid] = inc;
+        __syncthreads();
+        int run = inc - mine;
+        for (int w = 0; w < wid; ++w) run += red[w];
+        if (tid == 0) {
+            int all = 0;
+            for (int w = 0; w < nw; ++w) all += red[w];
+            s_run = all;
+        }
+        for (int w = w0; w < w1; ++w) {
+            wpre[w] = run;
+            run += __popc(bits[w]);
+        }
+        __syncthreads();
+        int* stb = S.slot_tbin + (int64_t)grp * S.cap_slots;
+        for (int64_t i = tid; i < G.ntbins; i += bs) {
+            const unsigned int word = bits[i >> 5], bit = 1u << (i & 31);
+            int sl = -1;
+            if (word & bit) {
+                const int k = wpre[i >> 5] + __popc(word & (bit - 1u));
+                if (k < S.cap_slots) {
+                    sl = k;
+                    stb[k] = (int)i;
+                }
+            }
+            smap[i] = sl;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int nsl = s_run;
+            if (nsl > S.cap_slots) atomicOr(A.status, kStatScratch);
+            S.n_slots[grp] = nsl < S.cap_slots ? nsl : S.cap_slots;
+        }
+        return;
+    }
     for (int64_t i = tid; i < G.ntbins; i += bs) smap[i] = 0;
     __syncthreads();
     for (int p = tid; p < np; p += bs) {
@@ -767,7 +843,9 @@ hipError_t launch_image_slots(const Cyl3D& G, const Scratch3D& S, const Args3D& 
 }
 
 size_t cyl3d_transaxial_smem(const Cyl3D& G) {
-    return sizeof(double) * (size_t)(G.R * (G.nc * G.P + 1) + G.nseg) + sizeof(int) * (size_t)(G.nseg + 1) + 64;
+    const size_t sweep = sizeof(double) * (size_t)(G.R * (G.nc * G.P + 1) + G.nseg) + sizeof(int) * (size_t)(G.nseg + 1) + 64;
+    const size_t bits = slot_bitmap_bytes(G);
+    return bits > sweep ? bits : sweep;
 }
 
 hipError_t launch_cyl3d_transaxial(const Cyl3D& G, const Scratch3D& S, const Args3D& a, int want_slots,
