@@ -116,6 +116,11 @@ void psf_destroy(psf_handle* h) {
         (void)hipEventDestroy(e.second);
     }
     if (h->frames_dev) (void)hipFree(h->frames_dev);
+    if (h->aux) {
+        (void)hipStreamSynchronize(h->aux);
+        for (int i = 0; i < kAuxEvents; ++i) (void)hipEventDestroy(h->aux_ev[i]);
+        (void)hipStreamDestroy(h->aux);
+    }
     delete h;
 }
 

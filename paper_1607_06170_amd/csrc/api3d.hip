@@ -98,6 +98,10 @@ struct Ws3 {
     int64_t max_chunks;
     int64_t cap_recs, per_vox;
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
+    // staged builds: a second set of the per-batch slot and band arrays (and the
+    // counters), so that one batch's compaction overlaps the next batch's geometry
+    size_t counts2, slot_tbin2, slot_order2, band2, bandc2;
+    int set2;
 };
 
 Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_events, int grad, int64_t stage_rows,
@@ -189,6 +193,20 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
         L.stage_val = off;
         off += align256(sizeof(float) * (size_t)L.cap_stage);
     }
+    L.set2 = L.cap_stage > 0;
+    L.counts2 = L.slot_tbin2 = L.slot_order2 = L.band2 = L.bandc2 = 0;
+    if (L.set2) {
+        L.counts2 = off;
+        off += align256(sizeof(int) * 3 * (size_t)L.bmax);
+        L.slot_tbin2 = off;
+        off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
+        L.slot_order2 = off;
+        off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
+        L.band2 = off;
+        off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
+        L.bandc2 = off;
+        off += align256(sizeof(int2) * (size_t)L.bcsr * L.cap_slots * L.band_rows);
+    }
     L.x64 = off;
     off += align256(sizeof(double) * b * (size_t)h->n_vox);
     L.ydiag = off;  // up to 8 sinograms in the diagonal ring-pair layout
@@ -247,6 +265,45 @@ Scratch3D make_scratch(void* ws, const Ws3& L) {
     S.bandc = at3<int2>(ws, L.bandc);
     S.band_rows = L.band_rows;
     return S;
+}
+
+// the scratch of odd batches of a staged build: the second set of slots,
+// bands and counters, everything else shared
+Scratch3D make_scratch_odd(void* ws, const Ws3& L) {
+    Scratch3D S = make_scratch(ws, L);
+    if (!L.set2) return S;
+    int* c = at3<int>(ws, L.counts2);
+    S.n_samples = c;
+    S.n_pairs = c + L.bmax;
+    S.n_slots = c + 2 * L.bmax;
+    S.slot_tbin = at3<int>(ws, L.slot_tbin2);
+    S.slot_order = at3<int>(ws, L.slot_order2);
+    S.band = at3<int2>(ws, L.band2);
+    S.bandc = at3<int2>(ws, L.bandc2);
+    return S;
+}
+
+// The staged build's second stream (the compaction's) and the events that order
+// it against the caller's stream: created on first use on the handle's device,
+// at the default priority.  False when it cannot be had (another device is
+// current, or creation failed): the build then runs on the caller's stream.
+bool aux_stream(psf_handle* h) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device) return false;
+    if (h->aux) return true;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+    hipEvent_t ev[kAuxEvents] = {};
+    for (int i = 0; i < kAuxEvents; ++i) {
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+            (void)hipStreamDestroy(st);
+            return false;
+        }
+    }
+    h->aux = st;
+    for (int i = 0; i < kAuxEvents; ++i) h->aux_ev[i] = ev[i];
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -723,18 +780,48 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         const int n_rows = staged < (int)pl.batches.size() ? pl.batches[staged].mem0 : (int)pl.mem.size();
         HIP_TRY(launch_stage_copy(a, n_rows, L.max_chunks, s));
     }
+    // A staged count phase compacts batch b on a second stream while the caller's
+    // stream runs the geometry of batch b + 1: odd batches take the second set of
+    // slots and bands, and a batch's contraction waits for the compaction before
+    // it (the accumulators are shared).  The geometry of batch b + 2 reuses the
+    // set of batch b after the contraction of b + 1, which waited for it.
+    const bool two = L.set2 && stage && !phase_fill && aux_stream(h);
+    const Scratch3D S_odd = two ? make_scratch_odd(ws, L) : S;
+    hipStream_t sc = two ? h->aux : s;  // the compaction's stream
+    // the caller's stream waits for the compaction stream when the loop ends,
+    // also on an early return
+    struct Join {
+        bool on;
+        hipStream_t s, sc;
+        hipEvent_t ev;
+        hipError_t now() {
+            if (!on) return hipSuccess;
+            on = false;
+            hipError_t e = hipEventRecord(ev, sc);
+            return e == hipSuccess ? hipStreamWaitEvent(s, ev, 0) : e;
+        }
+        ~Join() { (void)now(); }
+    } join{two, s, sc, two ? h->aux_ev[3] : nullptr};
     for (int bi = staged; bi < (int)pl.batches.size(); ++bi) {
         const Batch3& bt = pl.batches[bi];
         Args3D a = a0;
         set_batch(a, bt, pd);
         a.stage = stage && !phase_fill;
-        if ((st = batch_geometry(h, G, S, a, bt, 1, s))) return st;
+        const Scratch3D& Sb = (bi & 1) ? S_odd : S;
+        if ((st = batch_geometry(h, G, Sb, a, bt, 1, s))) return st;
+        if (two && bi > staged) HIP_TRY(hipStreamWaitEvent(s, h->aux_ev[1 + ((bi - 1) & 1)], 0));
         {
             ProfScope pm_(h, s, 0);
-            HIP_TRY(launch_cyl3d_mma(kModeCount, G, S, a, s));
+            HIP_TRY(launch_cyl3d_mma(kModeCount, G, Sb, a, s));
         }
-        HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, S, a, s));
+        if (two) {
+            HIP_TRY(hipEventRecord(h->aux_ev[0], s));
+            HIP_TRY(hipStreamWaitEvent(sc, h->aux_ev[0], 0));
+        }
+        HIP_TRY(launch_cyl3d_compact(phase_fill ? kModeFill : kModeCount, G, Sb, a, sc));
+        if (two) HIP_TRY(hipEventRecord(h->aux_ev[1 + (bi & 1)], sc));
     }
+    HIP_TRY(join.now());
     if (use_dense) HIP_TRY(launch_dense_mark(dstate, dsig, 1, s));  // every batch compacted: clear again
     if (!phase_fill) {
         HIP_TRY(launch_scan_rowptr(csr->row_ptr, ve - vb, s));

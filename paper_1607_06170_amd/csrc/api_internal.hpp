@@ -20,6 +20,8 @@ struct ClassOrderCache {
     std::vector<int2> mem;          // by position: voxel, ring shift
 };
 
+constexpr int kAuxEvents = 4;  // after a contraction; after an even / odd batch's compaction; the join
+
 struct psf_handle {
     ClassOrderCache order;
     psf_geometry g;
@@ -33,6 +35,9 @@ struct psf_handle {
     bool prof_on;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     std::vector<int> prof_kind;
+    // the 3D build's second stream and its events (created on first use)
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_ev[kAuxEvents] = {};
 };
 
 // bracket one launch of the contraction kernel with events when profiling
