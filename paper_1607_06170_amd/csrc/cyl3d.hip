@@ -992,7 +992,7 @@ constexpr int kWavesT = 4;
 constexpr int kGeomWG = 1024;
 constexpr unsigned int kSlotChunk = 16;
 constexpr int kR2Chunk = 8;  // rings r2 handled together
-constexpr int kR1Run = 8;    // consecutive rings r1 of one crystal pair per work unit
+constexpr int kR1Run = 16;   // consecutive rings r1 of one crystal pair per work unit
 constexpr int kQueue = 128;  // candidate queue (a power of two >= 127)
 
 // Most candidates (r2, sample, pz1, pz2) fail the quick test; the survivors
