@@ -237,7 +237,12 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
  *   row would exceed what phase 1 allotted.
  * 3D: PSF_EUNSUPPORTED when a class's accumulator cells (4096 transaxial
  * slots x (NR + 15)^2 ring pairs x 16 voxels) would not index in 32 bits, that
- * is for more than about 165 crystal rings. */
+ * is for more than about 165 crystal rings.  A 3D phase 1 with
+ * PSF_OPT_STAGE_CSR also runs work on a second stream of the handle's own
+ * (created on the first such call, on the device current at psf_create),
+ * ordered against `stream` by events both ways: `stream` waits for it before
+ * the call returns, on error returns too.  Calls on one handle are not
+ * thread-safe. */
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
                      size_t workspace_bytes, psf_csr* csr, void* stream);
 
