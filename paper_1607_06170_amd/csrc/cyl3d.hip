@@ -1301,7 +1301,7 @@ k_cyl3d_geom(Cyl3D G, Scratch3D S, Args3D A) {
 // which are spent by then); the emission then walks the members, each with its
 // rings shifted, the lanes spread over the list.
 
-constexpr int kGE = 4;  // adjoint list entries whose sinogram loads are in flight together
+constexpr int kGE = 8;  // adjoint list entries whose sinogram loads are in flight together
 
 struct MmaOps {
     float W[16][17];
