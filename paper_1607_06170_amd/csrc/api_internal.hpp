@@ -20,7 +20,10 @@ struct ClassOrderCache {
     std::vector<int2> mem;          // by position: voxel, ring shift
 };
 
-constexpr int kAuxEvents = 4;  // after a contraction; after an even / odd batch's compaction; the join
+// the second stream's events: after a contraction (build); after an even / odd
+// batch (build: its compaction; projections: its last kernel); the join; a
+// batch's geometry (projections); the start (projections)
+constexpr int kAuxEvents = 6;
 
 struct psf_handle {
     ClassOrderCache order;
