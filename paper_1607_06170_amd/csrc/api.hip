@@ -118,8 +118,10 @@ void psf_destroy(psf_handle* h) {
     if (h->frames_dev) (void)hipFree(h->frames_dev);
     if (h->aux) {
         (void)hipStreamSynchronize(h->aux);
+        (void)hipStreamSynchronize(h->aux2);
         for (int i = 0; i < kAuxEvents; ++i) (void)hipEventDestroy(h->aux_ev[i]);
         (void)hipStreamDestroy(h->aux);
+        (void)hipStreamDestroy(h->aux2);
     }
     delete h;
 }

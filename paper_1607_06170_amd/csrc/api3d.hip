@@ -100,7 +100,7 @@ struct Ws3 {
     int64_t cap_uv_rings, cap_uv;  // response-row table: (relative ring) slots per crystal, and in all
     // staged builds: a second set of the per-batch slot and band arrays (and the
     // counters), so that one batch's compaction overlaps the next batch's geometry
-    size_t counts2, slot_tbin2, slot_order2, band2, bandc2;
+    size_t counts2, slotmap2, slot_tbin2, slot_order2, band2, bandc2;
     int set2;
     // the projections (no staging): a second set of the geometry's outputs, so
     // that one batch's geometry overlaps the previous batch's contraction
@@ -198,8 +198,8 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
         off += align256(sizeof(float) * (size_t)L.cap_stage);
     }
     L.set2 = L.cap_stage > 0;
-    L.geo2 = !L.set2;
-    L.counts2 = L.slot_tbin2 = L.slot_order2 = L.band2 = L.bandc2 = 0;
+    L.geo2 = 1;
+    L.counts2 = L.slotmap2 = L.slot_tbin2 = L.slot_order2 = L.band2 = L.bandc2 = 0;
     L.sidx2 = L.sth2 = L.pairs2 = L.recs2 = L.reccount2 = L.uvtab2 = L.uvmask2 = 0;
     L.counts2 = off;
     off += align256(sizeof(int) * 3 * (size_t)L.bmax);
@@ -220,6 +220,8 @@ Ws3 ws3_layout(const psf_handle* h, const psf_table* t, int batch, int64_t n_eve
         off += align256(sizeof(int) * (size_t)L.cap_uv);
     }
     if (L.set2) {
+        L.slotmap2 = off;
+        off += align256(sizeof(int) * (size_t)L.bcsr * ntbins);
         L.slot_tbin2 = off;
         off += align256(sizeof(int) * (size_t)L.bcsr * L.cap_slots);
         L.slot_order2 = off;
@@ -309,15 +311,16 @@ Scratch3D make_scratch_geo_odd(void* ws, const Ws3& L) {
     return S;
 }
 
-// the scratch of odd batches of a staged build: the second set of slots,
-// bands and counters, everything else shared
+// the scratch of odd batches of a staged build: the second sets of the
+// geometry's outputs and of the slots and bands, everything else shared
 Scratch3D make_scratch_odd(void* ws, const Ws3& L) {
-    Scratch3D S = make_scratch(ws, L);
+    Scratch3D S = make_scratch_geo_odd(ws, L);
     if (!L.set2) return S;
     int* c = at3<int>(ws, L.counts2);
     S.n_samples = c;
     S.n_pairs = c + L.bmax;
     S.n_slots = c + 2 * L.bmax;
+    S.slotmap = at3<int>(ws, L.slotmap2);
     S.slot_tbin = at3<int>(ws, L.slot_tbin2);
     S.slot_order = at3<int>(ws, L.slot_order2);
     S.band = at3<int2>(ws, L.band2);
@@ -325,25 +328,32 @@ Scratch3D make_scratch_odd(void* ws, const Ws3& L) {
     return S;
 }
 
-// The staged build's second stream (the compaction's) and the events that order
-// it against the caller's stream: created on first use on the handle's device,
-// at the default priority.  False when it cannot be had (another device is
-// current, or creation failed): the build then runs on the caller's stream.
+// The handle's second and third streams (the build's compaction and geometry;
+// the forward's geometry) and the events that order them against the caller's
+// stream: created on first use on the handle's device, at the default
+// priority.  False when they cannot be had (another device is current, or
+// creation failed): the work then runs on the caller's stream.
 bool aux_stream(psf_handle* h) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != h->device) return false;
     if (h->aux) return true;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr, st2 = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return false;
+    }
     hipEvent_t ev[kAuxEvents] = {};
     for (int i = 0; i < kAuxEvents; ++i) {
         if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
             for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
             (void)hipStreamDestroy(st);
+            (void)hipStreamDestroy(st2);
             return false;
         }
     }
     h->aux = st;
+    h->aux2 = st2;
     for (int i = 0; i < kAuxEvents; ++i) h->aux_ev[i] = ev[i];
     return true;
 }
@@ -900,36 +910,51 @@ int build_sysmat_3d(psf_handle* h, const psf_table* t, const psf_opts* o, void* 
         const int n_rows = staged < (int)pl.batches.size() ? pl.batches[staged].mem0 : (int)pl.mem.size();
         HIP_TRY(launch_stage_copy(a, n_rows, L.max_chunks, s));
     }
-    // A staged count phase compacts batch b on a second stream while the caller's
-    // stream runs the geometry of batch b + 1: odd batches take the second set of
-    // slots and bands, and a batch's contraction waits for the compaction before
-    // it (the accumulators are shared).  The geometry of batch b + 2 reuses the
-    // set of batch b after the contraction of b + 1, which waited for it.
-    const bool two = L.set2 && stage && !phase_fill && aux_stream(h);
+    // A staged count phase runs three streams: the geometry of a batch on the
+    // third one, during the previous batch's contraction; the contraction on
+    // the caller's stream; the compaction on the second one.  Odd batches take
+    // the second sets of the geometry's outputs and of the slots and bands.
+    // Batch b's geometry waits for batch b - 2's compaction (the last user of
+    // its sets); its contraction waits for its geometry and for batch b - 1's
+    // compaction (the accumulators are shared); its compaction for its
+    // contraction.
+    const bool two = L.set2 && L.geo2 && stage && !phase_fill && aux_stream(h);
     const Scratch3D S_odd = two ? make_scratch_odd(ws, L) : S;
-    hipStream_t sc = two ? h->aux : s;  // the compaction's stream
-    // the caller's stream waits for the compaction stream when the loop ends,
-    // also on an early return
+    hipStream_t sc = two ? h->aux : s;   // the compaction's stream
+    hipStream_t sg = two ? h->aux2 : s;  // the geometry's stream
+    // the caller's stream waits for the other two when the loop ends, also on
+    // an early return
     struct Join {
         bool on;
-        hipStream_t s, sc;
+        hipStream_t s, sc, sg;
         hipEvent_t ev;
         hipError_t now() {
             if (!on) return hipSuccess;
             on = false;
             hipError_t e = hipEventRecord(ev, sc);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+            if (e == hipSuccess) e = hipEventRecord(ev, sg);
             return e == hipSuccess ? hipStreamWaitEvent(s, ev, 0) : e;
         }
         ~Join() { (void)now(); }
-    } join{two, s, sc, two ? h->aux_ev[3] : nullptr};
+    } join{two, s, sc, sg, two ? h->aux_ev[3] : nullptr};
+    if (two) {  // the geometry stream after everything queued on s so far
+        HIP_TRY(hipEventRecord(h->aux_ev[5], s));
+        HIP_TRY(hipStreamWaitEvent(sg, h->aux_ev[5], 0));
+    }
     for (int bi = staged; bi < (int)pl.batches.size(); ++bi) {
         const Batch3& bt = pl.batches[bi];
         Args3D a = a0;
         set_batch(a, bt, pd);
         a.stage = stage && !phase_fill;
         const Scratch3D& Sb = (bi & 1) ? S_odd : S;
-        if ((st = batch_geometry(h, G, Sb, a, bt, 1, s))) return st;
-        if (two && bi > staged) HIP_TRY(hipStreamWaitEvent(s, h->aux_ev[1 + ((bi - 1) & 1)], 0));
+        if (two && bi >= staged + 2) HIP_TRY(hipStreamWaitEvent(sg, h->aux_ev[1 + (bi & 1)], 0));
+        if ((st = batch_geometry(h, G, Sb, a, bt, 1, sg))) return st;
+        if (two) {
+            HIP_TRY(hipEventRecord(h->aux_ev[4], sg));
+            HIP_TRY(hipStreamWaitEvent(s, h->aux_ev[4], 0));
+            if (bi > staged) HIP_TRY(hipStreamWaitEvent(s, h->aux_ev[1 + ((bi - 1) & 1)], 0));
+        }
         {
             ProfScope pm_(h, s, 0);
             HIP_TRY(launch_cyl3d_mma(kModeCount, G, Sb, a, s));

@@ -20,9 +20,9 @@ struct ClassOrderCache {
     std::vector<int2> mem;          // by position: voxel, ring shift
 };
 
-// the second stream's events: after a contraction (build); after an even / odd
+// the extra streams' events: after a contraction (build); after an even / odd
 // batch (build: its compaction; projections: its last kernel); the join; a
-// batch's geometry (projections); the start (projections)
+// batch's geometry; the start
 constexpr int kAuxEvents = 6;
 
 struct psf_handle {
@@ -38,8 +38,8 @@ struct psf_handle {
     bool prof_on;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     std::vector<int> prof_kind;
-    // the 3D build's second stream and its events (created on first use)
-    hipStream_t aux = nullptr;
+    // the 3D calls' second and third streams and their events (created on first use)
+    hipStream_t aux = nullptr, aux2 = nullptr;
     hipEvent_t aux_ev[kAuxEvents] = {};
 };
 
