@@ -12,10 +12,11 @@
  *   - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream)
  *     and runs asynchronously unless the description says the call blocks.
  *     Some 3D calls (the count phase of a staged build, the forward
- *     projection and what runs it) also use a second stream of the handle's
- *     own, created on first use on the device current at psf_create, at the
- *     default priority, and ordered against `stream` by events both ways:
- *     `stream` waits for it before the call returns, on error returns too.
+ *     projection and what runs it) also use a second and a third stream of
+ *     the handle's own, created on first use on the device current at
+ *     psf_create, at the default priority, and ordered against `stream` by
+ *     events both ways: `stream` waits for them before the call returns, on
+ *     error returns too.
  *     Calls on one handle are not thread-safe.
  *   - The caller owns every buffer passed in.  The library never frees caller
  *     memory; its own device state lives in the handle (geometry constants)
@@ -244,7 +245,7 @@ int psf_workspace_size(const psf_handle* h, const psf_table* table, const psf_op
  * 3D: PSF_EUNSUPPORTED when a class's accumulator cells (4096 transaxial
  * slots x (NR + 15)^2 ring pairs x 16 voxels) would not index in 32 bits, that
  * is for more than about 165 crystal rings.  A 3D phase 1 with
- * PSF_OPT_STAGE_CSR also uses the handle's second stream (see the conventions
+ * PSF_OPT_STAGE_CSR also uses the handle's extra streams (see the conventions
  * above). */
 int build_psf_sysmat(psf_handle* h, const psf_table* table, const psf_opts* opts, void* workspace_dev,
                      size_t workspace_bytes, psf_csr* csr, void* stream);
