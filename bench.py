@@ -462,8 +462,8 @@ def top_n_rows(skipped):
 def forms_rows(sc, skipped):
     """The three precision forms of the tile contraction on the central
     16 x 16 x 16 voxels: one step each (matrix build, forward of the phantom,
-    adjoint of the sinogram), timed after a warm-up step; their errors against
-    the FP64 oracle are in rel_err_vs_fp64."""
+    adjoint of the sinogram), timed after a warm-up step of every form; their
+    errors against the FP64 oracle are in rel_err_vs_fp64."""
     import torch
     if _left() < 30.0:
         skipped.append("forms (wall-clock budget)")
@@ -473,8 +473,13 @@ def forms_rows(sc, skipped):
     x = torch.tensor(phantom(c16, m16), dtype=torch.float32, device="cuda")
     ev = lambda: torch.cuda.Event(enable_timing=True)
     res = {"workload": "the central 16x16x16 voxels of the 128x128x96 image, one call each"}
+    for p in range(len(PREC_NAMES)):  # a warm-up step of every form first
+        rp, col, val = sc.build_psf_sysmat(tab, threshold=0.0, precision=p)
+        sc.project_adj(tab, sc.project_fwd(tab, x, precision=p), precision=p)
+        del rp, col, val
+    torch.cuda.synchronize()
     for p, name in enumerate(PREC_NAMES):
-        for _ in range(2):
+        for _ in range(1):
             e = [ev() for _ in range(4)]
             e[0].record()
             rp, col, val = sc.build_psf_sysmat(tab, threshold=0.0, precision=p)

@@ -116,12 +116,11 @@ void psf_destroy(psf_handle* h) {
         (void)hipEventDestroy(e.second);
     }
     if (h->frames_dev) (void)hipFree(h->frames_dev);
-    if (h->aux) {
-        (void)hipStreamSynchronize(h->aux);
-        (void)hipStreamSynchronize(h->aux2);
-        for (int i = 0; i < kAuxEvents; ++i) (void)hipEventDestroy(h->aux_ev[i]);
-        (void)hipStreamDestroy(h->aux);
-        (void)hipStreamDestroy(h->aux2);
+    if (h->aux) {  // the streams are the device's and stay; this handle's events go
+        for (int i = 0; i < kAuxEvents; ++i) {
+            (void)hipEventSynchronize(h->aux_ev[i]);
+            (void)hipEventDestroy(h->aux_ev[i]);
+        }
     }
     delete h;
 }

@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -328,32 +329,41 @@ Scratch3D make_scratch_odd(void* ws, const Ws3& L) {
     return S;
 }
 
-// The handle's second and third streams (the build's compaction and geometry;
-// the forward's geometry) and the events that order them against the caller's
-// stream: created on first use on the handle's device, at the default
-// priority.  False when they cannot be had (another device is current, or
-// creation failed): the work then runs on the caller's stream.
+// The second and third streams (the build's compaction and geometry; the
+// forward's geometry), one pair per device for the process, and the handle's
+// events that order them against the caller's stream: created on first use,
+// at the default priority.  False when they cannot be had (another device is
+// current, or creation failed): the work then runs on the caller's stream.
 bool aux_stream(psf_handle* h) {
     int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != h->device) return false;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device || dev < 0 || dev >= kAuxDevices) return false;
     if (h->aux) return true;
-    hipStream_t st = nullptr, st2 = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
-    if (hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipStreamDestroy(st);
-        return false;
+    // the streams: two per device for the process, shared by every handle, so
+    // that handles do not multiply the streams the hardware queues serve
+    static std::mutex mu;
+    static hipStream_t dev_streams[kAuxDevices][2];
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!dev_streams[dev][0]) {
+            hipStream_t st = nullptr, st2 = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+            if (hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipStreamDestroy(st);
+                return false;
+            }
+            dev_streams[dev][0] = st;
+            dev_streams[dev][1] = st2;
+        }
     }
     hipEvent_t ev[kAuxEvents] = {};
     for (int i = 0; i < kAuxEvents; ++i) {
         if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
             for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
-            (void)hipStreamDestroy(st);
-            (void)hipStreamDestroy(st2);
             return false;
         }
     }
-    h->aux = st;
-    h->aux2 = st2;
+    h->aux = dev_streams[dev][0];
+    h->aux2 = dev_streams[dev][1];
     for (int i = 0; i < kAuxEvents; ++i) h->aux_ev[i] = ev[i];
     return true;
 }

@@ -24,6 +24,7 @@ struct ClassOrderCache {
 // batch (build: its compaction; projections: its last kernel); the join; a
 // batch's geometry; the start
 constexpr int kAuxEvents = 6;
+constexpr int kAuxDevices = 64;  // devices with the extra streams
 
 struct psf_handle {
     ClassOrderCache order;
@@ -38,7 +39,8 @@ struct psf_handle {
     bool prof_on;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     std::vector<int> prof_kind;
-    // the 3D calls' second and third streams and their events (created on first use)
+    // the 3D calls' second and third streams (the device's, shared by the
+    // process's handles) and this handle's events (created on first use)
     hipStream_t aux = nullptr, aux2 = nullptr;
     hipEvent_t aux_ev[kAuxEvents] = {};
 };
