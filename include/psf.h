@@ -187,6 +187,9 @@ typedef struct psf_handle psf_handle;
  * nz = 1, lines in the transaxial plane); mode3d = 1: the 3D scanner.
  * PSF_EGEOM if any voxel centre lies outside the ring of face lines. */
 int psf_create(const psf_geometry* geom, const psf_image* img, int32_t mode3d, psf_handle** out);
+/* Release the handle: waits for the work it ordered on its extra streams,
+ * then frees its events and device constants.  The extra streams themselves
+ * belong to the device and serve every handle until the process ends. */
 void psf_destroy(psf_handle* h);
 
 /* Number of crystals N and of bins N (N - 1) / 2; number of voxels. */
