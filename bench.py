@@ -128,8 +128,8 @@ def phantom(cfg, meta):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU layout (voxel sharding plus "
-                                   "one all-reduce of the sinogram) is described in the design notes, not built"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only (--gpus 1): sharding voxels across GPUs, "
+                                   "with one all-reduce of the sinogram, is not implemented"}))
         sys.exit(2)
     import torch
     from paper_1607_06170_amd import Scanner
