@@ -12,11 +12,11 @@
  *   - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream)
  *     and runs asynchronously unless the description says the call blocks.
  *     Some 3D calls (the count phase of a staged build, the forward
- *     projection and what runs it) also use a second and a third stream of
- *     the handle's own, created on first use on the device current at
- *     psf_create, at the default priority, and ordered against `stream` by
- *     events both ways: `stream` waits for them before the call returns, on
- *     error returns too.
+ *     projection and what runs it) also use a second and a third stream that
+ *     the library keeps for each device (shared by the process's handles,
+ *     created on first use, at the default priority), ordered against
+ *     `stream` by the handle's events both ways: `stream` waits for them
+ *     before the call returns, on error returns too.
  *     Calls on one handle are not thread-safe.
  *   - The caller owns every buffer passed in.  The library never frees caller
  *     memory; its own device state lives in the handle (geometry constants)
@@ -56,7 +56,7 @@ enum {
     PSF_ESIZE = -4,        /* a buffer is too small; the required size is written back */
     PSF_EHIP = -5,         /* a HIP runtime error (see psf_last_hip_error) */
     PSF_EOVERFLOW = -6,    /* fill phase produced more entries than the count phase allotted */
-    PSF_EUNSUPPORTED = -7, /* geometry or option combination this build does not handle */
+    PSF_EUNSUPPORTED = -7, /* geometry or option combination this library does not handle */
     PSF_ECAPACITY = -8     /* 3D: a voxel's lines exceeded a fixed scratch capacity (more than 4096
                             * sub-segment pairs or 1024 crystal pairs seen from one voxel, more than
                             * 16 sub-segment pairs per crystal pair, more than 4096 transaxial bins

@@ -5,7 +5,7 @@
  *
  * The paper builds the matrix for a 2D ring and names the 3D matrix as future
  * work (Sec 4).  This file extends each step of Sec 2 to a cylinder of block
- * rings, with these readings (also listed in the repository's design notes):
+ * rings, with these readings:
  *   - Response table indexed by the two projected incidence angles: alpha_t in
  *     the transaxial plane and alpha_z, whose tangents are the lateral slopes
  *     of the ray per unit depth along the face normal.  Entry (a_t, a_z) is
